@@ -1,0 +1,151 @@
+// internal.h -- declarations shared by the kernels and the host runtime of
+// libmlsgd (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace mlsgd {
+
+constexpr int KMAX = 5;
+constexpr int RED_BLOCKS = 256;   // fixed block count of the deterministic dot kernels
+
+// Tiling of one grid size for the marching stencil kernels: a workgroup owns
+// a TY x TZ patch of the (y, z) plane and marches along x over xchunk planes.
+struct Tiling {
+  int TY, TZ;
+  int nty, ntz, nxc, xchunk;
+  int tiles_per_row;
+};
+
+Tiling make_tiling(int n);
+
+// Per-problem state of the batched Krylov solves (all FP64).
+struct CgScal {
+  double rz;      // <r, z> of the current iterate
+  double pq;      // <p, A p>
+  double rr;      // <r, r>
+  double bb;      // <b, b>
+  double alpha, beta;
+  int active;     // 1 while the problem iterates
+  int iters;
+};
+
+// Arguments common to every launch over one grid size.
+struct GridArgs {
+  int n;                // vertices per axis
+  int rows;             // rows (problems) in the launch, rows [0, rows)
+  int row0;             // problem index of row 0
+  long long stride;     // elements per row (n^3)
+  Tiling t;
+  const double* coef;   // [problem][K^3] KL coefficients sqrt(sigma2 lam) xi
+  int K;
+  const double* cosT;   // [K][n] cos(pi k x_i)
+  const CgScal* scal;   // per problem; inactive problems are skipped (nullable)
+  double ih2;           // 1/h^2
+};
+
+// ---- stencil kernels (marching LDS tiles, coefficient regenerated) ----
+template <typename T>
+void march_resid(const GridArgs& g, const T* x, const T* b, T* r, hipStream_t s);
+template <typename T>
+void march_matvec(const GridArgs& g, const T* z, const T* p_old, T* p_new, T* q,
+                  const int* poff, double* partial, hipStream_t s);
+template <typename T>
+void march_gs(const GridArgs& g, T* x, const T* b, int color, int x_zero,
+              const int* poff, double* partial, int top_begin, hipStream_t s);
+
+// ---- batched grid transfers (rows of one grid size) ----
+template <typename T>
+void restrict_rows(int nf, int rows, int row0, const CgScal* scal, const T* fine,
+                   T* coarse, hipStream_t s);
+template <typename T>
+void prolong_add_rows(int nc, int rows, int row0, const CgScal* scal, const T* coarse,
+                      T* fine, hipStream_t s);
+
+// ---- random field ----
+void kl_coeffs(const int* prob_level, const int64_t* prob_sample, int nprob,
+               uint64_t seed, int K, double sigma2, double* coef, hipStream_t s);
+void kl_normals(uint64_t seed, int level, int64_t first, int64_t count, int K3,
+                double* xi, hipStream_t s);
+void philox_words(uint64_t seed, int level, int64_t sample, int tag, int nblocks,
+                  uint64_t* out, hipStream_t s);
+void cos_table(int n, int K, double* out, hipStream_t s);
+
+// ---- elementwise over the rows of one group (full n^3 per row) ----
+void rows_broadcast(int n, int rows, const double* src, double* dst, hipStream_t s);
+void rows_zero(long long count, double* x, hipStream_t s);
+void group_dot(const GridArgs& g, const double* a, const double* b, const int* poff,
+               double* partial, hipStream_t s);
+void group_update(const GridArgs& g, double* x, const double* p, double* r,
+                  const double* q, const int* poff, double* partial, hipStream_t s);
+void group_misfit(const GridArgs& g, double* y, const double* yd, double* b_rows,
+                  const int* poff, double* partial, hipStream_t s);
+
+// ---- per-problem scalar steps of the batched Krylov method ----
+enum ScalPhase {
+  PH_INIT_BB = 0,    // bb = rr = sum; active = bb > 0; iters = 0
+  PH_RZ0 = 1,        // rz = sum; beta = 0
+  PH_RZ0_RR = 2,     // unpreconditioned start: rz = rr; beta = 0
+  PH_ALPHA = 3,      // pq = sum; alpha = rz / pq
+  PH_RR = 4,         // rr = sum; ++iters; converged or out of iterations -> inactive
+  PH_RZ = 5,         // rz_new = sum; beta = rz_new / rz; rz = rz_new
+  PH_RZ_RR = 6,      // unpreconditioned: rz_new = rr
+  PH_TRUE = 7,       // rr = sum (true residual); active = rr > rtol^2 bb
+};
+void cg_scalar(int phase, CgScal* scal, int nprob, const int* poff, const int* pcnt,
+               const double* partial, double rtol, int max_iters, int* active_count,
+               hipStream_t s);
+void scal_to_stats(const CgScal* scal, int nprob, double rtol, int* iters_max,
+                   int* nonconv, double* relres_max, hipStream_t s);
+void sum_partials(int nprob, const int* poff, const int* pcnt, const double* partial,
+                  double scale, double* dst, hipStream_t s);
+
+// ---- whole-field kernels on one grid (epilogue, control transfer) ----
+void restrict_full(int nf, const double* fine, double* coarse, hipStream_t s);
+void prolong_full(int nc, const double* coarse, double* fine, hipStream_t s);
+void inject_full(int nf, const double* fine, int nc, double* coarse, hipStream_t s);
+void add_mask(int n, const double* f, const double* u, double* out, hipStream_t s);
+void axpy_full(int n, double a, const double* x, double* y, hipStream_t s);
+void dot_blocks(long long N, const double* a, const double* b, double* part,
+                hipStream_t s);   // RED_BLOCKS partials of sum a*b
+void box_step(int n, double* u, const double* g, double tau, double lo, double hi,
+              int use_box, hipStream_t s);
+void nonfinite_flag(long long count, const double* x, int* flag, hipStream_t s);
+void copy_rows_strided(int n, int rows, const double* src, double* dst, hipStream_t s);
+
+// ---- entropic epilogue ----
+void shift_weights(int nprob, const double* phi, double theta, double* w, double* s_out,
+                   hipStream_t s);
+int level_sample_blocks(int M);
+void level_dx_partial(int nf, int M, const double* pf, const double* wf, const double* pc,
+                      const double* wc, double* part, hipStream_t s);
+void level_dx_mean(int nf, int M, const double* part, double* mean, hipStream_t s);
+int level_m2_chunks(int nf);
+void level_dx_m2(int nf, int M, const double* pf, const double* wf, const double* pc,
+                 const double* wc, const double* mean, double* part2, hipStream_t s);
+
+struct EpiLevel {   // one level of the estimate, for the scalar epilogue
+  int M;
+  int fine_off;     // problem index of the first fine problem
+  int coarse_off;   // problem index of the first coarse problem (-1 on level 0)
+  int nf;
+  long long m2_off; // offset of this level's M2 partials in the partial buffer
+  int m2_cnt;
+  long long nm_off; // offset of the RED_BLOCKS partials of |mean|^2
+};
+struct EpiOut {     // device-side scalar results, copied to the host once
+  double s, EY, denom, J, gnorm2, unorm2, exnorm2;
+  double mean_dY[8], norm2_mean_dX[8], m2_dX[8], m2_dY[8], mean_phi_f[8];
+  int truncated, pad;
+};
+void epilogue_scalars(int L, const EpiLevel* lev, const double* phi, const double* w,
+                      const double* part, long long u_off, int nL, double theta,
+                      double alpha, int with_dx, EpiOut* out, hipStream_t s);
+void final_grad(int n, const double* acc, const double* u, const EpiOut* eo, double alpha,
+                double* grad, hipStream_t s);
+void finish_norm(int n, const double* part, double* dst, hipStream_t s);  // h^3 sum
+
+}  // namespace mlsgd

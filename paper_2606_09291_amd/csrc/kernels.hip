@@ -1,0 +1,1220 @@
+// kernels.hip -- gfx950 kernels of libmlsgd.
+//
+// Stencil work is HBM-bound (a few flop per byte), so the kernels are built
+// for coalesced z-fastest access, LDS reuse of the (y, z) neighbours, and no
+// stored coefficient: the diffusion coefficient a = exp(log a) of every
+// sample is regenerated from its KL coefficients inside each sweep (Sec. 5
+// model problem).  MFMA does not apply to this work.
+//
+// Layout: a "row" is one problem (one sample on one grid); a batch of rows of
+// one grid size is [rows][n^3], z fastest, boundary entries held at zero.
+#include "internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+
+namespace mlsgd {
+
+// ---------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double dexp(double x) { return exp(x); }
+__device__ __forceinline__ float dexp(float x) { return __expf(x); }
+
+// Reciprocal: hardware estimate refined by two Newton steps (FP64) -- within
+// one ulp for the positive, O(1) arguments it sees here.
+__device__ __forceinline__ double drcp(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  double e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  e = __builtin_fma(-d, r, 1.0);
+  r = __builtin_fma(r, e, r);
+  return r;
+}
+__device__ __forceinline__ float drcp(float d) { return __builtin_amdgcn_rcpf(d); }
+
+// Harmonic face coefficient from the reciprocal vertex coefficients
+// b = 1/a:  2 a_v a_w / (a_v + a_w) = 2 / (b_v + b_w).
+template <typename T>
+__device__ __forceinline__ T face(T bv, T bw) {
+  return T(2) * drcp(bv + bw);
+}
+
+// Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each
+// XCD (own L2) receives a contiguous range of logical tiles, which then share
+// halo rows in that L2.
+__device__ __forceinline__ int xcd_swizzle(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7;
+  const int xcd = b & 7, loc = b >> 3;
+  return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + loc;
+}
+
+template <int NT>
+__device__ __forceinline__ double block_sum(double v, double* sred) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) sred[w] = v;
+  __syncthreads();
+  double s = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i) s += sred[i];
+  }
+  __syncthreads();
+  return s;  // valid in thread 0
+}
+
+static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
+
+Tiling make_tiling(int n) {
+  const int m = n - 2;
+  Tiling t;
+  if (m <= 8) {
+    t.TY = 8; t.TZ = 8;
+  } else if (m <= 16) {
+    t.TY = 16; t.TZ = 16;
+  } else if (m <= 32) {
+    t.TY = 8; t.TZ = 32;
+  } else {
+    t.TY = 4; t.TZ = 64;
+  }
+  t.nty = cdiv(m, t.TY);
+  t.ntz = cdiv(m, t.TZ);
+  t.xchunk = m <= 32 ? m : 32;
+  t.nxc = cdiv(m, t.xchunk);
+  t.tiles_per_row = t.nty * t.ntz * t.nxc;
+  return t;
+}
+
+// ---------------------------------------------------------------------------
+// Marching stencil kernel.
+//
+// A workgroup owns the (y, z) patch [y0, y0+TY) x [z0, z0+TZ) of one row and
+// walks the x planes of its chunk.  Each thread keeps its own column's
+// values and reciprocal coefficients at x-1, x, x+1 in registers; the
+// current plane (patch plus a one-point halo in y and z) sits in LDS,
+// double-buffered so one barrier per plane suffices.  The coefficient of a
+// vertex is computed once per plane from the separable KL sum: per (y, z)
+// column S[k1] = sum_{k2,k3} c[k1,k2,k3] cos(pi k2 y) cos(pi k3 z) is formed
+// once, after which each plane costs K FMAs and one exp.
+//
+// OP_RESID : r = b - A x
+// OP_MATVEC: p = z + beta p (on the fly, halo included), q = A p, <p, q>
+// OP_GS    : one colour of a red-black Gauss-Seidel sweep in place
+//            (x_zero: start from x = 0; partial: <b, x> after the sweep)
+// ---------------------------------------------------------------------------
+enum MarchOp { OP_RESID = 0, OP_MATVEC = 1, OP_GS = 2 };
+
+template <typename T, int TY, int TZ, int OP>
+__global__ void __launch_bounds__(TY* TZ)
+    k_march(GridArgs g, const T* in, const T* in2, const T* rhs, T* out, T* out2,
+            const int* __restrict__ poff, double* __restrict__ partial, int color,
+            int x_zero, int top_begin) {
+  constexpr int NT = TY * TZ;
+  constexpr int PZ = TZ + 2;
+  constexpr int PLANE = (TY + 2) * PZ;
+  __shared__ T sx[2][PLANE];
+  __shared__ T sb[2][PLANE];
+  __shared__ double sc[KMAX * KMAX * KMAX];
+  __shared__ double sred[NT / 64];
+
+  const int n = g.n;
+  const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int tpr = g.t.tiles_per_row;
+  const int row = bid / tpr;
+  const int tile = bid - row * tpr;
+  int tt = tile;
+  const int ty = tt % g.t.nty;
+  tt /= g.t.nty;
+  const int tz = tt % g.t.ntz;
+  const int xc = tt / g.t.ntz;
+  const int prob = g.row0 + row;
+  if (g.scal && !g.scal[prob].active) return;  // uniform per workgroup
+
+  const int K = g.K;
+  const int K3 = K * K * K;
+  for (int j = threadIdx.x; j < K3; j += NT) sc[j] = g.coef[(size_t)prob * K3 + j];
+  __syncthreads();
+
+  const size_t base = (size_t)row * (size_t)g.stride;
+  const double* __restrict__ cosT = g.cosT;
+  const int tid = threadIdx.x;
+  const int ly = tid / TZ, lz = tid - (tid / TZ) * TZ;
+  const int y0 = 1 + ty * TY, z0 = 1 + tz * TZ;
+  const int iy = y0 + ly, iz = z0 + lz;
+  const bool inside = (iy <= n - 1) && (iz <= n - 1);
+  const bool own = (iy <= n - 2) && (iz <= n - 2);
+
+  // halo slot (no corners are needed by a 7-point stencil)
+  constexpr int NH = 2 * (TY + TZ);
+  int hly = 0, hlz = 0;
+  if (tid < NH) {
+    if (tid < TZ) {
+      hly = 0; hlz = tid + 1;
+    } else if (tid < 2 * TZ) {
+      hly = TY + 1; hlz = tid - TZ + 1;
+    } else if (tid < 2 * TZ + TY) {
+      hly = tid - 2 * TZ + 1; hlz = 0;
+    } else {
+      hly = tid - 2 * TZ - TY + 1; hlz = TZ + 1;
+    }
+  }
+  const int hy = y0 - 1 + hly, hz = z0 - 1 + hlz;
+  const bool has_halo = (tid < NH) && (hy <= n - 1) && (hz <= n - 1);
+
+  T beta = T(0);
+  if (OP == OP_MATVEC) beta = (T)g.scal[prob].beta;
+
+  auto ld = [&](int ix, int jy, int jz) -> T {
+    if (x_zero) return T(0);
+    if (ix <= 0 || ix >= n - 1 || jy <= 0 || jy >= n - 1 || jz <= 0 || jz >= n - 1) return T(0);
+    const size_t idx = base + ((size_t)ix * n + jy) * n + jz;
+    if (OP == OP_MATVEC) return in[idx] + beta * in2[idx];
+    return in[idx];
+  };
+
+  auto compS = [&](int jy, int jz, T* S) {
+    T cy[KMAX], cz[KMAX];
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      cy[k] = (k < K) ? (T)cosT[k * n + jy] : T(0);
+      cz[k] = (k < K) ? (T)cosT[k * n + jz] : T(0);
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < KMAX; ++k1) {
+      T acc = T(0);
+      if (k1 < K) {
+#pragma unroll
+        for (int k2 = 0; k2 < KMAX; ++k2) {
+          if (k2 < K) {
+            T t = T(0);
+#pragma unroll
+            for (int k3 = 0; k3 < KMAX; ++k3)
+              if (k3 < K) t += (T)sc[(k1 * K + k2) * K + k3] * cz[k3];
+            acc += t * cy[k2];
+          }
+        }
+      }
+      S[k1] = acc;
+    }
+  };
+  // reciprocal coefficient 1/a = exp(-log a) on plane ix of a column with sums S
+  auto coefb = [&](int ix, const T* S) -> T {
+    T l = T(0);
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (k < K) l += (T)cosT[k * n + ix] * S[k];
+    return dexp(-l);
+  };
+
+  T Sm[KMAX], Sh[KMAX];
+#pragma unroll
+  for (int k = 0; k < KMAX; ++k) {
+    Sm[k] = T(0);
+    Sh[k] = T(0);
+  }
+  if (inside) compS(iy, iz, Sm);
+  if (has_halo) compS(hy, hz, Sh);
+
+  const int x0 = 1 + xc * g.t.xchunk;
+  const int x1 = min(x0 + g.t.xchunk, n - 1);
+  const T ih2 = (T)g.ih2;
+
+  T xm = T(0), xcur = T(0), bm = T(1), bc = T(1);
+  if (inside) {
+    xm = ld(x0 - 1, iy, iz);
+    xcur = ld(x0, iy, iz);
+    bm = coefb(x0 - 1, Sm);
+    bc = coefb(x0, Sm);
+  }
+  T fxm = face(bm, bc);
+  T hcur = T(0), hbc = T(1);
+  if (has_halo) {
+    hcur = ld(x0, hy, hz);
+    hbc = coefb(x0, Sh);
+  }
+  double dot = 0.0;
+  const int cidx = (ly + 1) * PZ + (lz + 1);
+  const int hidx = hly * PZ + hlz;
+
+  for (int ix = x0; ix < x1; ++ix) {
+    const int buf = ix & 1;
+    // prefetch the next plane of the own column and of the halo slot
+    T xp = inside ? ld(ix + 1, iy, iz) : T(0);
+    T hnext = (has_halo && ix + 1 < x1) ? ld(ix + 1, hy, hz) : T(0);
+    T bv = T(0);
+    if (OP == OP_RESID || OP == OP_GS) {
+      if (own) bv = rhs[base + ((size_t)ix * n + iy) * n + iz];
+    }
+    sx[buf][cidx] = inside ? xcur : T(0);
+    sb[buf][cidx] = inside ? bc : T(1);
+    if (tid < NH) {
+      sx[buf][hidx] = has_halo ? hcur : T(0);
+      sb[buf][hidx] = has_halo ? hbc : T(1);
+    }
+    __syncthreads();
+    T bp = inside ? coefb(ix + 1, Sm) : T(1);
+    T fxp = face(bc, bp);
+    if (own) {
+      const T xym = sx[buf][cidx - PZ], xyp = sx[buf][cidx + PZ];
+      const T xzm = sx[buf][cidx - 1], xzp = sx[buf][cidx + 1];
+      const T fym = face(bc, sb[buf][cidx - PZ]), fyp = face(bc, sb[buf][cidx + PZ]);
+      const T fzm = face(bc, sb[buf][cidx - 1]), fzp = face(bc, sb[buf][cidx + 1]);
+      const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
+      const T off = ((fxm * xm + fxp * xp) + (fym * xym + fyp * xyp)) + (fzm * xzm + fzp * xzp);
+      const size_t idx = base + ((size_t)ix * n + iy) * n + iz;
+      if (OP == OP_RESID) {
+        out[idx] = bv - ih2 * (diag * xcur - off);
+      } else if (OP == OP_MATVEC) {
+        const T q = ih2 * (diag * xcur - off);
+        out[idx] = q;
+        out2[idx] = xcur;
+        dot += (double)xcur * (double)q;
+      } else {  // OP_GS
+        T val = xcur;
+        if (((ix + iy + iz) & 1) == color) {
+          val = (bv + ih2 * off) * drcp(ih2 * diag);
+          out[idx] = val;
+        } else if (x_zero) {
+          val = T(0);
+          out[idx] = val;
+        }
+        if (partial) {
+          const T bb = (((ix + iy + iz) & 1) == color) ? bv : rhs[idx];
+          dot += (double)bb * (double)val;
+        }
+      }
+    }
+    xm = xcur;
+    xcur = xp;
+    bm = bc;
+    bc = bp;
+    fxm = fxp;
+    if (has_halo && ix + 1 < x1) {
+      hcur = hnext;
+      hbc = coefb(ix + 1, Sh);
+    }
+  }
+  const bool want = (OP == OP_MATVEC) || (OP == OP_GS && partial != nullptr && prob >= top_begin);
+  if (want) {
+    const double s = block_sum<NT>(dot, sred);
+    if (threadIdx.x == 0) partial[poff[prob] + tile] = s;
+  }
+}
+
+template <typename T, int OP>
+static void launch_march(const GridArgs& g, const T* in, const T* in2, const T* rhs, T* out,
+                         T* out2, const int* poff, double* partial, int color, int x_zero,
+                         int top_begin, hipStream_t s) {
+  if (g.rows <= 0) return;
+  const int nblk = g.rows * g.t.tiles_per_row;
+  switch (g.t.TZ) {
+    case 8:
+      hipLaunchKernelGGL((k_march<T, 8, 8, OP>), dim3(nblk), dim3(64), 0, s, g, in, in2, rhs,
+                         out, out2, poff, partial, color, x_zero, top_begin);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_march<T, 16, 16, OP>), dim3(nblk), dim3(256), 0, s, g, in, in2,
+                         rhs, out, out2, poff, partial, color, x_zero, top_begin);
+      break;
+    case 32:
+      hipLaunchKernelGGL((k_march<T, 8, 32, OP>), dim3(nblk), dim3(256), 0, s, g, in, in2,
+                         rhs, out, out2, poff, partial, color, x_zero, top_begin);
+      break;
+    default:
+      hipLaunchKernelGGL((k_march<T, 4, 64, OP>), dim3(nblk), dim3(256), 0, s, g, in, in2,
+                         rhs, out, out2, poff, partial, color, x_zero, top_begin);
+      break;
+  }
+}
+
+template <typename T>
+void march_resid(const GridArgs& g, const T* x, const T* b, T* r, hipStream_t s) {
+  launch_march<T, OP_RESID>(g, x, nullptr, b, r, nullptr, nullptr, nullptr, 0, 0, 0, s);
+}
+template <typename T>
+void march_matvec(const GridArgs& g, const T* z, const T* p_old, T* p_new, T* q,
+                  const int* poff, double* partial, hipStream_t s) {
+  launch_march<T, OP_MATVEC>(g, z, p_old, nullptr, q, p_new, poff, partial, 0, 0, 0, s);
+}
+template <typename T>
+void march_gs(const GridArgs& g, T* x, const T* b, int color, int x_zero, const int* poff,
+              double* partial, int top_begin, hipStream_t s) {
+  launch_march<T, OP_GS>(g, x, nullptr, b, x, nullptr, poff, partial, color, x_zero, top_begin,
+                         s);
+}
+template void march_resid<double>(const GridArgs&, const double*, const double*, double*,
+                                  hipStream_t);
+template void march_resid<float>(const GridArgs&, const float*, const float*, float*,
+                                 hipStream_t);
+template void march_matvec<double>(const GridArgs&, const double*, const double*, double*,
+                                   double*, const int*, double*, hipStream_t);
+template void march_gs<double>(const GridArgs&, double*, const double*, int, int, const int*,
+                               double*, int, hipStream_t);
+template void march_gs<float>(const GridArgs&, float*, const float*, int, int, const int*,
+                              double*, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Batched grid transfers.  Full weighting R = P^T / 8 (weights 1/4, 1/2, 1/4
+// per axis) from fine interior to coarse interior, and trilinear
+// prolongation added onto the fine rows.  Coarse boundary entries are zero.
+// ---------------------------------------------------------------------------
+template <typename T>
+__global__ void k_restrict_rows(int nf, int rows, int row0, const CgScal* scal,
+                                const T* __restrict__ fine, T* __restrict__ coarse) {
+  const int nc = (nf - 1) / 2 + 1, mc = nc - 2;
+  const long long per = (long long)mc * mc * mc;
+  const long long total = per * rows;
+  const size_t sf = (size_t)nf * nf * nf, scs = (size_t)nc * nc * nc;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int row = (int)(i / per);
+    if (scal && !scal[row0 + row].active) continue;
+    const int r = (int)(i - (long long)row * per);
+    const int jx = 1 + r / (mc * mc), jy = 1 + (r / mc) % mc, jz = 1 + r % mc;
+    const T* f = fine + (size_t)row * sf;
+    T acc = T(0);
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const T wx = dx == 0 ? T(0.5) : T(0.25);
+      T ay = T(0);
+#pragma unroll
+      for (int dy = -1; dy <= 1; ++dy) {
+        const T wy = dy == 0 ? T(0.5) : T(0.25);
+        const T* p = f + ((size_t)(2 * jx + dx) * nf + (2 * jy + dy)) * nf + 2 * jz;
+        ay += wy * (T(0.25) * p[-1] + T(0.5) * p[0] + T(0.25) * p[1]);
+      }
+      acc += wx * ay;
+    }
+    coarse[(size_t)row * scs + ((size_t)jx * nc + jy) * nc + jz] = acc;
+  }
+}
+
+template <typename T>
+__global__ void k_prolong_add_rows(int nc, int rows, int row0, const CgScal* scal,
+                                   const T* __restrict__ coarse, T* __restrict__ fine) {
+  const int nf = 2 * (nc - 1) + 1, mf = nf - 2;
+  const long long per = (long long)mf * mf * mf;
+  const long long total = per * rows;
+  const size_t sf = (size_t)nf * nf * nf, scs = (size_t)nc * nc * nc;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int row = (int)(i / per);
+    if (scal && !scal[row0 + row].active) continue;
+    const int r = (int)(i - (long long)row * per);
+    const int ix = 1 + r / (mf * mf), iy = 1 + (r / mf) % mf, iz = 1 + r % mf;
+    const T* c = coarse + (size_t)row * scs;
+    const int ax = ix >> 1, bx = (ix + 1) >> 1;
+    const int ay = iy >> 1, by = (iy + 1) >> 1;
+    const int az = iz >> 1, bz = (iz + 1) >> 1;
+    const T wx = (ix & 1) ? T(0.5) : T(1), wy = (iy & 1) ? T(0.5) : T(1),
+            wz = (iz & 1) ? T(0.5) : T(1);
+    auto cv = [&](int a, int b, int d) { return c[((size_t)a * nc + b) * nc + d]; };
+    T v = cv(ax, ay, az);
+    if (iz & 1) v += cv(ax, ay, bz);
+    if (iy & 1) {
+      v += cv(ax, by, az);
+      if (iz & 1) v += cv(ax, by, bz);
+    }
+    if (ix & 1) {
+      v += cv(bx, ay, az);
+      if (iz & 1) v += cv(bx, ay, bz);
+      if (iy & 1) {
+        v += cv(bx, by, az);
+        if (iz & 1) v += cv(bx, by, bz);
+      }
+    }
+    fine[(size_t)row * sf + ((size_t)ix * nf + iy) * nf + iz] += wx * wy * wz * v;
+  }
+}
+
+static int grid_for(long long total, int bs) {
+  long long b = (total + bs - 1) / bs;
+  if (b > 65536LL * 8) b = 65536LL * 8;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+template <typename T>
+void restrict_rows(int nf, int rows, int row0, const CgScal* scal, const T* fine, T* coarse,
+                   hipStream_t s) {
+  if (rows <= 0) return;
+  const int mc = (nf - 1) / 2 - 1;
+  const long long total = (long long)mc * mc * mc * rows;
+  hipLaunchKernelGGL(k_restrict_rows<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, nf, rows,
+                     row0, scal, fine, coarse);
+}
+template <typename T>
+void prolong_add_rows(int nc, int rows, int row0, const CgScal* scal, const T* coarse, T* fine,
+                      hipStream_t s) {
+  if (rows <= 0) return;
+  const int mf = 2 * (nc - 1) - 1;
+  const long long total = (long long)mf * mf * mf * rows;
+  hipLaunchKernelGGL(k_prolong_add_rows<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, nc,
+                     rows, row0, scal, coarse, fine);
+}
+template void restrict_rows<double>(int, int, int, const CgScal*, const double*, double*,
+                                    hipStream_t);
+template void restrict_rows<float>(int, int, int, const CgScal*, const float*, float*,
+                                   hipStream_t);
+template void prolong_add_rows<double>(int, int, int, const CgScal*, const double*, double*,
+                                       hipStream_t);
+template void prolong_add_rows<float>(int, int, int, const CgScal*, const float*, float*,
+                                      hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Random field: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by
+// (seed, 0) with counter (block, sample, level, tag); Box-Muller normals; KL
+// coefficients c_j = sqrt(sigma2 lam_k) xi_j, lam_k = (1 + |k|^2)^(-5/2).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void philox_block(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                             uint64_t k0, uint64_t k1, uint64_t w[4]) {
+  const uint64_t M0 = 0xD2E7470EE14C6C93ULL, M1 = 0xCA5A826395121157ULL;
+  const uint64_t W0 = 0x9E3779B97F4A7C15ULL, W1 = 0xBB67AE8584CAA73BULL;
+#pragma unroll
+  for (int rd = 0; rd < 10; ++rd) {
+    if (rd > 0) {
+      k0 += W0;
+      k1 += W1;
+    }
+    const uint64_t lo0 = M0 * c0, hi0 = __umul64hi(M0, c0);
+    const uint64_t lo1 = M1 * c2, hi1 = __umul64hi(M1, c2);
+    const uint64_t n0 = hi1 ^ c1 ^ k0;
+    const uint64_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  w[0] = c0; w[1] = c1; w[2] = c2; w[3] = c3;
+}
+
+__device__ __forceinline__ void normals4(uint64_t seed, int level, int64_t sample, int tag,
+                                         int blk, double z[4]) {
+  uint64_t w[4];
+  philox_block((uint64_t)blk, (uint64_t)sample, (uint64_t)level, (uint64_t)tag, seed, 0ULL, w);
+  const double two_pi = 2.0 * 3.14159265358979323846;
+#pragma unroll
+  for (int pr = 0; pr < 2; ++pr) {
+    const double u1 = ((double)(w[2 * pr] >> 11) + 0.5) * 0x1.0p-53;
+    const double u2 = ((double)(w[2 * pr + 1] >> 11) + 0.5) * 0x1.0p-53;
+    const double r = sqrt(-2.0 * log(u1));
+    const double t = two_pi * u2;
+    z[2 * pr] = r * cos(t);
+    z[2 * pr + 1] = r * sin(t);
+  }
+}
+
+__global__ void k_kl_coeffs(const int* __restrict__ prob_level,
+                            const int64_t* __restrict__ prob_sample, int nprob, uint64_t seed,
+                            int K, double sigma2, double* __restrict__ coef) {
+  const int K3 = K * K * K;
+  const int nblk = (K3 + 3) / 4;
+  const long long total = (long long)nprob * nblk;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int p = (int)(i / nblk), b = (int)(i % nblk);
+    double z[4];
+    normals4(seed, prob_level[p], prob_sample[p], 0, b, z);
+    for (int q = 0; q < 4; ++q) {
+      const int j = 4 * b + q;
+      if (j >= K3) break;
+      const int k1 = j / (K * K) + 1, k2 = (j / K) % K + 1, k3 = j % K + 1;
+      const double lam = pow(1.0 + (double)(k1 * k1 + k2 * k2 + k3 * k3), -2.5);
+      coef[(size_t)p * K3 + j] = sqrt(sigma2) * sqrt(lam) * z[q];
+    }
+  }
+}
+
+__global__ void k_kl_normals(uint64_t seed, int level, int64_t first, int64_t count, int K3,
+                             double* __restrict__ xi) {
+  const int nblk = (K3 + 3) / 4;
+  const long long total = count * nblk;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const long long m = i / nblk;
+    const int b = (int)(i % nblk);
+    double z[4];
+    normals4(seed, level, first + m, 0, b, z);
+    for (int q = 0; q < 4; ++q) {
+      const int j = 4 * b + q;
+      if (j < K3) xi[m * K3 + j] = z[q];
+    }
+  }
+}
+
+__global__ void k_philox_words(uint64_t seed, int level, int64_t sample, int tag, int nblocks,
+                               uint64_t* out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nblocks) return;
+  uint64_t w[4];
+  philox_block((uint64_t)b, (uint64_t)sample, (uint64_t)level, (uint64_t)tag, seed, 0ULL, w);
+  for (int q = 0; q < 4; ++q) out[4 * b + q] = w[q];
+}
+
+__global__ void k_cos_table(int n, int K, double* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * K) return;
+  const int k = i / n + 1, v = i % n;
+  const double h = 1.0 / (double)(n - 1);
+  out[i] = cos(3.14159265358979323846 * (double)k * ((double)v * h));
+}
+
+void kl_coeffs(const int* prob_level, const int64_t* prob_sample, int nprob, uint64_t seed,
+               int K, double sigma2, double* coef, hipStream_t s) {
+  if (nprob <= 0) return;
+  const long long total = (long long)nprob * ((K * K * K + 3) / 4);
+  hipLaunchKernelGGL(k_kl_coeffs, dim3(grid_for(total, 256)), dim3(256), 0, s, prob_level,
+                     prob_sample, nprob, seed, K, sigma2, coef);
+}
+void kl_normals(uint64_t seed, int level, int64_t first, int64_t count, int K3, double* xi,
+                hipStream_t s) {
+  if (count <= 0) return;
+  const long long total = count * ((K3 + 3) / 4);
+  hipLaunchKernelGGL(k_kl_normals, dim3(grid_for(total, 256)), dim3(256), 0, s, seed, level,
+                     first, count, K3, xi);
+}
+void philox_words(uint64_t seed, int level, int64_t sample, int tag, int nblocks, uint64_t* out,
+                  hipStream_t s) {
+  if (nblocks <= 0) return;
+  hipLaunchKernelGGL(k_philox_words, dim3(cdiv(nblocks, 64)), dim3(64), 0, s, seed, level,
+                     sample, tag, nblocks, out);
+}
+void cos_table(int n, int K, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_cos_table, dim3(cdiv((long long)n * K, 256)), dim3(256), 0, s, n, K, out);
+}
+
+// ---------------------------------------------------------------------------
+// Elementwise kernels over the rows of one group.  A row is cut into
+// tiles_per_row contiguous chunks, one workgroup each, so partial sums land
+// in fixed slots and every reduction is deterministic.
+// ---------------------------------------------------------------------------
+__global__ void k_rows_broadcast(long long per, long long total, const double* __restrict__ src,
+                                 double* __restrict__ dst) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i % per];
+}
+void rows_broadcast(int n, int rows, const double* src, double* dst, hipStream_t s) {
+  const long long per = (long long)n * n * n, total = per * rows;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_rows_broadcast, dim3(grid_for(total, 256)), dim3(256), 0, s, per, total,
+                     src, dst);
+}
+__global__ void k_zero(long long count, double* x) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    x[i] = 0.0;
+}
+void rows_zero(long long count, double* x, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_zero, dim3(grid_for(count, 256)), dim3(256), 0, s, count, x);
+}
+
+enum GroupOp { G_DOT = 0, G_UPDATE = 1, G_MISFIT = 2 };
+
+template <int OP>
+__global__ void __launch_bounds__(256)
+    k_group(GridArgs g, double* a, const double* b, double* c, const double* d,
+            const int* __restrict__ poff, double* __restrict__ partial) {
+  __shared__ double sred[4];
+  const int tpr = g.t.tiles_per_row;
+  const int row = blockIdx.x / tpr;
+  const int tile = blockIdx.x - row * tpr;
+  const int prob = g.row0 + row;
+  if (g.scal && !g.scal[prob].active) return;
+  const long long N = g.stride;
+  const long long chunk = (N + tpr - 1) / tpr;
+  const long long lo = (long long)tile * chunk;
+  const long long hi = min(N, lo + chunk);
+  const size_t base = (size_t)row * (size_t)N;
+  const int n = g.n;
+  double acc = 0.0;
+  if (OP == G_DOT) {
+    for (long long i = lo + threadIdx.x; i < hi; i += 256) acc += a[base + i] * b[base + i];
+  } else if (OP == G_UPDATE) {
+    const double al = g.scal[prob].alpha;
+    for (long long i = lo + threadIdx.x; i < hi; i += 256) {
+      a[base + i] += al * b[base + i];
+      const double r = c[base + i] - al * d[base + i];
+      c[base + i] = r;
+      acc += r * r;
+    }
+  } else {  // G_MISFIT: a = y (reset to 0 afterwards), b = y_d (shared), c = adjoint rhs rows
+    for (long long i = lo + threadIdx.x; i < hi; i += 256) {
+      const int ix = (int)(i / ((long long)n * n)), iy = (int)((i / n) % n), iz = (int)(i % n);
+      const bool in = ix > 0 && iy > 0 && iz > 0 && ix < n - 1 && iy < n - 1 && iz < n - 1;
+      const double r = in ? a[base + i] - b[i] : 0.0;
+      c[base + i] = r;
+      a[base + i] = 0.0;
+      acc += r * r;
+    }
+  }
+  const double sum = block_sum<256>(acc, sred);
+  if (threadIdx.x == 0) partial[poff[prob] + tile] = sum;
+}
+
+void group_dot(const GridArgs& g, const double* a, const double* b, const int* poff,
+               double* partial, hipStream_t s) {
+  if (g.rows <= 0) return;
+  hipLaunchKernelGGL(k_group<G_DOT>, dim3(g.rows * g.t.tiles_per_row), dim3(256), 0, s, g,
+                     (double*)a, b, nullptr, nullptr, poff, partial);
+}
+void group_update(const GridArgs& g, double* x, const double* p, double* r, const double* q,
+                  const int* poff, double* partial, hipStream_t s) {
+  if (g.rows <= 0) return;
+  hipLaunchKernelGGL(k_group<G_UPDATE>, dim3(g.rows * g.t.tiles_per_row), dim3(256), 0, s, g,
+                     x, p, r, q, poff, partial);
+}
+void group_misfit(const GridArgs& g, double* y, const double* yd, double* b_rows,
+                  const int* poff, double* partial, hipStream_t s) {
+  if (g.rows <= 0) return;
+  hipLaunchKernelGGL(k_group<G_MISFIT>, dim3(g.rows * g.t.tiles_per_row), dim3(256), 0, s, g,
+                     y, yd, b_rows, nullptr, poff, partial);
+}
+
+// ---------------------------------------------------------------------------
+// Per-problem scalar steps, one workgroup for all problems (fixed summation
+// order; integer count reduced in LDS).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(1024)
+    k_cg_scalar(int phase, CgScal* scal, int nprob, const int* __restrict__ poff,
+                const int* __restrict__ pcnt, const double* __restrict__ partial, double rtol,
+                int max_iters, int* active_count) {
+  __shared__ int scount[1024];
+  int cnt = 0;
+  const double rt2 = rtol * rtol;
+  for (int p = threadIdx.x; p < nprob; p += 1024) {
+    double sum = 0.0;
+    if (partial) {
+      const int o = poff[p], c = pcnt[p];
+      for (int j = 0; j < c; ++j) sum += partial[o + j];
+    }
+    CgScal sc = scal[p];
+    switch (phase) {
+      case PH_INIT_BB:
+        sc.bb = sum;
+        sc.rr = sum;
+        sc.active = sum > 0.0;
+        sc.iters = 0;
+        sc.alpha = 0.0;
+        sc.beta = 0.0;
+        sc.rz = 0.0;
+        sc.pq = 0.0;
+        break;
+      case PH_RZ0:
+        if (sc.active) {
+          sc.rz = sum;
+          sc.beta = 0.0;
+        }
+        break;
+      case PH_RZ0_RR:
+        if (sc.active) {
+          sc.rz = sc.rr;
+          sc.beta = 0.0;
+        }
+        break;
+      case PH_ALPHA:
+        if (sc.active) {
+          sc.pq = sum;
+          if (sum > 0.0) {
+            sc.alpha = sc.rz / sum;
+          } else {
+            sc.alpha = 0.0;
+            sc.active = 0;
+          }
+        }
+        break;
+      case PH_RR:
+        if (sc.active) {
+          sc.rr = sum;
+          sc.iters += 1;
+          if (!(sum > rt2 * sc.bb) || sc.iters >= max_iters) sc.active = 0;
+        }
+        break;
+      case PH_RZ:
+        if (sc.active) {
+          sc.beta = sum / sc.rz;
+          sc.rz = sum;
+        }
+        break;
+      case PH_RZ_RR:
+        if (sc.active) {
+          sc.beta = sc.rr / sc.rz;
+          sc.rz = sc.rr;
+        }
+        break;
+      case PH_TRUE:
+        sc.rr = sum;
+        sc.active = (sc.bb > 0.0) && (sum > rt2 * sc.bb) && (sc.iters < max_iters);
+        sc.alpha = 0.0;
+        sc.beta = 0.0;
+        break;
+    }
+    scal[p] = sc;
+    cnt += sc.active;
+  }
+  scount[threadIdx.x] = cnt;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) scount[threadIdx.x] += scount[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && active_count) *active_count = scount[0];
+}
+
+void cg_scalar(int phase, CgScal* scal, int nprob, const int* poff, const int* pcnt,
+               const double* partial, double rtol, int max_iters, int* active_count,
+               hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(1024), 0, s, phase, scal, nprob, poff, pcnt,
+                     partial, rtol, max_iters, active_count);
+}
+
+__global__ void __launch_bounds__(1024)
+    k_scal_stats(const CgScal* scal, int nprob, double rtol, int* iters_max, int* nonconv,
+                 double* relres_max) {
+  __shared__ int si[1024], sn[1024];
+  __shared__ double sr[1024];
+  int it = 0, nc = 0;
+  double rr = 0.0;
+  for (int p = threadIdx.x; p < nprob; p += 1024) {
+    const CgScal sc = scal[p];
+    it = max(it, sc.iters);
+    const double rel = sc.bb > 0.0 ? sqrt(sc.rr / sc.bb) : 0.0;
+    if (!(rel <= rtol)) nc += 1;
+    rr = fmax(rr, rel != rel ? 1e300 : rel);
+  }
+  si[threadIdx.x] = it;
+  sn[threadIdx.x] = nc;
+  sr[threadIdx.x] = rr;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) {
+      si[threadIdx.x] = max(si[threadIdx.x], si[threadIdx.x + o]);
+      sn[threadIdx.x] += sn[threadIdx.x + o];
+      sr[threadIdx.x] = fmax(sr[threadIdx.x], sr[threadIdx.x + o]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    *iters_max = si[0];
+    *nonconv = sn[0];
+    *relres_max = sr[0];
+  }
+}
+void scal_to_stats(const CgScal* scal, int nprob, double rtol, int* iters_max, int* nonconv,
+                   double* relres_max, hipStream_t s) {
+  hipLaunchKernelGGL(k_scal_stats, dim3(1), dim3(1024), 0, s, scal, nprob, rtol, iters_max,
+                     nonconv, relres_max);
+}
+
+__global__ void k_sum_partials(int nprob, const int* poff, const int* pcnt,
+                               const double* partial, double scale, double* dst) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nprob) return;
+  double sum = 0.0;
+  for (int j = 0; j < pcnt[p]; ++j) sum += partial[poff[p] + j];
+  dst[p] = scale * sum;
+}
+void sum_partials(int nprob, const int* poff, const int* pcnt, const double* partial,
+                  double scale, double* dst, hipStream_t s) {
+  if (nprob <= 0) return;
+  hipLaunchKernelGGL(k_sum_partials, dim3(cdiv(nprob, 256)), dim3(256), 0, s, nprob, poff, pcnt,
+                     partial, scale, dst);
+}
+
+// ---------------------------------------------------------------------------
+// Whole-field kernels on one grid.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool interior(int n, int ix, int iy, int iz) {
+  return ix > 0 && iy > 0 && iz > 0 && ix < n - 1 && iy < n - 1 && iz < n - 1;
+}
+
+__global__ void k_restrict_full(int nf, const double* __restrict__ f, double* __restrict__ c) {
+  const int nc = (nf - 1) / 2 + 1;
+  const long long N = (long long)nc * nc * nc;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int jx = (int)(i / ((long long)nc * nc)), jy = (int)((i / nc) % nc), jz = (int)(i % nc);
+    if (!interior(nc, jx, jy, jz)) {
+      c[i] = 0.0;
+      continue;
+    }
+    double acc = 0.0;
+    for (int dx = -1; dx <= 1; ++dx) {
+      const double wx = dx == 0 ? 0.5 : 0.25;
+      double ay = 0.0;
+      for (int dy = -1; dy <= 1; ++dy) {
+        const double wy = dy == 0 ? 0.5 : 0.25;
+        const double* p = f + ((size_t)(2 * jx + dx) * nf + (2 * jy + dy)) * nf + 2 * jz;
+        ay += wy * (0.25 * p[-1] + 0.5 * p[0] + 0.25 * p[1]);
+      }
+      acc += wx * ay;
+    }
+    c[i] = acc;
+  }
+}
+void restrict_full(int nf, const double* fine, double* coarse, hipStream_t s) {
+  const int nc = (nf - 1) / 2 + 1;
+  hipLaunchKernelGGL(k_restrict_full, dim3(grid_for((long long)nc * nc * nc, 256)), dim3(256), 0,
+                     s, nf, fine, coarse);
+}
+
+__device__ __forceinline__ double prolong_at(int nc, const double* __restrict__ c, int ix, int iy,
+                                             int iz) {
+  const int ax = ix >> 1, bx = (ix + 1) >> 1;
+  const int ay = iy >> 1, by = (iy + 1) >> 1;
+  const int az = iz >> 1, bz = (iz + 1) >> 1;
+  auto cv = [&](int a, int b, int d) { return c[((size_t)a * nc + b) * nc + d]; };
+  double v = cv(ax, ay, az);
+  if (iz & 1) v += cv(ax, ay, bz);
+  if (iy & 1) {
+    v += cv(ax, by, az);
+    if (iz & 1) v += cv(ax, by, bz);
+  }
+  if (ix & 1) {
+    v += cv(bx, ay, az);
+    if (iz & 1) v += cv(bx, ay, bz);
+    if (iy & 1) {
+      v += cv(bx, by, az);
+      if (iz & 1) v += cv(bx, by, bz);
+    }
+  }
+  const double w = ((ix & 1) ? 0.5 : 1.0) * ((iy & 1) ? 0.5 : 1.0) * ((iz & 1) ? 0.5 : 1.0);
+  return w * v;
+}
+
+__global__ void k_prolong_full(int nc, const double* __restrict__ c, double* __restrict__ f) {
+  const int nf = 2 * (nc - 1) + 1;
+  const long long N = (long long)nf * nf * nf;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i / ((long long)nf * nf)), iy = (int)((i / nf) % nf), iz = (int)(i % nf);
+    f[i] = interior(nf, ix, iy, iz) ? prolong_at(nc, c, ix, iy, iz) : 0.0;
+  }
+}
+void prolong_full(int nc, const double* coarse, double* fine, hipStream_t s) {
+  const int nf = 2 * (nc - 1) + 1;
+  hipLaunchKernelGGL(k_prolong_full, dim3(grid_for((long long)nf * nf * nf, 256)), dim3(256), 0,
+                     s, nc, coarse, fine);
+}
+
+__global__ void k_inject_full(int nf, const double* __restrict__ f, int nc,
+                              double* __restrict__ c) {
+  const long long N = (long long)nc * nc * nc;
+  const int st = (nf - 1) / (nc - 1);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int jx = (int)(i / ((long long)nc * nc)), jy = (int)((i / nc) % nc), jz = (int)(i % nc);
+    c[i] = f[((size_t)jx * st * nf + (size_t)jy * st) * nf + (size_t)jz * st];
+  }
+}
+void inject_full(int nf, const double* fine, int nc, double* coarse, hipStream_t s) {
+  hipLaunchKernelGGL(k_inject_full, dim3(grid_for((long long)nc * nc * nc, 256)), dim3(256), 0,
+                     s, nf, fine, nc, coarse);
+}
+
+__global__ void k_add_mask(int n, const double* __restrict__ f, const double* __restrict__ u,
+                           double* __restrict__ out) {
+  const long long N = (long long)n * n * n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i / ((long long)n * n)), iy = (int)((i / n) % n), iz = (int)(i % n);
+    out[i] = interior(n, ix, iy, iz) ? (f ? f[i] : 0.0) + u[i] : 0.0;
+  }
+}
+void add_mask(int n, const double* f, const double* u, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_add_mask, dim3(grid_for((long long)n * n * n, 256)), dim3(256), 0, s, n, f,
+                     u, out);
+}
+
+__global__ void k_axpy_full(long long N, double a, const double* __restrict__ x,
+                            double* __restrict__ y) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+void axpy_full(int n, double a, const double* x, double* y, hipStream_t s) {
+  const long long N = (long long)n * n * n;
+  hipLaunchKernelGGL(k_axpy_full, dim3(grid_for(N, 256)), dim3(256), 0, s, N, a, x, y);
+}
+
+__global__ void __launch_bounds__(256)
+    k_dot_blocks(long long N, const double* __restrict__ a, const double* __restrict__ b,
+                 double* __restrict__ part) {
+  __shared__ double sred[4];
+  double acc = 0.0;
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < N; i += (long long)RED_BLOCKS * 256)
+    acc += a[i] * b[i];
+  const double s = block_sum<256>(acc, sred);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+void dot_blocks(long long N, const double* a, const double* b, double* part, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot_blocks, dim3(RED_BLOCKS), dim3(256), 0, s, N, a, b, part);
+}
+
+__global__ void k_box_step(int n, double* __restrict__ u, const double* __restrict__ g, double tau,
+                           double lo, double hi, int use_box) {
+  const long long N = (long long)n * n * n;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i / ((long long)n * n)), iy = (int)((i / n) % n), iz = (int)(i % n);
+    if (!interior(n, ix, iy, iz)) continue;
+    double v = u[i] - tau * g[i];
+    if (use_box) v = fmin(fmax(v, lo), hi);
+    u[i] = v;
+  }
+}
+void box_step(int n, double* u, const double* g, double tau, double lo, double hi, int use_box,
+              hipStream_t s) {
+  hipLaunchKernelGGL(k_box_step, dim3(grid_for((long long)n * n * n, 256)), dim3(256), 0, s, n, u,
+                     g, tau, lo, hi, use_box);
+}
+
+__global__ void k_nonfinite(long long count, const double* __restrict__ x, int* flag) {
+  int bad = 0;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    if (!isfinite(x[i])) bad = 1;
+  if (bad) atomicOr(flag, 1);
+}
+void nonfinite_flag(long long count, const double* x, int* flag, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_nonfinite, dim3(grid_for(count, 256)), dim3(256), 0, s, count, x, flag);
+}
+
+__global__ void k_copy_rows(long long total, const double* __restrict__ src,
+                            double* __restrict__ dst) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+void copy_rows_strided(int n, int rows, const double* src, double* dst, hipStream_t s) {
+  const long long total = (long long)n * n * n * rows;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_copy_rows, dim3(grid_for(total, 256)), dim3(256), 0, s, total, src, dst);
+}
+
+// ---------------------------------------------------------------------------
+// Entropic epilogue (Sec. 2.2 estimator, Sec. 4.1 power sums).
+// ---------------------------------------------------------------------------
+// s = max Phi over every solve; w = exp(theta (Phi - s)) in FP64.
+__global__ void __launch_bounds__(1024)
+    k_shift_weights(int nprob, const double* __restrict__ phi, double theta,
+                    double* __restrict__ w, double* s_out) {
+  __shared__ double sm[1024];
+  double m = -INFINITY;
+  for (int p = threadIdx.x; p < nprob; p += 1024) m = fmax(m, phi[p]);
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + o]);
+    __syncthreads();
+  }
+  const double s = sm[0];
+  for (int p = threadIdx.x; p < nprob; p += 1024) w[p] = exp(theta * (phi[p] - s));
+  if (threadIdx.x == 0) *s_out = s;
+}
+void shift_weights(int nprob, const double* phi, double theta, double* w, double* s_out,
+                   hipStream_t s) {
+  hipLaunchKernelGGL(k_shift_weights, dim3(1), dim3(1024), 0, s, nprob, phi, theta, w, s_out);
+}
+
+constexpr int SB = 32;  // samples per block of the level reductions
+int level_sample_blocks(int M) { return (M + SB - 1) / SB; }
+
+// dX_m(v) = w_f[m] p_f[m](v) - w_c[m] (P p_c[m])(v) at interior v of the fine grid
+__device__ __forceinline__ double dx_at(int nf, int m, const double* __restrict__ pf,
+                                        const double* __restrict__ wf,
+                                        const double* __restrict__ pc,
+                                        const double* __restrict__ wc, long long v, int ix,
+                                        int iy, int iz) {
+  const size_t sf = (size_t)nf * nf * nf;
+  double d = wf[m] * pf[(size_t)m * sf + v];
+  if (pc) {
+    const int nc = (nf - 1) / 2 + 1;
+    const size_t scs = (size_t)nc * nc * nc;
+    d -= wc[m] * prolong_at(nc, pc + (size_t)m * scs, ix, iy, iz);
+  }
+  return d;
+}
+
+__global__ void k_level_dx_partial(int nf, int M, const double* __restrict__ pf,
+                                   const double* __restrict__ wf, const double* __restrict__ pc,
+                                   const double* __restrict__ wc, double* __restrict__ part) {
+  const long long N = (long long)nf * nf * nf;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int sb = blockIdx.y;
+  if (v >= N) return;
+  const int ix = (int)(v / ((long long)nf * nf)), iy = (int)((v / nf) % nf), iz = (int)(v % nf);
+  double acc = 0.0;
+  if (interior(nf, ix, iy, iz)) {
+    const int m1 = min(M, (sb + 1) * SB);
+    for (int m = sb * SB; m < m1; ++m) acc += dx_at(nf, m, pf, wf, pc, wc, v, ix, iy, iz);
+  }
+  part[(size_t)sb * N + v] = acc;
+}
+void level_dx_partial(int nf, int M, const double* pf, const double* wf, const double* pc,
+                      const double* wc, double* part, hipStream_t s) {
+  const long long N = (long long)nf * nf * nf;
+  hipLaunchKernelGGL(k_level_dx_partial, dim3(cdiv(N, 256), level_sample_blocks(M)), dim3(256),
+                     0, s, nf, M, pf, wf, pc, wc, part);
+}
+
+__global__ void k_level_dx_mean(long long N, int nsb, int M, const double* __restrict__ part,
+                                double* __restrict__ mean) {
+  for (long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x; v < N;
+       v += (long long)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int sb = 0; sb < nsb; ++sb) acc += part[(size_t)sb * N + v];
+    mean[v] = acc / (double)M;
+  }
+}
+void level_dx_mean(int nf, int M, const double* part, double* mean, hipStream_t s) {
+  const long long N = (long long)nf * nf * nf;
+  hipLaunchKernelGGL(k_level_dx_mean, dim3(grid_for(N, 256)), dim3(256), 0, s, N,
+                     level_sample_blocks(M), M, part, mean);
+}
+
+int level_m2_chunks(int nf) {
+  const long long N = (long long)nf * nf * nf;
+  return cdiv(N, 256 * 16);
+}
+__global__ void __launch_bounds__(256)
+    k_level_dx_m2(int nf, int M, const double* __restrict__ pf, const double* __restrict__ wf,
+                  const double* __restrict__ pc, const double* __restrict__ wc,
+                  const double* __restrict__ mean, double* __restrict__ part2) {
+  __shared__ double sred[4];
+  const long long N = (long long)nf * nf * nf;
+  const int chunk = blockIdx.x, sb = blockIdx.y;
+  const long long lo = (long long)chunk * 256 * 16, hi = min(N, lo + 256 * 16);
+  const int m1 = min(M, (sb + 1) * SB);
+  double acc = 0.0;
+  for (long long v = lo + threadIdx.x; v < hi; v += 256) {
+    const int ix = (int)(v / ((long long)nf * nf)), iy = (int)((v / nf) % nf), iz = (int)(v % nf);
+    if (!interior(nf, ix, iy, iz)) continue;
+    const double mv = mean[v];
+    for (int m = sb * SB; m < m1; ++m) {
+      const double d = dx_at(nf, m, pf, wf, pc, wc, v, ix, iy, iz) - mv;
+      acc += d * d;
+    }
+  }
+  const double sum = block_sum<256>(acc, sred);
+  if (threadIdx.x == 0) part2[(size_t)sb * gridDim.x + chunk] = sum;
+}
+void level_dx_m2(int nf, int M, const double* pf, const double* wf, const double* pc,
+                 const double* wc, const double* mean, double* part2, hipStream_t s) {
+  hipLaunchKernelGGL(k_level_dx_m2, dim3(level_m2_chunks(nf), level_sample_blocks(M)), dim3(256),
+                     0, s, nf, M, pf, wf, pc, wc, mean, part2);
+}
+
+// Fixed-order block sum of f(i) over i in [0, count) for 1024 threads.
+template <typename F>
+__device__ double block_sum_1024(int count, F f, double* sm) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < count; i += 1024) acc += f(i);
+  sm[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 512; o > 0; o >>= 1) {
+    if (threadIdx.x < o) sm[threadIdx.x] += sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  const double r = sm[0];
+  __syncthreads();
+  return r;
+}
+
+// Level statistics, E^ML[Y], truncation, objective (shifted units).
+__global__ void __launch_bounds__(1024)
+    k_epilogue_scalars(int L, const EpiLevel* __restrict__ lev, const double* __restrict__ phi,
+                       const double* __restrict__ w, const double* __restrict__ part,
+                       long long u_off, int nL, double theta, double alpha, int with_dx,
+                       EpiOut* out) {
+  __shared__ double sm[1024];
+  const double s = out->s;
+  double EY = 0.0, Ephi = 0.0;
+  for (int i = 0; i < L; ++i) {
+    const EpiLevel lv = lev[i];
+    const double invM = 1.0 / (double)lv.M;
+    const bool hc = lv.coarse_off >= 0;
+    auto dY = [&](int m) {
+      return w[lv.fine_off + m] - (hc ? w[lv.coarse_off + m] : 0.0);
+    };
+    const double mdy = block_sum_1024(lv.M, dY, sm) * invM;
+    const double m2y = block_sum_1024(
+        lv.M, [&](int m) { const double d = dY(m) - mdy; return d * d; }, sm);
+    const double mphi = block_sum_1024(lv.M, [&](int m) { return phi[lv.fine_off + m]; }, sm) * invM;
+    const double mdphi =
+        block_sum_1024(lv.M, [&](int m) {
+          return phi[lv.fine_off + m] - (hc ? phi[lv.coarse_off + m] : 0.0);
+        }, sm) * invM;
+    double m2x = 0.0, nmx = 0.0;
+    if (with_dx) {
+      const double hf = 1.0 / (double)(lv.nf - 1);
+      const double h3 = hf * hf * hf;
+      m2x = h3 * block_sum_1024(lv.m2_cnt, [&](int j) { return part[lv.m2_off + j]; }, sm);
+      nmx = h3 * block_sum_1024(RED_BLOCKS, [&](int j) { return part[lv.nm_off + j]; }, sm);
+    }
+    if (threadIdx.x == 0) {
+      out->mean_dY[i] = mdy;
+      out->m2_dY[i] = m2y;
+      out->mean_phi_f[i] = mphi;
+      out->m2_dX[i] = m2x;
+      out->norm2_mean_dX[i] = nmx;
+    }
+    EY += mdy;
+    Ephi += mdphi;
+  }
+  const double hL = 1.0 / (double)(nL - 1);
+  const double un =
+      hL * hL * hL * block_sum_1024(RED_BLOCKS, [&](int j) { return part[u_off + j]; }, sm);
+  if (threadIdx.x == 0) {
+    const double floor_ = exp(-theta * s);
+    out->EY = EY;
+    out->unorm2 = un;
+    out->truncated = (theta > 0.0) && (EY < floor_);
+    out->denom = (theta > 0.0) ? fmax(EY, floor_) : 1.0;
+    out->J = (theta > 0.0) ? s + log(out->denom) / theta + 0.5 * alpha * un
+                           : Ephi + 0.5 * alpha * un;
+  }
+}
+void epilogue_scalars(int L, const EpiLevel* lev, const double* phi, const double* w,
+                      const double* part, long long u_off, int nL, double theta, double alpha,
+                      int with_dx, EpiOut* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_epilogue_scalars, dim3(1), dim3(1024), 0, s, L, lev, phi, w, part, u_off,
+                     nL, theta, alpha, with_dx, out);
+}
+
+
+__global__ void k_final_grad(int n, const double* __restrict__ acc, const double* __restrict__ u,
+                             const EpiOut* __restrict__ eo, double alpha,
+                             double* __restrict__ grad) {
+  const long long N = (long long)n * n * n;
+  const double inv = 1.0 / eo->denom;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(i / ((long long)n * n)), iy = (int)((i / n) % n), iz = (int)(i % n);
+    grad[i] = interior(n, ix, iy, iz) ? acc[i] * inv + alpha * u[i] : 0.0;
+  }
+}
+void final_grad(int n, const double* acc, const double* u, const EpiOut* eo, double alpha,
+                double* grad, hipStream_t s) {
+  hipLaunchKernelGGL(k_final_grad, dim3(grid_for((long long)n * n * n, 256)), dim3(256), 0, s, n,
+                     acc, u, eo, alpha, grad);
+}
+
+__global__ void k_finish_norm(int n, const double* __restrict__ part, double* dst) {
+  if (threadIdx.x != 0) return;
+  double acc = 0.0;
+  for (int j = 0; j < RED_BLOCKS; ++j) acc += part[j];
+  const double h = 1.0 / (double)(n - 1);
+  *dst = h * h * h * acc;
+}
+void finish_norm(int n, const double* part, double* dst, hipStream_t s) {
+  hipLaunchKernelGGL(k_finish_norm, dim3(1), dim3(64), 0, s, n, part, dst);
+}
+
+}  // namespace mlsgd

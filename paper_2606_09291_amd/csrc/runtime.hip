@@ -1,0 +1,961 @@
+// runtime.hip -- host runtime and C ABI of libmlsgd (gfx950).
+//
+// A call builds (or reuses) a plan: the list of problems (level, sample,
+// grid) of the estimate, sorted by grid size so that every grid size of the
+// multigrid hierarchy holds a prefix of the problems.  All problems of all
+// levels are then solved in lockstep by one batched Krylov iteration whose
+// kernels each cover every problem that lives on one grid size; converged
+// problems are skipped by the kernels.  The host only enqueues kernels and
+// reads one integer (problems still active) per iteration.
+#include "mlsgd.h"
+#include "internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <functional>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+using namespace mlsgd;
+
+namespace {
+
+struct Fail {
+  int code;
+  std::string msg;
+};
+
+#define HIPCHK(x)                                                                 \
+  do {                                                                            \
+    hipError_t e_ = (x);                                                          \
+    if (e_ != hipSuccess)                                                         \
+      throw Fail{e_ == hipErrorOutOfMemory ? MLSGD_EOOM : MLSGD_EHIP,             \
+                 std::string(#x) + ": " + hipGetErrorString(e_)};                 \
+  } while (0)
+
+static void require(bool ok, const std::string& msg) {
+  if (!ok) throw Fail{MLSGD_EINVAL, msg};
+}
+
+static bool is_dyadic(int n) {
+  if (n < 3) return false;
+  int m = n - 1;
+  return (m & (m - 1)) == 0;
+}
+
+static inline size_t cube(int n) { return (size_t)n * n * n; }
+
+// One grid size of the hierarchy: rows [0, rows) are the problems whose top
+// grid is at least this size; rows [top_begin, rows) have exactly this top.
+struct SizeLvl {
+  int n = 0, rows = 0, top_begin = 0;
+  Tiling t{};
+  double *X = nullptr, *B = nullptr, *R = nullptr;
+  const double* cosT = nullptr;
+};
+
+// Problems sharing a top grid: Krylov vectors.
+struct Group {
+  int n = 0, p0 = 0, count = 0, sl = 0;
+  double *x = nullptr, *q = nullptr, *b0 = nullptr;
+  double* p[2] = {nullptr, nullptr};
+  int pcur = 0;
+};
+
+struct Block {   // a run of problems on one grid keyed by one level's draws
+  int n;
+  int level;
+  int64_t first;
+  int64_t count;
+};
+
+struct Plan {
+  std::string key;
+  int nprob = 0;
+  std::vector<int> h_n, h_level;
+  std::vector<int64_t> h_sample;
+  std::vector<int> h_poff, h_pcnt;
+  std::vector<Group> groups;
+  std::vector<SizeLvl> sizes;
+  int* d_level = nullptr;
+  int64_t* d_sample = nullptr;
+  double* d_coef = nullptr;
+  CgScal* d_scal = nullptr;
+  int* d_poff = nullptr;
+  int* d_pcnt = nullptr;
+  double* d_partial = nullptr;
+  double* d_phi = nullptr;
+  double* d_w = nullptr;
+  void* arena = nullptr;
+  size_t arena_bytes = 0;
+};
+
+}  // namespace
+
+struct mlsgd_ctx {
+  mlsgd_problem pb{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  int nfin = 0;                            // finest grid of the problem
+  double* d_f = nullptr;                   // finest-grid f (zero if not given)
+  double* d_yd = nullptr;                  // finest-grid target
+  std::map<int, double*> cosT;             // per grid size
+  std::map<int, double*> yd_lvl;           // target injected per level grid
+  std::map<int, double*> rhs_lvl;          // R(f + u) per level grid
+  std::map<int, double*> mean_lvl;         // E_i[dX] per level grid
+  std::map<int, double*> acc_lvl;          // telescoped sum per level grid
+  double* d_umask = nullptr;               // u with zero boundary (finest)
+  double* d_grad = nullptr;                // gradient scratch for mlsgd_step
+  double* d_epi_part = nullptr;
+  size_t epi_part_len = 0;
+  double* d_dxpart = nullptr;
+  size_t dxpart_len = 0;
+  EpiLevel* d_epi_lev = nullptr;
+  EpiOut* d_epi_out = nullptr;
+  EpiOut* h_epi_out = nullptr;             // pinned
+  int* d_count = nullptr;
+  int* h_count = nullptr;                  // pinned
+  struct StatDev { int iters, nonconv; double relres; };
+  StatDev* d_stat = nullptr;
+  StatDev* h_stat = nullptr;               // pinned
+  int* d_flag = nullptr;
+  std::map<std::string, std::unique_ptr<Plan>> plans;
+  std::vector<void*> allocs;
+  // batch used by mlsgd_step
+  int cur_L = 0;
+  int64_t cur_M[MLSGD_MAX_LEVELS] = {0};
+  int64_t cur_off[MLSGD_MAX_LEVELS] = {0};
+  double prev_gnorm = -1.0;
+  hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+};
+
+namespace {
+
+void* dalloc(mlsgd_ctx* c, size_t bytes) {
+  void* p = nullptr;
+  if (bytes == 0) bytes = 256;
+  hipError_t e = hipMalloc(&p, bytes);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    throw Fail{MLSGD_EOOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed"};
+  }
+  c->allocs.push_back(p);
+  return p;
+}
+
+const double* cos_for(mlsgd_ctx* c, int n) {
+  auto it = c->cosT.find(n);
+  if (it != c->cosT.end()) return it->second;
+  double* d = (double*)dalloc(c, sizeof(double) * (size_t)n * c->pb.kl_K);
+  cos_table(n, c->pb.kl_K, d, c->stream);
+  HIPCHK(hipGetLastError());
+  c->cosT[n] = d;
+  return d;
+}
+
+// Arena carving with 256-byte alignment.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + 255) & ~(size_t)255;
+    T* p = (T*)(base ? base + off : nullptr);
+    off += sizeof(T) * (count ? count : 1);
+    return p;
+  }
+};
+
+// Build the layout for a list of blocks (grid sizes non-increasing).
+Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks) {
+  std::string key;
+  for (const auto& b : blocks) key += std::to_string(b.n) + ":" + std::to_string(b.count) + ";";
+  auto it = c->plans.find(key);
+  Plan* P = nullptr;
+  const int K = c->pb.kl_K, K3 = K * K * K;
+  if (it != c->plans.end()) {
+    P = it->second.get();
+  } else {
+    auto up = std::make_unique<Plan>();
+    P = up.get();
+    P->key = key;
+    long long np = 0;
+    for (const auto& b : blocks) np += b.count;
+    require(np > 0 && np < (1LL << 30), "problem count out of range");
+    P->nprob = (int)np;
+    P->h_n.resize(np);
+    P->h_level.resize(np);
+    P->h_sample.resize(np);
+    // groups
+    int p = 0;
+    for (size_t bi = 0; bi < blocks.size(); ++bi) {
+      const Block& b = blocks[bi];
+      require(bi == 0 || b.n <= blocks[bi - 1].n, "blocks must have non-increasing grids");
+      if (P->groups.empty() || P->groups.back().n != b.n) {
+        Group g;
+        g.n = b.n;
+        g.p0 = p;
+        g.count = 0;
+        P->groups.push_back(g);
+      }
+      for (int64_t m = 0; m < b.count; ++m, ++p) P->h_n[p] = b.n;
+      P->groups.back().count += (int)b.count;
+    }
+    // grid sizes from the largest top grid down to 3
+    int nmax = blocks.front().n;
+    for (int n = nmax;; n = (n - 1) / 2 + 1) {
+      SizeLvl s;
+      s.n = n;
+      s.t = make_tiling(n);
+      int rows = 0, top = 0;
+      for (int q = 0; q < P->nprob; ++q) {
+        if (P->h_n[q] >= n) rows = q + 1;
+        if (P->h_n[q] > n) top = q + 1;
+      }
+      s.rows = rows;
+      s.top_begin = top;
+      s.cosT = cos_for(c, n);
+      P->sizes.push_back(s);
+      if (n <= 3) break;
+    }
+    for (auto& g : P->groups) {
+      for (size_t k = 0; k < P->sizes.size(); ++k)
+        if (P->sizes[k].n == g.n) g.sl = (int)k;
+    }
+    P->h_pcnt.resize(np);
+    P->h_poff.resize(np);
+    long long off = 0;
+    for (int q = 0; q < P->nprob; ++q) {
+      P->h_pcnt[q] = make_tiling(P->h_n[q]).tiles_per_row;
+      P->h_poff[q] = (int)off;
+      off += P->h_pcnt[q];
+    }
+    require(off < (1LL << 31), "partial buffer too large");
+    // carve (twice: measure, then assign)
+    for (int pass = 0; pass < 2; ++pass) {
+      Carver cv{pass == 0 ? nullptr : (char*)P->arena};
+      for (auto& s : P->sizes) {
+        const size_t e = (size_t)s.rows * cube(s.n);
+        s.X = cv.take<double>(e);
+        s.B = cv.take<double>(e);
+        s.R = cv.take<double>(e);
+      }
+      for (auto& g : P->groups) {
+        const size_t e = (size_t)g.count * cube(g.n);
+        g.x = cv.take<double>(e);
+        g.q = cv.take<double>(e);
+        g.b0 = cv.take<double>(e);
+        g.p[0] = cv.take<double>(e);
+        g.p[1] = cv.take<double>(e);
+      }
+      P->d_level = cv.take<int>(np);
+      P->d_sample = cv.take<int64_t>(np);
+      P->d_coef = cv.take<double>((size_t)np * K3);
+      P->d_scal = cv.take<CgScal>(np);
+      P->d_poff = cv.take<int>(np);
+      P->d_pcnt = cv.take<int>(np);
+      P->d_partial = cv.take<double>((size_t)off);
+      P->d_phi = cv.take<double>(np);
+      P->d_w = cv.take<double>(np);
+      if (pass == 0) {
+        P->arena_bytes = cv.off + 256;
+        P->arena = dalloc(c, P->arena_bytes);
+      }
+    }
+    HIPCHK(hipMemsetAsync(P->arena, 0, P->arena_bytes, c->stream));
+    HIPCHK(hipMemcpyAsync(P->d_poff, P->h_poff.data(), sizeof(int) * np, hipMemcpyHostToDevice,
+                          c->stream));
+    HIPCHK(hipMemcpyAsync(P->d_pcnt, P->h_pcnt.data(), sizeof(int) * np, hipMemcpyHostToDevice,
+                          c->stream));
+    c->plans[key] = std::move(up);
+  }
+  // draws of this call
+  int p = 0;
+  for (const auto& b : blocks)
+    for (int64_t m = 0; m < b.count; ++m, ++p) {
+      P->h_level[p] = b.level;
+      P->h_sample[p] = b.first + m;
+    }
+  HIPCHK(hipMemcpyAsync(P->d_level, P->h_level.data(), sizeof(int) * P->nprob,
+                        hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(P->d_sample, P->h_sample.data(), sizeof(int64_t) * P->nprob,
+                        hipMemcpyHostToDevice, c->stream));
+  kl_coeffs(P->d_level, P->d_sample, P->nprob, c->pb.seed, K, c->pb.kl_sigma2, P->d_coef,
+            c->stream);
+  HIPCHK(hipGetLastError());
+  return P;
+}
+
+GridArgs args_size(mlsgd_ctx* c, Plan* P, const SizeLvl& s) {
+  GridArgs g;
+  g.n = s.n;
+  g.rows = s.rows;
+  g.row0 = 0;
+  g.stride = (long long)cube(s.n);
+  g.t = s.t;
+  g.coef = P->d_coef;
+  g.K = c->pb.kl_K;
+  g.cosT = s.cosT;
+  g.scal = P->d_scal;
+  g.ih2 = (double)(s.n - 1) * (double)(s.n - 1);
+  return g;
+}
+
+GridArgs args_group(mlsgd_ctx* c, Plan* P, const Group& gr, bool skip_inactive) {
+  GridArgs g = args_size(c, P, P->sizes[gr.sl]);
+  g.rows = gr.count;
+  g.row0 = gr.p0;
+  g.scal = skip_inactive ? P->d_scal : nullptr;
+  return g;
+}
+
+inline double* rows_of(double* base, const Group& gr) { return base + (size_t)gr.p0 * cube(gr.n); }
+
+// Symmetric V(1,1) cycle for every active problem: z = V(r) with r in the B
+// rows of each problem's top grid and z left in its X rows.  Pre-smoothing
+// is red then black from a zero guess, post-smoothing black then red (so the
+// cycle is a symmetric preconditioner); the last red pass also forms <r, z>
+// for the problems whose top grid it is.  On the 3^3 grid the single unknown
+// is black and the sweep is an exact solve.
+void vcycle(mlsgd_ctx* c, Plan* P) {
+  hipStream_t s = c->stream;
+  const int S = (int)P->sizes.size();
+  for (int k = 0; k < S; ++k) {
+    SizeLvl& L = P->sizes[k];
+    GridArgs g = args_size(c, P, L);
+    if (k == S - 1) {
+      march_gs<double>(g, L.X, L.B, 0, 1, nullptr, nullptr, 0, s);
+      march_gs<double>(g, L.X, L.B, 1, 0, P->d_poff, P->d_partial, L.top_begin, s);
+      break;
+    }
+    march_gs<double>(g, L.X, L.B, 0, 1, nullptr, nullptr, 0, s);
+    march_gs<double>(g, L.X, L.B, 1, 0, nullptr, nullptr, 0, s);
+    march_resid<double>(g, L.X, L.B, L.R, s);
+    restrict_rows<double>(L.n, L.rows, 0, P->d_scal, L.R, P->sizes[k + 1].B, s);
+  }
+  for (int k = S - 2; k >= 0; --k) {
+    SizeLvl& L = P->sizes[k];
+    GridArgs g = args_size(c, P, L);
+    prolong_add_rows<double>(P->sizes[k + 1].n, L.rows, 0, P->d_scal, P->sizes[k + 1].X, L.X, s);
+    march_gs<double>(g, L.X, L.B, 1, 0, nullptr, nullptr, 0, s);
+    march_gs<double>(g, L.X, L.B, 0, 0, P->d_poff, P->d_partial, L.top_begin, s);
+  }
+}
+
+int read_count(mlsgd_ctx* c) {
+  HIPCHK(hipMemcpyAsync(c->h_count, c->d_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return *c->h_count;
+}
+
+// Batched (preconditioned) CG on every problem of the plan.  On entry the
+// B rows of each top grid hold the right-hand side b, b0 a copy of it, x = 0.
+void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* relres_out) {
+  hipStream_t s = c->stream;
+  const bool mg = c->pb.solver == MLSGD_SOLVER_MGPCG;
+  const double rtol = c->pb.rtol;
+  const int maxit = c->pb.max_iters;
+  for (auto& gr : P->groups) {
+    GridArgs g = args_group(c, P, gr, false);
+    double* r = rows_of(P->sizes[gr.sl].B, gr);
+    group_dot(g, r, r, P->d_poff, P->d_partial, s);
+  }
+  cg_scalar(PH_INIT_BB, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
+            c->d_count, s);
+  for (int restart = 0; restart < 3; ++restart) {
+    if (mg) {
+      vcycle(c, P);
+      cg_scalar(PH_RZ0, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
+                c->d_count, s);
+    } else {
+      cg_scalar(PH_RZ0_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, nullptr, rtol, maxit,
+                c->d_count, s);
+    }
+    for (int it = 0; it < maxit; ++it) {
+      for (auto& gr : P->groups) {
+        GridArgs g = args_group(c, P, gr, true);
+        SizeLvl& L = P->sizes[gr.sl];
+        const double* z = mg ? rows_of(L.X, gr) : rows_of(L.B, gr);
+        march_matvec<double>(g, z, gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q, P->d_poff,
+                             P->d_partial, s);
+      }
+      cg_scalar(PH_ALPHA, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
+                c->d_count, s);
+      for (auto& gr : P->groups) {
+        GridArgs g = args_group(c, P, gr, true);
+        group_update(g, gr.x, gr.p[gr.pcur ^ 1], rows_of(P->sizes[gr.sl].B, gr), gr.q,
+                     P->d_poff, P->d_partial, s);
+        gr.pcur ^= 1;
+      }
+      cg_scalar(PH_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
+                c->d_count, s);
+      HIPCHK(hipGetLastError());
+      if (read_count(c) == 0) break;
+      if (mg) {
+        vcycle(c, P);
+        cg_scalar(PH_RZ, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
+                  c->d_count, s);
+      } else {
+        cg_scalar(PH_RZ_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, nullptr, rtol, maxit,
+                  c->d_count, s);
+      }
+    }
+    // true residual b0 - A x into q, its norm; restart the problems that drifted
+    for (auto& gr : P->groups) {
+      GridArgs g = args_group(c, P, gr, false);
+      march_resid<double>(g, gr.x, gr.b0, gr.q, s);
+      group_dot(g, gr.q, gr.q, P->d_poff, P->d_partial, s);
+    }
+    cg_scalar(PH_TRUE, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
+              c->d_count, s);
+    HIPCHK(hipGetLastError());
+    if (read_count(c) == 0) break;
+    for (auto& gr : P->groups)
+      copy_rows_strided(gr.n, gr.count, gr.q, rows_of(P->sizes[gr.sl].B, gr), s);
+  }
+  scal_to_stats(P->d_scal, P->nprob, rtol, &c->d_stat->iters, &c->d_stat->nonconv,
+                &c->d_stat->relres, s);
+  HIPCHK(hipMemcpyAsync(c->h_stat, c->d_stat, sizeof(mlsgd_ctx::StatDev), hipMemcpyDeviceToHost,
+                        s));
+  HIPCHK(hipStreamSynchronize(s));
+  *iters_out = c->h_stat->iters;
+  *nonconv_out = c->h_stat->nonconv;
+  *relres_out = c->h_stat->relres;
+}
+
+// Right-hand sides R^(finest -> n)(f + u) on every level grid.
+void level_rhs(mlsgd_ctx* c, const double* u) {
+  const int L = c->pb.n_levels;
+  const int nf = c->nfin;
+  add_mask(nf, c->d_f, u, c->rhs_lvl[nf], c->stream);
+  for (int i = L - 2; i >= 0; --i) {
+    const int n = c->pb.grid_n[i];
+    restrict_full(c->pb.grid_n[i + 1], c->rhs_lvl[c->pb.grid_n[i + 1]], c->rhs_lvl[n], c->stream);
+  }
+  HIPCHK(hipGetLastError());
+}
+
+// State solves of every problem, then misfits Phi and the adjoint right-hand
+// sides y - y_d in the B rows (x reset to 0).
+void state_phase(mlsgd_ctx* c, Plan* P, int* it, int* nc, double* rr, double* y_out) {
+  hipStream_t s = c->stream;
+  for (auto& gr : P->groups) {
+    double* b = rows_of(P->sizes[gr.sl].B, gr);
+    rows_broadcast(gr.n, gr.count, c->rhs_lvl[gr.n], b, s);
+    rows_broadcast(gr.n, gr.count, c->rhs_lvl[gr.n], gr.b0, s);
+    rows_zero((long long)gr.count * cube(gr.n), gr.x, s);
+  }
+  HIPCHK(hipGetLastError());
+  krylov(c, P, it, nc, rr);
+  for (auto& gr : P->groups) {
+    if (y_out) copy_rows_strided(gr.n, gr.count, gr.x, y_out, s);
+    GridArgs g = args_group(c, P, gr, false);
+    double* b = rows_of(P->sizes[gr.sl].B, gr);
+    group_misfit(g, gr.x, c->yd_lvl[gr.n], b, P->d_poff, P->d_partial, s);
+    copy_rows_strided(gr.n, gr.count, b, gr.b0, s);
+    const double h = 1.0 / (double)(gr.n - 1);
+    sum_partials(gr.count, P->d_poff + gr.p0, P->d_pcnt + gr.p0, P->d_partial, 0.5 * h * h * h,
+                 P->d_phi + gr.p0, s);
+  }
+  HIPCHK(hipGetLastError());
+}
+
+void check_u(mlsgd_ctx* c, const double* u) {
+  require(u != nullptr, "u_fine is null");
+  HIPCHK(hipMemsetAsync(c->d_flag, 0, sizeof(int), c->stream));
+  nonfinite_flag((long long)cube(c->nfin), u, c->d_flag, c->stream);
+  HIPCHK(hipMemcpyAsync(c->h_count, c->d_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (*c->h_count) throw Fail{MLSGD_ENONFINITE, "u_fine holds NaN or Inf"};
+}
+
+// Problem blocks of an MLMC estimate over levels 0..L-1, grouped by grid:
+// grid n_i holds the fine solves of level i, then the coarse solves of
+// level i+1 (both keyed by their own level's draws).
+std::vector<Block> mlmc_blocks(mlsgd_ctx* c, int L, const int64_t* M, const int64_t* first) {
+  std::vector<Block> b;
+  for (int i = L - 1; i >= 0; --i) {
+    b.push_back(Block{c->pb.grid_n[i], i, first ? first[i] : 0, M[i]});
+    if (i + 1 <= L - 1) b.push_back(Block{c->pb.grid_n[i], i + 1, first ? first[i + 1] : 0, M[i + 1]});
+  }
+  return b;
+}
+
+struct LevelRows {
+  int fine_prob, coarse_prob;   // problem index of the first fine / coarse problem
+  const Group* gf;
+  const Group* gc;
+  int fine_row, coarse_row;     // row within the group
+};
+
+std::vector<LevelRows> level_rows(Plan* P, mlsgd_ctx* c, int L, const int64_t* M) {
+  std::vector<LevelRows> out(L);
+  // blocks are: for i = L-1..0: [fine i][coarse i+1]
+  int p = 0;
+  std::vector<int> fine_p(L), coarse_p(L, -1);
+  for (int i = L - 1; i >= 0; --i) {
+    fine_p[i] = p;
+    p += (int)M[i];
+    if (i + 1 <= L - 1) {
+      coarse_p[i + 1] = p;
+      p += (int)M[i + 1];
+    }
+  }
+  for (int i = 0; i < L; ++i) {
+    LevelRows lr;
+    lr.fine_prob = fine_p[i];
+    lr.coarse_prob = coarse_p[i];
+    lr.gf = lr.gc = nullptr;
+    lr.fine_row = lr.coarse_row = 0;
+    for (const auto& g : P->groups) {
+      if (g.n == c->pb.grid_n[i]) {
+        lr.gf = &g;
+        lr.fine_row = fine_p[i] - g.p0;
+      }
+      if (i > 0 && g.n == c->pb.grid_n[i - 1]) {
+        lr.gc = &g;
+        lr.coarse_row = coarse_p[i] - g.p0;
+      }
+    }
+    out[i] = lr;
+  }
+  return out;
+}
+
+void ensure_epi(mlsgd_ctx* c, size_t part_len, size_t dx_len) {
+  if (part_len > c->epi_part_len) {
+    c->d_epi_part = (double*)dalloc(c, sizeof(double) * part_len);
+    c->epi_part_len = part_len;
+  }
+  if (dx_len > c->dxpart_len) {
+    c->d_dxpart = (double*)dalloc(c, sizeof(double) * dx_len);
+    c->dxpart_len = dx_len;
+  }
+}
+
+// One estimate (gradient or objective only).
+int run_estimate(mlsgd_ctx* c, const double* u, int L, const int64_t* M, const int64_t* first,
+                 double* grad_out, double* J_out, mlsgd_grad_stats* st) {
+  require(L >= 1 && L <= c->pb.n_levels, "L out of range");
+  require(M != nullptr, "M is null");
+  for (int i = 0; i < L; ++i) {
+    require(M[i] >= 1, "sample counts must be >= 1");
+    if (first) require(first[i] >= 0, "sample offsets must be >= 0");
+  }
+  check_u(c, u);
+  hipStream_t s = c->stream;
+  HIPCHK(hipEventRecord(c->ev[0], s));
+  level_rhs(c, u);
+  Plan* P = get_plan(c, mlmc_blocks(c, L, M, first));
+  int it_s = 0, nc_s = 0, it_a = 0, nc_a = 0;
+  double rr_s = 0, rr_a = 0;
+  state_phase(c, P, &it_s, &nc_s, &rr_s, nullptr);
+  if (grad_out) krylov(c, P, &it_a, &nc_a, &rr_a);
+  HIPCHK(hipEventRecord(c->ev[1], s));
+
+  // epilogue
+  const int nL = c->pb.grid_n[L - 1];
+  std::vector<LevelRows> lr = level_rows(P, c, L, M);
+  std::vector<EpiLevel> ev(L);
+  size_t part_len = RED_BLOCKS, dx_len = 0;
+  for (int i = 0; i < L; ++i) {
+    const int nf = c->pb.grid_n[i];
+    ev[i].M = (int)M[i];
+    ev[i].fine_off = lr[i].fine_prob;
+    ev[i].coarse_off = lr[i].coarse_prob;
+    ev[i].nf = nf;
+    ev[i].m2_off = (long long)part_len;
+    ev[i].m2_cnt = level_sample_blocks((int)M[i]) * level_m2_chunks(nf);
+    part_len += ev[i].m2_cnt;
+    ev[i].nm_off = (long long)part_len;
+    part_len += RED_BLOCKS;
+    dx_len = std::max(dx_len, (size_t)level_sample_blocks((int)M[i]) * cube(nf));
+  }
+  const long long g_off = (long long)part_len;
+  part_len += RED_BLOCKS;
+  ensure_epi(c, part_len, dx_len);
+  shift_weights(P->nprob, P->d_phi, c->pb.theta, P->d_w, &c->d_epi_out->s, s);
+  add_mask(c->nfin, nullptr, u, c->d_umask, s);
+  dot_blocks((long long)cube(c->nfin), c->d_umask, c->d_umask, c->d_epi_part, s);
+  if (grad_out) {
+    for (int i = 0; i < L; ++i) {
+      const int nf = c->pb.grid_n[i];
+      const double* pf = lr[i].gf->x + (size_t)lr[i].fine_row * cube(nf);
+      const double* wf = P->d_w + lr[i].fine_prob;
+      const double* pc = nullptr;
+      const double* wc = nullptr;
+      if (i > 0) {
+        pc = lr[i].gc->x + (size_t)lr[i].coarse_row * cube(c->pb.grid_n[i - 1]);
+        wc = P->d_w + lr[i].coarse_prob;
+      }
+      double* mean = c->mean_lvl[nf];
+      level_dx_partial(nf, (int)M[i], pf, wf, pc, wc, c->d_dxpart, s);
+      level_dx_mean(nf, (int)M[i], c->d_dxpart, mean, s);
+      level_dx_m2(nf, (int)M[i], pf, wf, pc, wc, mean, c->d_epi_part + ev[i].m2_off, s);
+      dot_blocks((long long)cube(nf), mean, mean, c->d_epi_part + ev[i].nm_off, s);
+    }
+  }
+  HIPCHK(hipMemcpyAsync(c->d_epi_lev, ev.data(), sizeof(EpiLevel) * L, hipMemcpyHostToDevice, s));
+  // the fine-grid misfit scale is the one of the level's own grid; u norm on the finest grid
+  epilogue_scalars(L, c->d_epi_lev, P->d_phi, P->d_w, c->d_epi_part, 0, c->nfin, c->pb.theta,
+                   c->pb.alpha, grad_out ? 1 : 0, c->d_epi_out, s);
+  if (grad_out) {
+    // telescoping: acc_i = P acc_{i-1} + E_i[dX], then up to the finest grid
+    const double* acc = c->mean_lvl[c->pb.grid_n[0]];
+    for (int i = 1; i < c->pb.n_levels; ++i) {
+      const int n = c->pb.grid_n[i];
+      double* dst = c->acc_lvl[n];
+      prolong_full(c->pb.grid_n[i - 1], acc, dst, s);
+      if (i < L) axpy_full(n, 1.0, c->mean_lvl[n], dst, s);
+      acc = dst;
+    }
+    dot_blocks((long long)cube(c->nfin), acc, acc, c->d_epi_part + g_off, s);
+    finish_norm(c->nfin, c->d_epi_part + g_off, &c->d_epi_out->exnorm2, s);
+    final_grad(c->nfin, acc, u, c->d_epi_out, c->pb.alpha, grad_out, s);
+    dot_blocks((long long)cube(c->nfin), grad_out, grad_out, c->d_epi_part + g_off, s);
+    finish_norm(c->nfin, c->d_epi_part + g_off, &c->d_epi_out->gnorm2, s);
+  }
+  (void)nL;
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(c->ev[2], s));
+  HIPCHK(hipMemcpyAsync(c->h_epi_out, c->d_epi_out, sizeof(EpiOut), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const EpiOut& eo = *c->h_epi_out;
+  if (J_out) *J_out = eo.J;
+  if (st) {
+    std::memset(st, 0, sizeof(*st));
+    st->s = eo.s;
+    st->EY_shifted = eo.EY;
+    st->J = eo.J;
+    st->truncated = eo.truncated;
+    st->iters_state = it_s;
+    st->iters_adjoint = it_a;
+    st->nonconverged = nc_s + nc_a;
+    st->max_relres = std::max(rr_s, rr_a);
+    for (int i = 0; i < L; ++i) {
+      st->mean_dY[i] = eo.mean_dY[i];
+      st->norm2_mean_dX[i] = eo.norm2_mean_dX[i];
+      st->m2_dX[i] = eo.m2_dX[i];
+      st->m2_dY[i] = eo.m2_dY[i];
+      st->mean_phi_f[i] = eo.mean_phi_f[i];
+    }
+    st->grad_norm = grad_out ? std::sqrt(eo.gnorm2) : 0.0;
+    st->norm2_EX = grad_out ? eo.exnorm2 : 0.0;
+    float ms1 = 0, ms2 = 0;
+    HIPCHK(hipEventElapsedTime(&ms1, c->ev[0], c->ev[1]));
+    HIPCHK(hipEventElapsedTime(&ms2, c->ev[0], c->ev[2]));
+    st->ms_solve = ms1;
+    st->ms_total = ms2;
+  }
+  if (!std::isfinite(eo.J)) throw Fail{MLSGD_ENONFINITE, "non-finite objective"};
+  if (nc_s + nc_a > 0) {
+    c->err = "some solves missed rtol";
+    return MLSGD_ENOCONV;
+  }
+  return MLSGD_OK;
+}
+
+// Adaptive controller (Sec. 4.1): second-order power sums v^2 per level,
+// optimal batch sizes for a sampling error eps^2/2, sampling-error estimate.
+// Units: the paper's unshifted X, Y (statistics are rescaled by e^{theta s}).
+// Costs: the deterministic model C_i = (fine + coarse interior unknowns) per
+// sample, so the batch sequence is reproducible.
+void controller(mlsgd_ctx* c, const mlsgd_grad_stats& g, int L, const int64_t* M,
+                mlsgd_step_stats* out, int64_t* M_next) {
+  const double th = c->pb.theta;
+  const double sc = std::exp(th * g.s);
+  const double EY = g.EY_shifted * sc;
+  // C_hat = |E^ML X|^2 / E^ML[Y]^2 (the shift cancels in the ratio)
+  const double Chat = g.norm2_EX / (g.EY_shifted * g.EY_shifted);
+  double v2[MLSGD_MAX_LEVELS], C[MLSGD_MAX_LEVELS];
+  for (int i = 0; i < L; ++i) {
+    v2[i] = (g.m2_dX[i] + Chat * g.m2_dY[i]) * sc * sc;
+    const double nf = (double)(c->pb.grid_n[i] - 2);
+    const double ncs = i > 0 ? (double)(c->pb.grid_n[i - 1] - 2) : 0.0;
+    C[i] = nf * nf * nf + ncs * ncs * ncs;
+  }
+  const double gn = g.grad_norm;
+  const double eps = 0.9 * (c->prev_gnorm > 0 ? c->prev_gnorm : gn);
+  double sum = 0.0;
+  for (int i = 0; i < L; ++i) sum += std::sqrt(v2[i] * C[i] / (double)std::max<int64_t>(M[i] - 1, 1));
+  double err_sam = 0.0;
+  for (int i = 0; i < L; ++i) {
+    const double Mi = (double)M[i];
+    err_sam += v2[i] / (Mi * std::max(Mi - 1.0, 1.0));
+    double mo = (2.0 / (eps * eps)) *
+                std::sqrt(v2[i] / ((double)std::max<int64_t>(M[i] - 1, 1) * C[i])) * sum;
+    if (!std::isfinite(mo) || mo > 1e9) mo = 1e9;
+    M_next[i] = std::max<int64_t>(2, (int64_t)std::ceil(mo));
+  }
+  // squared-bias estimate with rate alpha_hat from a least-squares fit of
+  // log2 sqrt(|E dX_i|^2 + C_hat |E dY_i|^2) over levels 1..L-1 (fallback 2)
+  double ahat = 2.0;
+  if (L >= 3) {
+    double sx = 0, sy = 0, sxx = 0, sxy = 0;
+    int cnt = 0;
+    for (int i = 1; i < L; ++i) {
+      const double e = std::sqrt(g.norm2_mean_dX[i] + Chat * g.mean_dY[i] * g.mean_dY[i]) * sc;
+      if (!(e > 0)) continue;
+      const double y = std::log2(e);
+      sx += i; sy += y; sxx += (double)i * i; sxy += i * y; ++cnt;
+    }
+    if (cnt >= 2) {
+      const double slope = (cnt * sxy - sx * sy) / (cnt * sxx - sx * sx);
+      if (std::isfinite(slope) && -slope > 0.5) ahat = -slope;
+    }
+  }
+  double err_num = 0.0;
+  for (int i = 1; i < L; ++i) {
+    const double e2 = (g.norm2_mean_dX[i] + Chat * g.mean_dY[i] * g.mean_dY[i]) * sc * sc;
+    const double hr = std::pow(2.0, (double)(L - 1 - i));  // h_i / h_L
+    const double d = (std::pow(2.0, ahat) - 1.0);
+    err_num = std::max(err_num, e2 / (d * d) * std::pow(hr, -2.0 * ahat));
+  }
+  if (out) {
+    out->err_sam = err_sam;
+    out->err_num = err_num;
+    out->eps = eps;
+  }
+}
+
+
+int guard_impl(mlsgd_ctx* c, const std::function<int()>& fn) {
+  try {
+    if (c) c->err.clear();
+    return fn();
+  } catch (const Fail& f) {
+    if (c) c->err = f.msg;
+    return f.code;
+  } catch (const std::exception& e) {
+    if (c) c->err = e.what();
+    return MLSGD_EHIP;
+  }
+}
+}  // namespace
+
+extern "C" {
+
+int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
+  if (!out || !pb) return MLSGD_EINVAL;
+  *out = nullptr;
+  auto c = std::make_unique<mlsgd_ctx>();
+  int rc = guard_impl(c.get(), [&]() -> int {
+    require(pb->n_levels >= 1 && pb->n_levels <= MLSGD_MAX_LEVELS, "n_levels out of range");
+    for (int i = 0; i < pb->n_levels; ++i) {
+      require(is_dyadic(pb->grid_n[i]) && pb->grid_n[i] >= 5 && pb->grid_n[i] <= 1025,
+              "grid sizes must be 2^m + 1 between 5 and 1025");
+      if (i > 0) require(pb->grid_n[i] == 2 * pb->grid_n[i - 1] - 1, "levels must be nested");
+    }
+    require(pb->kl_K >= 1 && pb->kl_K <= MLSGD_MAX_K, "kl_K out of range");
+    require(pb->kl_sigma2 >= 0.0 && std::isfinite(pb->kl_sigma2), "kl_sigma2 must be >= 0");
+    require(pb->theta >= 0.0 && std::isfinite(pb->theta), "theta must be >= 0");
+    require(pb->alpha >= 0.0 && std::isfinite(pb->alpha), "alpha must be >= 0");
+    require(pb->precision == MLSGD_FP64, "this build supports precision MLSGD_FP64");
+    require(pb->solver == MLSGD_SOLVER_CG || pb->solver == MLSGD_SOLVER_MGPCG, "unknown solver");
+    require(pb->rtol > 0.0 && pb->rtol < 1.0, "rtol must be in (0, 1)");
+    require(pb->max_iters >= 1, "max_iters must be >= 1");
+    require(pb->y_d != nullptr, "y_d is null");
+    c->pb = *pb;
+    c->stream = (hipStream_t)stream;
+    c->nfin = pb->grid_n[pb->n_levels - 1];
+    const size_t NF = cube(c->nfin);
+    c->d_f = (double*)dalloc(c.get(), sizeof(double) * NF);
+    c->d_yd = (double*)dalloc(c.get(), sizeof(double) * NF);
+    if (pb->f)
+      HIPCHK(hipMemcpyAsync(c->d_f, pb->f, sizeof(double) * NF, hipMemcpyDeviceToDevice, c->stream));
+    else
+      HIPCHK(hipMemsetAsync(c->d_f, 0, sizeof(double) * NF, c->stream));
+    HIPCHK(hipMemcpyAsync(c->d_yd, pb->y_d, sizeof(double) * NF, hipMemcpyDeviceToDevice,
+                          c->stream));
+    c->pb.f = c->d_f;
+    c->pb.y_d = c->d_yd;
+    for (int i = 0; i < pb->n_levels; ++i) {
+      const int n = pb->grid_n[i];
+      const size_t N = cube(n);
+      c->yd_lvl[n] = (double*)dalloc(c.get(), sizeof(double) * N);
+      c->rhs_lvl[n] = (double*)dalloc(c.get(), sizeof(double) * N);
+      c->mean_lvl[n] = (double*)dalloc(c.get(), sizeof(double) * N);
+      c->acc_lvl[n] = (double*)dalloc(c.get(), sizeof(double) * N);
+      HIPCHK(hipMemsetAsync(c->mean_lvl[n], 0, sizeof(double) * N, c->stream));
+      inject_full(c->nfin, c->d_yd, n, c->yd_lvl[n], c->stream);
+    }
+    c->d_umask = (double*)dalloc(c.get(), sizeof(double) * NF);
+    c->d_grad = (double*)dalloc(c.get(), sizeof(double) * NF);
+    c->d_epi_lev = (EpiLevel*)dalloc(c.get(), sizeof(EpiLevel) * MLSGD_MAX_LEVELS);
+    c->d_epi_out = (EpiOut*)dalloc(c.get(), sizeof(EpiOut));
+    c->d_count = (int*)dalloc(c.get(), sizeof(int));
+    c->d_flag = (int*)dalloc(c.get(), sizeof(int));
+    c->d_stat = (mlsgd_ctx::StatDev*)dalloc(c.get(), sizeof(mlsgd_ctx::StatDev));
+    HIPCHK(hipHostMalloc((void**)&c->h_epi_out, sizeof(EpiOut), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->h_count, sizeof(int), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->h_stat, sizeof(mlsgd_ctx::StatDev), hipHostMallocDefault));
+    for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+    c->cur_L = pb->n_levels;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MLSGD_OK;
+  });
+  if (rc != MLSGD_OK) {
+    mlsgd_destroy(c.release());
+    return rc;
+  }
+  *out = c.release();
+  return MLSGD_OK;
+}
+
+int mlsgd_destroy(mlsgd_ctx* c) {
+  if (!c) return MLSGD_OK;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  (void)hipDeviceSynchronize();
+  for (void* p : c->allocs) (void)hipFree(p);
+  if (c->h_epi_out) (void)hipHostFree(c->h_epi_out);
+  if (c->h_count) (void)hipHostFree(c->h_count);
+  if (c->h_stat) (void)hipHostFree(c->h_stat);
+  for (auto& e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  delete c;
+  return MLSGD_OK;
+}
+
+const char* mlsgd_last_error(const mlsgd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int mlsgd_sample_fields(mlsgd_ctx* c, int level, int64_t first, int64_t count, double* xi_out) {
+  if (!c) return MLSGD_EINVAL;
+  return guard_impl(c, [&]() -> int {
+    require(level >= 0 && level < c->pb.n_levels, "level out of range");
+    require(first >= 0 && count >= 0, "first and count must be >= 0");
+    require(count == 0 || xi_out != nullptr, "xi_out is null");
+    const int K3 = c->pb.kl_K * c->pb.kl_K * c->pb.kl_K;
+    kl_normals(c->pb.seed, level, first, count, K3, xi_out, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return MLSGD_OK;
+  });
+}
+
+int mlsgd_philox_words(uint64_t seed, int level, int64_t sample, int tag, int nblocks,
+                       uint64_t* out, void* stream) {
+  if (nblocks < 0 || (nblocks > 0 && !out)) return MLSGD_EINVAL;
+  philox_words(seed, level, sample, tag, nblocks, out, (hipStream_t)stream);
+  if (hipGetLastError() != hipSuccess) return MLSGD_EHIP;
+  if (hipStreamSynchronize((hipStream_t)stream) != hipSuccess) return MLSGD_EHIP;
+  return MLSGD_OK;
+}
+
+int mlsgd_solve_state_adjoint(mlsgd_ctx* c, int level, int coarse, int64_t first, int64_t count,
+                              const double* u, double* y_out, double* p_out, double* phi_out,
+                              mlsgd_solve_stats* st) {
+  if (!c) return MLSGD_EINVAL;
+  return guard_impl(c, [&]() -> int {
+    require(level >= 0 && level < c->pb.n_levels, "level out of range");
+    require(coarse == 0 || (coarse == 1 && level >= 1), "coarse solve needs level >= 1");
+    require(first >= 0 && count >= 1, "need first >= 0 and count >= 1");
+    check_u(c, u);
+    const int n = c->pb.grid_n[level - coarse];
+    level_rhs(c, u);
+    std::vector<Block> b{Block{n, level, first, count}};
+    Plan* P = get_plan(c, b);
+    int it1 = 0, nc1 = 0, it2 = 0, nc2 = 0;
+    double r1 = 0, r2 = 0;
+    state_phase(c, P, &it1, &nc1, &r1, y_out);
+    if (phi_out)
+      HIPCHK(hipMemcpyAsync(phi_out, P->d_phi, sizeof(double) * count, hipMemcpyDeviceToDevice,
+                            c->stream));
+    if (p_out) {
+      krylov(c, P, &it2, &nc2, &r2);
+      copy_rows_strided(n, (int)count, P->groups[0].x, p_out, c->stream);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (st) {
+      st->iterations = std::max(it1, it2);
+      st->nonconverged = nc1 + nc2;
+      st->max_relres = std::max(r1, r2);
+    }
+    if (nc1 + nc2 > 0) {
+      c->err = "some solves missed rtol";
+      return MLSGD_ENOCONV;
+    }
+    return MLSGD_OK;
+  });
+}
+
+int mlsgd_mlmc_gradient(mlsgd_ctx* c, const double* u, int L, const int64_t* M,
+                        const int64_t* first, double* grad_out, mlsgd_grad_stats* st) {
+  if (!c) return MLSGD_EINVAL;
+  return guard_impl(c, [&]() -> int {
+    require(grad_out != nullptr, "grad_out is null");
+    return run_estimate(c, u, L, M, first, grad_out, nullptr, st);
+  });
+}
+
+int mlsgd_mlmc_objective(mlsgd_ctx* c, const double* u, int L, const int64_t* M,
+                         const int64_t* first, double* J_out, mlsgd_grad_stats* st) {
+  if (!c) return MLSGD_EINVAL;
+  return guard_impl(c, [&]() -> int {
+    require(J_out != nullptr, "J_out is null");
+    return run_estimate(c, u, L, M, first, nullptr, J_out, st);
+  });
+}
+
+int mlsgd_set_batch(mlsgd_ctx* c, int L, const int64_t* M, const int64_t* offsets) {
+  if (!c) return MLSGD_EINVAL;
+  return guard_impl(c, [&]() -> int {
+    require(L >= 1 && L <= c->pb.n_levels, "L out of range");
+    require(M != nullptr, "M is null");
+    for (int i = 0; i < L; ++i) {
+      require(M[i] >= 1, "sample counts must be >= 1");
+      if (offsets) require(offsets[i] >= 0, "offsets must be >= 0");
+    }
+    c->cur_L = L;
+    for (int i = 0; i < MLSGD_MAX_LEVELS; ++i) {
+      c->cur_M[i] = i < L ? M[i] : 0;
+      c->cur_off[i] = (offsets && i < L) ? offsets[i] : 0;
+    }
+    c->prev_gnorm = -1.0;
+    return MLSGD_OK;
+  });
+}
+
+int mlsgd_step(mlsgd_ctx* c, double* u, double tau, int adapt, mlsgd_step_stats* st) {
+  if (!c) return MLSGD_EINVAL;
+  return guard_impl(c, [&]() -> int {
+    require(u != nullptr, "u is null");
+    require(std::isfinite(tau), "tau must be finite");
+    require(c->cur_M[0] >= 1, "call mlsgd_set_batch first");
+    if (adapt)
+      for (int i = 0; i < c->cur_L; ++i) require(c->cur_M[i] >= 2, "adapt needs M >= 2");
+    mlsgd_grad_stats g{};
+    const int rc = run_estimate(c, u, c->cur_L, c->cur_M, c->cur_off, c->d_grad, nullptr, &g);
+    if (rc != MLSGD_OK && rc != MLSGD_ENOCONV) return rc;
+    const bool box = c->pb.u_lo <= c->pb.u_hi;
+    box_step(c->nfin, u, c->d_grad, tau, c->pb.u_lo, c->pb.u_hi, box ? 1 : 0, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    int64_t Mn[MLSGD_MAX_LEVELS];
+    for (int i = 0; i < MLSGD_MAX_LEVELS; ++i) Mn[i] = c->cur_M[i];
+    mlsgd_step_stats loc{};
+    if (adapt) controller(c, g, c->cur_L, c->cur_M, &loc, Mn);
+    for (int i = 0; i < c->cur_L; ++i) c->cur_off[i] += c->cur_M[i];
+    c->prev_gnorm = g.grad_norm;
+    if (adapt)
+      for (int i = 0; i < c->cur_L; ++i) c->cur_M[i] = Mn[i];
+    if (st) {
+      loc.grad = g;
+      for (int i = 0; i < MLSGD_MAX_LEVELS; ++i) {
+        loc.M_next[i] = i < c->cur_L ? c->cur_M[i] : 0;
+        loc.offset[i] = i < c->cur_L ? c->cur_off[i] : 0;
+      }
+      *st = loc;
+    }
+    return rc;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,192 @@
+"""GPU path (through the C ABI) against the FP64 oracle on identical inputs.
+
+Tolerances: solves 1e-10 relative L2 at solver tolerance 1e-12; gradient
+estimates 1e-9 relative L2 (FP64 path); Philox words and sample bookkeeping
+bit-exact; normals within a few ulp (device vs host libm).
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2606_09291_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def mm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_09291_amd as m
+    m.lib()
+    return m
+
+
+def _ctx(mm, grid, **kw):
+    nL = grid[-1]
+    yd = kw.pop("yd", inputs.target_sin(nL))
+    f = kw.pop("f", None)
+    pb = mm.Problem(grid_n=grid, y_d=yd, f=f, **kw)
+    return mm.Context(pb)
+
+
+@pytest.mark.parametrize("seed,level,sample,tag", [(0, 0, 0, 0), (0, 4, 1023, 0),
+                                                   (12345, 5, 2 ** 40 + 7, 1)])
+def test_philox_words_bit_exact(mm, orc, seed, level, sample, tag):
+    w = mm.philox_words(seed, level, sample, tag, 32).cpu().numpy().view(np.uint64)
+    ref = orc.philox_words(seed, level, sample, tag, 32)
+    assert np.array_equal(w, ref)
+
+
+def test_sample_fields(mm, orc):
+    print("sample_fields", flush=True)
+    ctx = _ctx(mm, [9, 17, 33], K=4)
+    for level, first, count in [(0, 0, 5), (2, 1000, 3)]:
+        xi = ctx.sample_fields(level, first, count).cpu().numpy()
+        for m in range(count):
+            ref = orc.normals(0, level, first + m, 0, 64)
+            assert np.max(np.abs(xi[m] - ref)) <= 8 * np.finfo(float).eps * np.max(np.abs(ref))
+    ctx.close()
+
+
+@pytest.mark.parametrize("grid,level,coarse,solver,count", [
+    ([17], 0, 0, "cg", 4), ([9, 17], 1, 0, "mgpcg", 5), ([9, 17], 1, 1, "mgpcg", 3),
+    ([9, 17, 33], 2, 0, "mgpcg", 3)])
+def test_solve_state_adjoint(mm, orc, grid, level, coarse, solver, count):
+    print("solve", grid, level, coarse, solver, count, flush=True)
+    nL = grid[-1]
+    u = inputs.control_xyz(nL) * 10.0 + 5.0 * inputs.target_sin(nL)
+    f = inputs.constant(nL, 1.0)
+    s = mm.SOLVER_CG if solver == "cg" else mm.SOLVER_MGPCG
+    ctx = _ctx(mm, grid, f=f, solver=s, rtol=1e-12, sigma2=2.0)
+    first = 7
+    y, p, phi, st = ctx.solve_state_adjoint(level, coarse, first, count, u)
+    assert st["nonconverged"] == 0 and st["max_relres"] <= 1e-12
+    n = grid[level - coarse]
+    # oracle right-hand side: restrict f + u from the finest grid
+    b = f + u
+    b[0] = b[-1] = 0
+    b[:, 0] = b[:, -1] = 0
+    b[:, :, 0] = b[:, :, -1] = 0
+    nn = nL
+    while nn > n:
+        b = orc.restrict(nn, b)
+        nn = (nn - 1) // 2 + 1
+    yd = inputs.target_sin(n)
+    y = y.cpu().numpy()
+    p = p.cpu().numpy()
+    phi = phi.cpu().numpy()
+    for m in range(count):
+        c = orc.kl_coeffs(0, level, first + m, 4, 2.0)
+        yo, _, rr = orc.solve(n, c, b, rtol=1e-14)
+        po, _, _ = orc.solve(n, c, yo - yd, rtol=1e-14)
+        assert _rel(y[m], yo) <= 1e-10
+        assert _rel(p[m], po) <= 1e-10
+        assert phi[m] == pytest.approx(orc.misfit(n, yo, yd), rel=1e-10)
+    ctx.close()
+
+
+def test_single_level_gradient_cg(mm, orc):
+    """17^3 single level, 64 samples, CG, theta = 1 (shape of the plain
+    single-level workload)."""
+    print("single level gradient", flush=True)
+    n = 17
+    yd = inputs.target_sin(n)
+    u = 30.0 * yd + inputs.random_field(n, 3, 1.0)
+    ctx = _ctx(mm, [n], solver=mm.SOLVER_CG, theta=1.0, alpha=1e-3, rtol=1e-12)
+    g, st = ctx.mlmc_gradient(u, [64], first=[5])
+    pb = orc.make_problem([n], theta=1.0, alpha=1e-3, rtol=1e-14)
+    go, so = orc.mlmc_gradient(pb, None, u, yd, [64], first=[5])
+    assert _rel(g.cpu().numpy(), go) <= 1e-9
+    assert st["J"] == pytest.approx(so["J"], rel=1e-10)
+    assert st["s"] == pytest.approx(so["s"], rel=1e-10)
+    ctx.close()
+
+
+@pytest.mark.parametrize("theta,sigma2", [(1.0, 1.0), (10.0, 2.0), (0.0, 1.0)])
+def test_mlmc_gradient_three_levels(mm, orc, theta, sigma2):
+    print("mlmc gradient", theta, sigma2, flush=True)
+    grid, M = [9, 17, 33], [24, 8, 4]
+    nL = grid[-1]
+    yd = inputs.target_sin(nL)
+    u = inputs.control_xyz(nL) + 20.0 * yd
+    ctx = _ctx(mm, grid, theta=theta, alpha=1e-3, sigma2=sigma2, rtol=1e-12)
+    g, st = ctx.mlmc_gradient(u, M, first=[0, 3, 11])
+    pb = orc.make_problem(grid, theta=theta, alpha=1e-3, sigma2=sigma2, rtol=1e-14)
+    go, so = orc.mlmc_gradient(pb, None, u, yd, M, first=[0, 3, 11])
+    assert _rel(g.cpu().numpy(), go) <= 1e-9
+    assert st["J"] == pytest.approx(so["J"], rel=1e-10)
+    assert st["EY_shifted"] == pytest.approx(so["EY_shifted"], rel=1e-10)
+    for i in range(3):
+        assert st["mean_dY"][i] == pytest.approx(so["mean_dY"][i], rel=1e-8, abs=1e-14)
+        assert st["m2_dX"][i] == pytest.approx(so["m2_dX"][i], rel=1e-8)
+        assert st["norm2_mean_dX"][i] == pytest.approx(so["norm2_mean_dX"][i], rel=1e-8)
+    assert st["truncated"] == so["truncated"]
+    ctx.close()
+
+
+def test_sigma_zero_closed_form(mm):
+    """a = 1, u = c y_d, f = 0: the estimate telescopes to the finest grid and
+    equals ((c/lam1 - 1)/lam1 + alpha c) y_d."""
+    grid, M = [9, 17, 33], [6, 3, 2]
+    nL = grid[-1]
+    yd = inputs.target_sin(nL)
+    cval, alpha = 40.0, 1e-3
+    h = 1.0 / (nL - 1)
+    lam = 12.0 / h ** 2 * math.sin(math.pi * h / 2) ** 2
+    ctx = _ctx(mm, grid, sigma2=0.0, theta=3.0, alpha=alpha)
+    g, st = ctx.mlmc_gradient(cval * yd, M)
+    gref = ((cval / lam - 1.0) / lam + alpha * cval) * yd
+    assert np.max(np.abs(g.cpu().numpy() - gref)) <= 1e-9 * np.max(np.abs(gref))
+    ctx.close()
+
+
+def test_sgd_steps_match_oracle(mm, orc):
+    """Two projected SGD steps with fresh samples (offsets advance by M)."""
+    import torch
+    grid, M = [9, 17], [8, 4]
+    nL = grid[-1]
+    yd = inputs.target_sin(nL)
+    ctx = _ctx(mm, grid, theta=1.0, alpha=1e-3)
+    u = torch.zeros((nL,) * 3, dtype=torch.float64, device="cuda:0")
+    ctx.set_batch(M)
+    for _ in range(2):
+        st = ctx.step(u, 10.0)
+    pb = orc.make_problem(grid, theta=1.0, alpha=1e-3, rtol=1e-14)
+    uo, _ = orc.sgd(pb, None, np.zeros((nL,) * 3), yd, M, steps=2, tau=10.0)
+    assert _rel(u.cpu().numpy(), uo) <= 1e-9
+    assert st["offset"] == [16, 8]
+    ctx.close()
+
+
+def test_errors(mm):
+    import torch
+    n = 17
+    yd = inputs.target_sin(n)
+    with pytest.raises(mm.MlsgdError):
+        mm.Context(mm.Problem(grid_n=[9, 18], y_d=inputs.target_sin(18)))
+    with pytest.raises(mm.MlsgdError):
+        mm.Context(mm.Problem(grid_n=[n], y_d=yd, theta=-1.0))
+    ctx = _ctx(mm, [n])
+    u = torch.zeros((n,) * 3, dtype=torch.float64, device="cuda:0")
+    with pytest.raises(mm.MlsgdError) as e:
+        ctx.mlmc_gradient(u, [0])
+    assert e.value.code == mm.MLSGD_EINVAL
+    u[3, 3, 3] = float("nan")
+    with pytest.raises(mm.MlsgdError) as e:
+        ctx.mlmc_gradient(u, [4])
+    assert e.value.code == mm.MLSGD_ENONFINITE
+    u[3, 3, 3] = 0.0
+    ctx2 = _ctx(mm, [n], max_iters=1, solver=mm.SOLVER_CG)
+    with pytest.raises(mm.NotConverged):
+        ctx2.mlmc_gradient(u + 1.0, [4])
+    ctx.close()
+    ctx2.close()
