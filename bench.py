@@ -1,0 +1,273 @@
+"""Benchmark: MLMC gradient estimates/s of the entropic-risk MLSGD hot path on
+one MI355X.
+
+A step is one complete MLMC gradient estimate (draws, batched state solves on
+every level, misfits, batched adjoint solves, max-shifted weights, level
+means, telescoping, gradient) with fresh samples, inputs resident in HBM.
+Headline workload: levels 9^3..129^3 with M = 4096/1024/256/64/16, FP64
+MG-PCG to rtol 1e-12, theta = 1, alpha = 1e-3, u = 0.1 xyz,
+y_d = sin(pi x) sin(pi y) sin(pi z) (synthetic, seed 0).  The mixed-precision
+form (FP32 V-cycles inside the FP64 Krylov iteration, sigma^2 = 2,
+theta = 10, same grids and counts) is reported beside it.
+
+Prints one JSON line.  --gpus N > 1 is not supported (one GPU per run).
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "MLMC gradient estimates/s + state/adjoint solves/s, mixed vs FP64, % HBM peak"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gs_pass_129.json")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="mlmc_129")
+    ap.add_argument("--mixed-workload", default="mlmc_129_mixed")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--quiet", action="store_true")
+    return ap.parse_args()
+
+
+def log(args, *a):
+    if not args.quiet:
+        print(*a, file=sys.stderr, flush=True)
+
+
+def problem_counts(grid, M):
+    """Solves per estimate (state and adjoint counted separately) and the
+    interior unknowns they cover."""
+    solves, unknowns = 0, 0
+    for i, n in enumerate(grid):
+        solves += 2 * M[i]
+        unknowns += 2 * M[i] * (n - 2) ** 3
+        if i > 0:
+            solves += 2 * M[i]
+            unknowns += 2 * M[i] * (grid[i - 1] - 2) ** 3
+    return solves, unknowns
+
+
+def make_ctx(m, w, dev):
+    prec = {"fp64": m.FP64, "mixed": m.MIXED_FP32, "mixed_bf16": m.MIXED_BF16}[w.precision]
+    solver = m.SOLVER_CG if w.solver == "cg" else m.SOLVER_MGPCG
+    pb = m.Problem(grid_n=w.grid_n, y_d=w.y_d(), f=w.f() if w.f_value else None, seed=w.seed,
+                   K=w.K, sigma2=w.sigma2, theta=w.theta, alpha=w.alpha, precision=prec,
+                   solver=solver, rtol=w.rtol, max_iters=200)
+    return m.Context(pb, device=dev)
+
+
+def run(args, m, w, dev, steps, warmup, timing_n=None):
+    """Warm up, then time `steps` estimates with fresh samples each."""
+    import torch
+    ctx = make_ctx(m, w, dev)
+    u = torch.as_tensor(w.u0(), device=dev).contiguous()
+    L = len(w.grid_n)
+    off = [0] * L
+    for k in range(warmup):
+        g, st = ctx.mlmc_gradient(u, w.M, first=off)
+        off = [o + mm for o, mm in zip(off, w.M)]
+        log(args, f"  warmup {k}: {st['ms_total']:.2f} ms, iters "
+                  f"{st['iters_state']}/{st['iters_adjoint']}")
+    if timing_n:
+        ctx.kernel_timing(1, timing_n)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = []
+    for k in range(steps):
+        g, st = ctx.mlmc_gradient(u, w.M, first=off)
+        off = [o + mm for o, mm in zip(off, w.M)]
+        stats.append(st)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    tm = ctx.kernel_timing(0, 0) if timing_n else None
+    ctx.close()
+    return {"dt": dt, "stats": stats, "timing": tm, "grad": g}
+
+
+def same_samples_error(m, w_fast, w_ref, dev):
+    """Relative L2 difference of one estimate of w_fast against the FP64 GPU
+    path on identical samples and problem data (the FP64 path itself matches
+    the oracle in the parity tests)."""
+    import dataclasses
+    import torch
+    w64 = dataclasses.replace(w_ref, precision="fp64")
+    u = torch.as_tensor(w_fast.u0(), device=dev).contiguous()
+    c1 = make_ctx(m, w_fast, dev)
+    g1, _ = c1.mlmc_gradient(u, w_fast.M)
+    c1.close()
+    c2 = make_ctx(m, w64, dev)
+    g2, _ = c2.mlmc_gradient(u, w64.M)
+    c2.close()
+    return float(torch.linalg.norm(g1 - g2) / torch.linalg.norm(g2))
+
+
+def cpu_baseline(w, threads):
+    """The oracle timed on the host cores: per level i, P pairs of level i
+    (fine + coarse state and adjoint solves) run on P threads; the per-pair
+    throughput of every level is extrapolated to the workload's M."""
+    import oracle
+    from paper_2606_09291_amd import inputs
+    P = threads
+    per_pair = []
+    for i in range(len(w.grid_n)):
+        grid = w.grid_n[:i + 1]
+        nL = grid[-1]
+        yd = inputs.target_sin(nL)
+        u = inputs.control_xyz(nL)
+        pb = oracle.make_problem(grid, K=w.K, sigma2=w.sigma2, theta=w.theta, alpha=w.alpha,
+                                 rtol=w.rtol, nthreads=P)
+        M = [1] * i + [P]
+        t = time.perf_counter()
+        oracle.mlmc_gradient(pb, None, u, yd, M)
+        per_pair.append((time.perf_counter() - t) / P)
+    est = sum(mm * tp for mm, tp in zip(w.M, per_pair))
+    return {"value": 1.0 / est, "unit": "gradient estimates/s", "cores": P, "kind": "oracle",
+            "sample": (f"per level i, {P} pairs of level i (plus one pair of each lower level) "
+                       f"on {P} threads; per-pair wall times {[round(x, 4) for x in per_pair]} s "
+                       f"extrapolated to M={list(w.M)}"),
+            "seconds_per_estimate": est}
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in ("kernels.hip", "runtime.hip", "internal.h"):
+        with open(os.path.join(ROOT, "paper_2606_09291_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(launch_points):
+    """HBM bytes per launch of the timed kernel from the committed counter
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factor), or
+    None when the kernels changed since the counters were taken."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_hash") != source_hash():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def copy_calibration(args):
+    import torch
+    n = 1 << 27  # 128 Mi doubles = 1 GiB each way
+    a = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    b = torch.empty_like(a)
+    for _ in range(5):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": n * 8, "copy_bytes_written": n * 8, "launches": 5}))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args)
+        return
+    import torch
+    import paper_2606_09291_amd as m
+    from paper_2606_09291_amd import inputs
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    dev = torch.device("cuda:0")
+    w = inputs.WORKLOADS[args.workload]
+    nfin = w.grid_n[-1]
+    log(args, f"workload {args.workload}: grids {w.grid_n} M {w.M} ({w.precision})")
+    r = run(args, m, w, dev, args.steps, args.warmup, timing_n=nfin)
+    dt = r["dt"]
+    stats = r["stats"]
+    log(args, f"timed {args.steps} steps in {dt:.3f} s")
+    solves, unknowns = problem_counts(w.grid_n, w.M)
+    value = args.steps / dt
+    tm = r["timing"]
+    avg_ms = tm["ms"] / max(tm["launches"], 1)
+    bytes_per_launch = tm["bytes"] / max(tm["launches"], 1)
+    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "gradient estimates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if w.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "grids": w.grid_n, "M": w.M, "K": w.K,
+                   "sigma2": w.sigma2, "theta": w.theta, "alpha": w.alpha, "rtol": w.rtol,
+                   "solver": w.solver, "precision": w.precision},
+        "solves_per_s": solves * value,
+        "unknown_solves_per_s": unknowns * value,
+        "iters_state": max(s["iters_state"] for s in stats),
+        "iters_adjoint": max(s["iters_adjoint"] for s in stats),
+        "max_relres": max(s["max_relres"] for s in stats),
+        "roofline": {
+            "kernel": f"red-black smoothing pass (k_march OP_GS) on the {nfin}^3 rows",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": traffic_for(bytes_per_launch),
+            "avg_launch_ms": avg_ms,
+            "launches": tm["launches"],
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+        },
+    }
+    if not args.no_mixed:
+        wm = inputs.WORKLOADS[args.mixed_workload]
+        log(args, f"mixed workload {args.mixed_workload} ({wm.precision})")
+        rm = run(args, m, wm, dev, args.steps, args.warmup, timing_n=wm.grid_n[-1])
+        vm = args.steps / rm["dt"]
+        tmm = rm["timing"]
+        avg_m = tmm["ms"] / max(tmm["launches"], 1)
+        bpl_m = tmm["bytes"] / max(tmm["launches"], 1)
+        sm, um = problem_counts(wm.grid_n, wm.M)
+        err = same_samples_error(m, wm, wm, dev)
+        out["mixed"] = {
+            "workload": wm.name,
+            "value": vm,
+            "unit": "gradient estimates/s",
+            "ms_per_step": 1e3 * rm["dt"] / args.steps,
+            "solves_per_s": sm * vm,
+            "unknown_solves_per_s": um * vm,
+            "iters_state": max(s["iters_state"] for s in rm["stats"]),
+            "iters_adjoint": max(s["iters_adjoint"] for s in rm["stats"]),
+            "grad_rel_err_vs_fp64_same_samples": err,
+            "smoothing_pass_GBps": bpl_m / (avg_m * 1e-3) / 1e9,
+            "smoothing_pass_frac": bpl_m / (avg_m * 1e-3) / 1e9 / HBM_PEAK_GBS,
+            "speedup_vs_fp64_batched": vm / value,
+        }
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        log(args, f"cpu baseline with {threads} threads")
+        out["cpu_baseline"] = cpu_baseline(w, threads)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -190,6 +190,16 @@ int mlsgd_set_batch(mlsgd_ctx* ctx, int L, const int64_t* M,
 int mlsgd_step(mlsgd_ctx* ctx, double* u_inout, double tau, int adapt,
                mlsgd_step_stats* st);
 
+/* Event timing of the red-black smoothing passes on grid size n (the
+ * dominant kernel of the solves), for roofline figures.  Each launch on that
+ * grid is bracketed by HIP events on the context's stream.  The call first
+ * returns the totals accumulated so far (host outputs, nullable: summed
+ * milliseconds, launch count, algorithmic bytes = interior points x bytes the
+ * pass must move), then, if enable >= 0, resets them and switches timing on
+ * (enable = 1, for grid n) or off (enable = 0); enable < 0 only reads. */
+int mlsgd_kernel_timing(mlsgd_ctx* ctx, int enable, int n, double* ms_total,
+                        int64_t* launches, double* bytes);
+
 #ifdef __cplusplus
 }
 #endif

@@ -22,7 +22,7 @@ SOLVER_CG, SOLVER_MGPCG = 0, 1
 EXPORTS = [
     "mlsgd_create", "mlsgd_destroy", "mlsgd_last_error", "mlsgd_sample_fields",
     "mlsgd_philox_words", "mlsgd_solve_state_adjoint", "mlsgd_mlmc_gradient",
-    "mlsgd_mlmc_objective", "mlsgd_set_batch", "mlsgd_step",
+    "mlsgd_mlmc_objective", "mlsgd_set_batch", "mlsgd_step", "mlsgd_kernel_timing",
 ]
 
 
@@ -117,6 +117,8 @@ def lib():
                                        P(_GradStats)]
     L.mlsgd_set_batch.argtypes = [vp, i32, P(i64), P(i64)]
     L.mlsgd_step.argtypes = [vp, vp, ctypes.c_double, i32, P(_StepStats)]
+    L.mlsgd_kernel_timing.argtypes = [vp, i32, i32, P(ctypes.c_double), P(i64),
+                                      P(ctypes.c_double)]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -298,6 +300,18 @@ class Context:
         return {"grad": st.grad.as_dict(L), "M_next": list(st.M_next)[:L],
                 "offset": list(st.offset)[:L], "err_sam": st.err_sam, "err_num": st.err_num,
                 "eps": st.eps}
+
+
+    def kernel_timing(self, enable, n=0):
+        """Read the smoothing-pass event totals, then (enable >= 0) reset and
+        switch timing on for grid n (1) or off (0)."""
+        ms = ctypes.c_double(0.0)
+        cnt = ctypes.c_int64(0)
+        by = ctypes.c_double(0.0)
+        rc = self.lib.mlsgd_kernel_timing(self._h, int(enable), int(n), ctypes.byref(ms),
+                                          ctypes.byref(cnt), ctypes.byref(by))
+        self._check(rc)
+        return {"ms": ms.value, "launches": cnt.value, "bytes": by.value}
 
 
 def philox_words(seed, level, sample, tag, nblocks, device="cuda:0"):

@@ -45,17 +45,21 @@ struct GridArgs {
   const double* cosT;   // [K][n] cos(pi k x_i)
   const CgScal* scal;   // per problem; inactive problems are skipped (nullable)
   double ih2;           // 1/h^2
+  const void* cache;    // [problem][n^3] cached 1/a of the compute type, or null
 };
 
 // ---- stencil kernels (marching LDS tiles, coefficient regenerated) ----
 template <typename T>
 void march_resid(const GridArgs& g, const T* x, const T* b, T* r, hipStream_t s);
-template <typename T>
-void march_matvec(const GridArgs& g, const T* z, const T* p_old, T* p_new, T* q,
+template <typename T, typename TZ>
+void march_matvec(const GridArgs& g, const TZ* z, const T* p_old, T* p_new, T* q,
                   const int* poff, double* partial, hipStream_t s);
 template <typename T>
 void march_gs(const GridArgs& g, T* x, const T* b, int color, int x_zero,
-              const int* poff, double* partial, int top_begin, hipStream_t s);
+              const int* poff, double* partial, int top_begin, double omega, hipStream_t s);
+template <typename T>
+void coef_cache(int n, int rows, const double* coef, int K, const double* cosT, T* out,
+                hipStream_t s);
 
 // ---- batched grid transfers (rows of one grid size) ----
 template <typename T>
@@ -77,10 +81,12 @@ void cos_table(int n, int K, double* out, hipStream_t s);
 // ---- elementwise over the rows of one group (full n^3 per row) ----
 void rows_broadcast(int n, int rows, const double* src, double* dst, hipStream_t s);
 void rows_zero(long long count, double* x, hipStream_t s);
+void to_f32(long long count, const double* x, float* y, hipStream_t s);
 void group_dot(const GridArgs& g, const double* a, const double* b, const int* poff,
                double* partial, hipStream_t s);
 void group_update(const GridArgs& g, double* x, const double* p, double* r,
-                  const double* q, const int* poff, double* partial, hipStream_t s);
+                  const double* q, const int* poff, double* partial, float* r32,
+                  hipStream_t s);
 void group_misfit(const GridArgs& g, double* y, const double* yd, double* b_rows,
                   const int* poff, double* partial, hipStream_t s);
 

@@ -14,6 +14,7 @@
 
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 
 namespace mlsgd {
 
@@ -79,7 +80,11 @@ Tiling make_tiling(int n) {
   } else if (m <= 32) {
     t.TY = 8; t.TZ = 32;
   } else {
-    t.TY = 4; t.TZ = 64;
+    static const int ty64 = [] {
+      const char* e = getenv("MLSGD_TY64");
+      return (e && atoi(e) == 4) ? 4 : 8;
+    }();
+    t.TY = ty64; t.TZ = 64;
   }
   t.nty = cdiv(m, t.TY);
   t.ntz = cdiv(m, t.TZ);
@@ -96,29 +101,31 @@ Tiling make_tiling(int n) {
 // walks the x planes of its chunk.  Each thread keeps its own column's
 // values and reciprocal coefficients at x-1, x, x+1 in registers; the
 // current plane (patch plus a one-point halo in y and z) sits in LDS,
-// double-buffered so one barrier per plane suffices.  The coefficient of a
-// vertex is computed once per plane from the separable KL sum: per (y, z)
-// column S[k1] = sum_{k2,k3} c[k1,k2,k3] cos(pi k2 y) cos(pi k3 z) is formed
-// once, after which each plane costs K FMAs and one exp.
+// double-buffered so one barrier per plane suffices.
+//
+// Coefficient: either regenerated in the sweep from the separable KL sum --
+// per (y, z) column S[k1] = sum_{k2,k3} c[k1,k2,k3] cos(pi k2 y) cos(pi k3 z)
+// is formed once, after which each plane costs K FMAs and one exp -- or read
+// from the per-estimate cache of 1/a written by k_coef_cache (CACHED).
 //
 // OP_RESID : r = b - A x
 // OP_MATVEC: p = z + beta p (on the fly, halo included), q = A p, <p, q>
-// OP_GS    : one colour of a red-black Gauss-Seidel sweep in place
-//            (x_zero: start from x = 0; partial: <b, x> after the sweep)
+// OP_GS    : one colour of a red-black Gauss-Seidel sweep in place with
+//            relaxation omega (x_zero: start from x = 0; partial: <b, x>)
 // ---------------------------------------------------------------------------
 enum MarchOp { OP_RESID = 0, OP_MATVEC = 1, OP_GS = 2 };
 
-template <typename T, int TY, int TZ, int OP>
+template <typename T, typename TI, int TY, int TZ, int OP, bool CACHED>
 __global__ void __launch_bounds__(TY* TZ)
-    k_march(GridArgs g, const T* in, const T* in2, const T* rhs, T* out, T* out2,
+    k_march(GridArgs g, const TI* in, const T* in2, const T* rhs, T* out, T* out2,
             const int* __restrict__ poff, double* __restrict__ partial, int color,
-            int x_zero, int top_begin) {
+            int x_zero, int top_begin, T omega) {
   constexpr int NT = TY * TZ;
   constexpr int PZ = TZ + 2;
   constexpr int PLANE = (TY + 2) * PZ;
   __shared__ T sx[2][PLANE];
   __shared__ T sb[2][PLANE];
-  __shared__ double sc[KMAX * KMAX * KMAX];
+  __shared__ double sc[CACHED ? 1 : KMAX * KMAX * KMAX];
   __shared__ double sred[NT / 64];
 
   const int n = g.n;
@@ -135,11 +142,14 @@ __global__ void __launch_bounds__(TY* TZ)
   if (g.scal && !g.scal[prob].active) return;  // uniform per workgroup
 
   const int K = g.K;
-  const int K3 = K * K * K;
-  for (int j = threadIdx.x; j < K3; j += NT) sc[j] = g.coef[(size_t)prob * K3 + j];
-  __syncthreads();
+  if (!CACHED) {
+    const int K3 = K * K * K;
+    for (int j = threadIdx.x; j < K3; j += NT) sc[j] = g.coef[(size_t)prob * K3 + j];
+    __syncthreads();
+  }
 
   const size_t base = (size_t)row * (size_t)g.stride;
+  const T* __restrict__ cache = (const T*)g.cache + (size_t)prob * (size_t)g.stride;
   const double* __restrict__ cosT = g.cosT;
   const int tid = threadIdx.x;
   const int ly = tid / TZ, lz = tid - (tid / TZ) * TZ;
@@ -172,8 +182,8 @@ __global__ void __launch_bounds__(TY* TZ)
     if (x_zero) return T(0);
     if (ix <= 0 || ix >= n - 1 || jy <= 0 || jy >= n - 1 || jz <= 0 || jz >= n - 1) return T(0);
     const size_t idx = base + ((size_t)ix * n + jy) * n + jz;
-    if (OP == OP_MATVEC) return in[idx] + beta * in2[idx];
-    return in[idx];
+    if (OP == OP_MATVEC) return (T)in[idx] + beta * in2[idx];
+    return (T)in[idx];
   };
 
   auto compS = [&](int jy, int jz, T* S) {
@@ -201,8 +211,9 @@ __global__ void __launch_bounds__(TY* TZ)
       S[k1] = acc;
     }
   };
-  // reciprocal coefficient 1/a = exp(-log a) on plane ix of a column with sums S
-  auto coefb = [&](int ix, const T* S) -> T {
+  // reciprocal coefficient 1/a = exp(-log a) at (ix, jy, jz)
+  auto coefb = [&](int ix, int jy, int jz, const T* S) -> T {
+    if (CACHED) return cache[((size_t)ix * n + jy) * n + jz];
     T l = T(0);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
@@ -216,8 +227,10 @@ __global__ void __launch_bounds__(TY* TZ)
     Sm[k] = T(0);
     Sh[k] = T(0);
   }
-  if (inside) compS(iy, iz, Sm);
-  if (has_halo) compS(hy, hz, Sh);
+  if (!CACHED) {
+    if (inside) compS(iy, iz, Sm);
+    if (has_halo) compS(hy, hz, Sh);
+  }
 
   const int x0 = 1 + xc * g.t.xchunk;
   const int x1 = min(x0 + g.t.xchunk, n - 1);
@@ -227,14 +240,14 @@ __global__ void __launch_bounds__(TY* TZ)
   if (inside) {
     xm = ld(x0 - 1, iy, iz);
     xcur = ld(x0, iy, iz);
-    bm = coefb(x0 - 1, Sm);
-    bc = coefb(x0, Sm);
+    bm = coefb(x0 - 1, iy, iz, Sm);
+    bc = coefb(x0, iy, iz, Sm);
   }
   T fxm = face(bm, bc);
   T hcur = T(0), hbc = T(1);
   if (has_halo) {
     hcur = ld(x0, hy, hz);
-    hbc = coefb(x0, Sh);
+    hbc = coefb(x0, hy, hz, Sh);
   }
   double dot = 0.0;
   const int cidx = (ly + 1) * PZ + (lz + 1);
@@ -243,8 +256,13 @@ __global__ void __launch_bounds__(TY* TZ)
   for (int ix = x0; ix < x1; ++ix) {
     const int buf = ix & 1;
     // prefetch the next plane of the own column and of the halo slot
-    T xp = inside ? ld(ix + 1, iy, iz) : T(0);
-    T hnext = (has_halo && ix + 1 < x1) ? ld(ix + 1, hy, hz) : T(0);
+    const T xp = inside ? ld(ix + 1, iy, iz) : T(0);
+    const T hnext = (has_halo && ix + 1 < x1) ? ld(ix + 1, hy, hz) : T(0);
+    T bp = T(1), hbn = T(1);
+    if (CACHED) {
+      if (inside) bp = coefb(ix + 1, iy, iz, Sm);
+      if (has_halo && ix + 1 < x1) hbn = coefb(ix + 1, hy, hz, Sh);
+    }
     T bv = T(0);
     if (OP == OP_RESID || OP == OP_GS) {
       if (own) bv = rhs[base + ((size_t)ix * n + iy) * n + iz];
@@ -256,8 +274,8 @@ __global__ void __launch_bounds__(TY* TZ)
       sb[buf][hidx] = has_halo ? hbc : T(1);
     }
     __syncthreads();
-    T bp = inside ? coefb(ix + 1, Sm) : T(1);
-    T fxp = face(bc, bp);
+    if (!CACHED) bp = inside ? coefb(ix + 1, iy, iz, Sm) : T(1);
+    const T fxp = face(bc, bp);
     if (own) {
       const T xym = sx[buf][cidx - PZ], xyp = sx[buf][cidx + PZ];
       const T xzm = sx[buf][cidx - 1], xzp = sx[buf][cidx + 1];
@@ -275,15 +293,17 @@ __global__ void __launch_bounds__(TY* TZ)
         dot += (double)xcur * (double)q;
       } else {  // OP_GS
         T val = xcur;
-        if (((ix + iy + iz) & 1) == color) {
-          val = (bv + ih2 * off) * drcp(ih2 * diag);
+        const bool upd = ((ix + iy + iz) & 1) == color;
+        if (upd) {
+          const T gs = (bv + ih2 * off) * drcp(ih2 * diag);
+          val = xcur + omega * (gs - xcur);
           out[idx] = val;
         } else if (x_zero) {
           val = T(0);
           out[idx] = val;
         }
         if (partial) {
-          const T bb = (((ix + iy + iz) & 1) == color) ? bv : rhs[idx];
+          const T bb = upd ? bv : rhs[idx];
           dot += (double)bb * (double)val;
         }
       }
@@ -295,7 +315,7 @@ __global__ void __launch_bounds__(TY* TZ)
     fxm = fxp;
     if (has_halo && ix + 1 < x1) {
       hcur = hnext;
-      hbc = coefb(ix + 1, Sh);
+      hbc = CACHED ? hbn : coefb(ix + 1, hy, hz, Sh);
     }
   }
   const bool want = (OP == OP_MATVEC) || (OP == OP_GS && partial != nullptr && prob >= top_begin);
@@ -305,58 +325,96 @@ __global__ void __launch_bounds__(TY* TZ)
   }
 }
 
-template <typename T, int OP>
-static void launch_march(const GridArgs& g, const T* in, const T* in2, const T* rhs, T* out,
-                         T* out2, const int* poff, double* partial, int color, int x_zero,
-                         int top_begin, hipStream_t s) {
-  if (g.rows <= 0) return;
+template <typename T, typename TI, int OP, bool CACHED>
+static void launch_march2(const GridArgs& g, const TI* in, const T* in2, const T* rhs, T* out,
+                          T* out2, const int* poff, double* partial, int color, int x_zero,
+                          int top_begin, T omega, hipStream_t s) {
   const int nblk = g.rows * g.t.tiles_per_row;
-  switch (g.t.TZ) {
-    case 8:
-      hipLaunchKernelGGL((k_march<T, 8, 8, OP>), dim3(nblk), dim3(64), 0, s, g, in, in2, rhs,
-                         out, out2, poff, partial, color, x_zero, top_begin);
-      break;
-    case 16:
-      hipLaunchKernelGGL((k_march<T, 16, 16, OP>), dim3(nblk), dim3(256), 0, s, g, in, in2,
-                         rhs, out, out2, poff, partial, color, x_zero, top_begin);
-      break;
-    case 32:
-      hipLaunchKernelGGL((k_march<T, 8, 32, OP>), dim3(nblk), dim3(256), 0, s, g, in, in2,
-                         rhs, out, out2, poff, partial, color, x_zero, top_begin);
-      break;
-    default:
-      hipLaunchKernelGGL((k_march<T, 4, 64, OP>), dim3(nblk), dim3(256), 0, s, g, in, in2,
-                         rhs, out, out2, poff, partial, color, x_zero, top_begin);
-      break;
+#define MLSGD_LAUNCH(TY_, TZ_)                                                              \
+  hipLaunchKernelGGL((k_march<T, TI, TY_, TZ_, OP, CACHED>), dim3(nblk), dim3(TY_ * TZ_), 0, s, \
+                     g, in, in2, rhs, out, out2, poff, partial, color, x_zero, top_begin, omega)
+  if (g.t.TZ == 8) {
+    MLSGD_LAUNCH(8, 8);
+  } else if (g.t.TZ == 16) {
+    MLSGD_LAUNCH(16, 16);
+  } else if (g.t.TZ == 32) {
+    MLSGD_LAUNCH(8, 32);
+  } else if (g.t.TY == 8) {
+    MLSGD_LAUNCH(8, 64);
+  } else {
+    MLSGD_LAUNCH(4, 64);
   }
+#undef MLSGD_LAUNCH
+}
+
+template <typename T, typename TI, int OP>
+static void launch_march(const GridArgs& g, const TI* in, const T* in2, const T* rhs, T* out,
+                         T* out2, const int* poff, double* partial, int color, int x_zero,
+                         int top_begin, T omega, hipStream_t s) {
+  if (g.rows <= 0) return;
+  if (g.cache)
+    launch_march2<T, TI, OP, true>(g, in, in2, rhs, out, out2, poff, partial, color, x_zero,
+                                   top_begin, omega, s);
+  else
+    launch_march2<T, TI, OP, false>(g, in, in2, rhs, out, out2, poff, partial, color, x_zero,
+                                    top_begin, omega, s);
 }
 
 template <typename T>
 void march_resid(const GridArgs& g, const T* x, const T* b, T* r, hipStream_t s) {
-  launch_march<T, OP_RESID>(g, x, nullptr, b, r, nullptr, nullptr, nullptr, 0, 0, 0, s);
+  launch_march<T, T, OP_RESID>(g, x, nullptr, b, r, nullptr, nullptr, nullptr, 0, 0, 0, T(1), s);
 }
-template <typename T>
-void march_matvec(const GridArgs& g, const T* z, const T* p_old, T* p_new, T* q,
+template <typename T, typename TZ>
+void march_matvec(const GridArgs& g, const TZ* z, const T* p_old, T* p_new, T* q,
                   const int* poff, double* partial, hipStream_t s) {
-  launch_march<T, OP_MATVEC>(g, z, p_old, nullptr, q, p_new, poff, partial, 0, 0, 0, s);
+  launch_march<T, TZ, OP_MATVEC>(g, z, p_old, nullptr, q, p_new, poff, partial, 0, 0, 0, T(1), s);
 }
 template <typename T>
 void march_gs(const GridArgs& g, T* x, const T* b, int color, int x_zero, const int* poff,
-              double* partial, int top_begin, hipStream_t s) {
-  launch_march<T, OP_GS>(g, x, nullptr, b, x, nullptr, poff, partial, color, x_zero, top_begin,
-                         s);
+              double* partial, int top_begin, double omega, hipStream_t s) {
+  launch_march<T, T, OP_GS>(g, x, nullptr, b, x, nullptr, poff, partial, color, x_zero, top_begin,
+                            (T)omega, s);
 }
 template void march_resid<double>(const GridArgs&, const double*, const double*, double*,
                                   hipStream_t);
 template void march_resid<float>(const GridArgs&, const float*, const float*, float*,
                                  hipStream_t);
-template void march_matvec<double>(const GridArgs&, const double*, const double*, double*,
-                                   double*, const int*, double*, hipStream_t);
+template void march_matvec<double, double>(const GridArgs&, const double*, const double*,
+                                           double*, double*, const int*, double*, hipStream_t);
+template void march_matvec<double, float>(const GridArgs&, const float*, const double*, double*,
+                                          double*, const int*, double*, hipStream_t);
 template void march_gs<double>(const GridArgs&, double*, const double*, int, int, const int*,
-                               double*, int, hipStream_t);
+                               double*, int, double, hipStream_t);
 template void march_gs<float>(const GridArgs&, float*, const float*, int, int, const int*,
-                              double*, int, hipStream_t);
+                              double*, int, double, hipStream_t);
 
+// Per-estimate cache of the reciprocal coefficient 1/a = exp(-log a) at every
+// vertex of every row of one grid size (the KL sum written out separably).
+template <typename T>
+__global__ void k_coef_cache(int n, int rows, const double* __restrict__ coef, int K,
+                             const double* __restrict__ cosT, T* __restrict__ out) {
+  const long long per = (long long)n * n * n;
+  const long long total = per * rows;
+  const int K3 = K * K * K;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int row = (int)(i / per);
+    const long long v = i - (long long)row * per;
+    const int ix = (int)(v / ((long long)n * n)), iy = (int)((v / n) % n), iz = (int)(v % n);
+    const double* c = coef + (size_t)row * K3;
+    double l = 0.0;
+    for (int k1 = 0; k1 < K; ++k1) {
+      double a1 = 0.0;
+      for (int k2 = 0; k2 < K; ++k2) {
+        double a2 = 0.0;
+        for (int k3 = 0; k3 < K; ++k3) a2 += c[(k1 * K + k2) * K + k3] * cosT[k3 * n + iz];
+        a1 += a2 * cosT[k2 * n + iy];
+      }
+      l += a1 * cosT[k1 * n + ix];
+    }
+    out[i] = (T)exp(-l);
+  }
+}
 // ---------------------------------------------------------------------------
 // Batched grid transfers.  Full weighting R = P^T / 8 (weights 1/4, 1/2, 1/4
 // per axis) from fine interior to coarse interior, and trilinear
@@ -437,6 +495,19 @@ static int grid_for(long long total, int bs) {
   if (b < 1) b = 1;
   return (int)b;
 }
+
+template <typename T>
+void coef_cache(int n, int rows, const double* coef, int K, const double* cosT, T* out,
+                hipStream_t s) {
+  if (rows <= 0) return;
+  const long long total = (long long)n * n * n * rows;
+  hipLaunchKernelGGL(k_coef_cache<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, n, rows, coef,
+                     K, cosT, out);
+}
+template void coef_cache<double>(int, int, const double*, int, const double*, double*,
+                                 hipStream_t);
+template void coef_cache<float>(int, int, const double*, int, const double*, float*,
+                                hipStream_t);
 
 template <typename T>
 void restrict_rows(int nf, int rows, int row0, const CgScal* scal, const T* fine, T* coarse,
@@ -604,6 +675,15 @@ void rows_broadcast(int n, int rows, const double* src, double* dst, hipStream_t
   hipLaunchKernelGGL(k_rows_broadcast, dim3(grid_for(total, 256)), dim3(256), 0, s, per, total,
                      src, dst);
 }
+__global__ void k_to_f32(long long count, const double* __restrict__ x, float* __restrict__ y) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (long long)gridDim.x * blockDim.x)
+    y[i] = (float)x[i];
+}
+void to_f32(long long count, const double* x, float* y, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_to_f32, dim3(grid_for(count, 256)), dim3(256), 0, s, count, x, y);
+}
 __global__ void k_zero(long long count, double* x) {
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (long long)gridDim.x * blockDim.x)
@@ -619,7 +699,7 @@ enum GroupOp { G_DOT = 0, G_UPDATE = 1, G_MISFIT = 2 };
 template <int OP>
 __global__ void __launch_bounds__(256)
     k_group(GridArgs g, double* a, const double* b, double* c, const double* d,
-            const int* __restrict__ poff, double* __restrict__ partial) {
+            const int* __restrict__ poff, double* __restrict__ partial, float* cf) {
   __shared__ double sred[4];
   const int tpr = g.t.tiles_per_row;
   const int row = blockIdx.x / tpr;
@@ -641,6 +721,7 @@ __global__ void __launch_bounds__(256)
       a[base + i] += al * b[base + i];
       const double r = c[base + i] - al * d[base + i];
       c[base + i] = r;
+      if (cf) cf[base + i] = (float)r;
       acc += r * r;
     }
   } else {  // G_MISFIT: a = y (reset to 0 afterwards), b = y_d (shared), c = adjoint rhs rows
@@ -661,19 +742,19 @@ void group_dot(const GridArgs& g, const double* a, const double* b, const int* p
                double* partial, hipStream_t s) {
   if (g.rows <= 0) return;
   hipLaunchKernelGGL(k_group<G_DOT>, dim3(g.rows * g.t.tiles_per_row), dim3(256), 0, s, g,
-                     (double*)a, b, nullptr, nullptr, poff, partial);
+                     (double*)a, b, nullptr, nullptr, poff, partial, nullptr);
 }
 void group_update(const GridArgs& g, double* x, const double* p, double* r, const double* q,
-                  const int* poff, double* partial, hipStream_t s) {
+                  const int* poff, double* partial, float* r32, hipStream_t s) {
   if (g.rows <= 0) return;
   hipLaunchKernelGGL(k_group<G_UPDATE>, dim3(g.rows * g.t.tiles_per_row), dim3(256), 0, s, g,
-                     x, p, r, q, poff, partial);
+                     x, p, r, q, poff, partial, r32);
 }
 void group_misfit(const GridArgs& g, double* y, const double* yd, double* b_rows,
                   const int* poff, double* partial, hipStream_t s) {
   if (g.rows <= 0) return;
   hipLaunchKernelGGL(k_group<G_MISFIT>, dim3(g.rows * g.t.tiles_per_row), dim3(256), 0, s, g,
-                     y, yd, b_rows, nullptr, poff, partial);
+                     y, yd, b_rows, nullptr, poff, partial, nullptr);
 }
 
 // ---------------------------------------------------------------------------

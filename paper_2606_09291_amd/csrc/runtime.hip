@@ -16,6 +16,7 @@
 #include <functional>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -57,7 +58,10 @@ static inline size_t cube(int n) { return (size_t)n * n * n; }
 struct SizeLvl {
   int n = 0, rows = 0, top_begin = 0;
   Tiling t{};
-  double *X = nullptr, *B = nullptr, *R = nullptr;
+  double *X = nullptr, *B = nullptr, *R = nullptr;  // FP64 multigrid rows (B: Krylov r on top rows)
+  double* C = nullptr;                              // FP64 cache of 1/a (null: regenerate)
+  float *Xf = nullptr, *Bf = nullptr, *Rf = nullptr;  // FP32 multigrid rows (mixed precision)
+  float* Cf = nullptr;                              // FP32 cache of 1/a (null: regenerate)
   const double* cosT = nullptr;
 };
 
@@ -134,6 +138,22 @@ struct mlsgd_ctx {
   int64_t cur_off[MLSGD_MAX_LEVELS] = {0};
   double prev_gnorm = -1.0;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+  // tunables of the solver (defaults from measurement; overridable for tuning)
+  int nu = 2;               // smoothing sweeps before and after the coarse correction
+  double omega = 1.0;       // red-black relaxation weight
+  bool cache64 = true;      // cache 1/a per estimate for FP64 sweeps
+  bool cache32 = true;      // cache 1/a per estimate for FP32 sweeps
+  bool mixed = false;       // FP32 V-cycles inside the FP64 Krylov iteration
+  // event timing of the smoothing passes on one grid size (roofline figures)
+  struct Timing {
+    bool on = false;
+    int n = 0;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
+    size_t used = 0;
+    std::vector<double> bytes;   // algorithmic bytes of each recorded launch
+    double ms = 0.0, total_bytes = 0.0;
+    int64_t launches = 0;
+  } tm;
 };
 
 namespace {
@@ -243,9 +263,17 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks) {
       Carver cv{pass == 0 ? nullptr : (char*)P->arena};
       for (auto& s : P->sizes) {
         const size_t e = (size_t)s.rows * cube(s.n);
-        s.X = cv.take<double>(e);
         s.B = cv.take<double>(e);
-        s.R = cv.take<double>(e);
+        if (!c->mixed) {
+          s.X = cv.take<double>(e);
+          s.R = cv.take<double>(e);
+        } else {
+          s.Xf = cv.take<float>(e);
+          s.Bf = cv.take<float>(e);
+          s.Rf = cv.take<float>(e);
+          if (c->cache32) s.Cf = cv.take<float>(e);
+        }
+        if (c->cache64) s.C = cv.take<double>(e);
       }
       for (auto& g : P->groups) {
         const size_t e = (size_t)g.count * cube(g.n);
@@ -289,6 +317,12 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks) {
                         hipMemcpyHostToDevice, c->stream));
   kl_coeffs(P->d_level, P->d_sample, P->nprob, c->pb.seed, K, c->pb.kl_sigma2, P->d_coef,
             c->stream);
+  // the coefficient is regenerated from the draws once per call for the
+  // cached sweeps (the Krylov matvec and residual always run in FP64)
+  for (auto& sl : P->sizes) {
+    if (sl.C) coef_cache<double>(sl.n, sl.rows, P->d_coef, K, sl.cosT, sl.C, c->stream);
+    if (sl.Cf) coef_cache<float>(sl.n, sl.rows, P->d_coef, K, sl.cosT, sl.Cf, c->stream);
+  }
   HIPCHK(hipGetLastError());
   return P;
 }
@@ -305,6 +339,14 @@ GridArgs args_size(mlsgd_ctx* c, Plan* P, const SizeLvl& s) {
   g.cosT = s.cosT;
   g.scal = P->d_scal;
   g.ih2 = (double)(s.n - 1) * (double)(s.n - 1);
+  g.cache = s.C;
+  return g;
+}
+
+// launch arguments of the FP32 multigrid sweeps on one grid size
+GridArgs args_size32(mlsgd_ctx* c, Plan* P, const SizeLvl& s) {
+  GridArgs g = args_size(c, P, s);
+  g.cache = s.Cf;
   return g;
 }
 
@@ -318,40 +360,128 @@ GridArgs args_group(mlsgd_ctx* c, Plan* P, const Group& gr, bool skip_inactive) 
 
 inline double* rows_of(double* base, const Group& gr) { return base + (size_t)gr.p0 * cube(gr.n); }
 
-// Symmetric V(1,1) cycle for every active problem: z = V(r) with r in the B
-// rows of each problem's top grid and z left in its X rows.  Pre-smoothing
-// is red then black from a zero guess, post-smoothing black then red (so the
-// cycle is a symmetric preconditioner); the last red pass also forms <r, z>
-// for the problems whose top grid it is.  On the 3^3 grid the single unknown
-// is black and the sweep is an exact solve.
+// Symmetric V(nu,nu) cycle for every active problem: z = V(r) with r in the
+// B rows of each problem's top grid and z left in its X rows.  Pre-smoothing
+// sweeps are red then black starting from a zero guess, post-smoothing
+// sweeps black then red (the cycle is a symmetric preconditioner); the last
+// red pass also forms <r, z> for the problems whose top grid it is.  On the
+// 3^3 grid the single unknown is black and one sweep is an exact solve.
+template <typename T>
+struct MgView {
+  T *X, *B, *R;
+};
+template <typename T>
+MgView<T> mg_view(SizeLvl& L);
+template <>
+MgView<double> mg_view<double>(SizeLvl& L) { return {L.X, L.B, L.R}; }
+template <>
+MgView<float> mg_view<float>(SizeLvl& L) { return {L.Xf, L.Bf, L.Rf}; }
+
+// Algorithmic bytes of one red-black pass over `rows` rows of an n^3 grid:
+// x read at every interior point (not when starting from zero), b read and x
+// written at the updated half, x zeroed at the other half on a zero start,
+// the cached coefficient read at every point, b read at the other half when
+// the pass also forms <b, x>.
+template <typename T>
+double gs_pass_bytes(const mlsgd_ctx* c, int n, int rows, bool x_zero, bool cached, bool dot) {
+  const double N = (double)rows * (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
+  const double e = (double)sizeof(T);
+  double b = 0.5 * e + 0.5 * e;          // b and x on the updated half
+  b += x_zero ? 0.5 * e : e;             // x read, or the other half zeroed
+  if (cached) b += e;
+  if (dot) b += 0.5 * e;
+  (void)c;
+  return N * b;
+}
+
+template <typename T>
+void timed_gs(mlsgd_ctx* c, const GridArgs& g, T* x, const T* b, int color, int x_zero,
+              const int* poff, double* partial, int top_begin, double om) {
+  mlsgd_ctx::Timing& tm = c->tm;
+  const bool rec = tm.on && g.n == tm.n && g.rows > 0;
+  if (rec) {
+    if (tm.used == tm.pool.size()) {
+      hipEvent_t a, e;
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&e));
+      tm.pool.push_back({a, e});
+    }
+    HIPCHK(hipEventRecord(tm.pool[tm.used].first, c->stream));
+  }
+  march_gs<T>(g, x, b, color, x_zero, poff, partial, top_begin, om, c->stream);
+  if (rec) {
+    HIPCHK(hipEventRecord(tm.pool[tm.used].second, c->stream));
+    tm.bytes.push_back(gs_pass_bytes<T>(c, g.n, g.rows, x_zero != 0, g.cache != nullptr,
+                                        partial != nullptr));
+    ++tm.used;
+  }
+}
+
+// Fold the recorded event pairs into the totals (the stream is synchronised).
+void timing_collect(mlsgd_ctx* c) {
+  mlsgd_ctx::Timing& tm = c->tm;
+  for (size_t i = 0; i < tm.used; ++i) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, tm.pool[i].first, tm.pool[i].second));
+    tm.ms += ms;
+    tm.total_bytes += tm.bytes[i];
+    ++tm.launches;
+  }
+  tm.used = 0;
+  tm.bytes.clear();
+}
+
+template <typename T>
 void vcycle(mlsgd_ctx* c, Plan* P) {
   hipStream_t s = c->stream;
   const int S = (int)P->sizes.size();
+  const int nu = c->nu;
+  const double om = c->omega;
+  auto args = [&](SizeLvl& L) {
+    return sizeof(T) == 8 ? args_size(c, P, L) : args_size32(c, P, L);
+  };
   for (int k = 0; k < S; ++k) {
     SizeLvl& L = P->sizes[k];
-    GridArgs g = args_size(c, P, L);
+    MgView<T> v = mg_view<T>(L);
+    GridArgs g = args(L);
     if (k == S - 1) {
-      march_gs<double>(g, L.X, L.B, 0, 1, nullptr, nullptr, 0, s);
-      march_gs<double>(g, L.X, L.B, 1, 0, P->d_poff, P->d_partial, L.top_begin, s);
+      timed_gs<T>(c, g, v.X, v.B, 0, 1, nullptr, nullptr, 0, 1.0);
+      timed_gs<T>(c, g, v.X, v.B, 1, 0, P->d_poff, P->d_partial, L.top_begin, 1.0);
       break;
     }
-    march_gs<double>(g, L.X, L.B, 0, 1, nullptr, nullptr, 0, s);
-    march_gs<double>(g, L.X, L.B, 1, 0, nullptr, nullptr, 0, s);
-    march_resid<double>(g, L.X, L.B, L.R, s);
-    restrict_rows<double>(L.n, L.rows, 0, P->d_scal, L.R, P->sizes[k + 1].B, s);
+    for (int sw = 0; sw < nu; ++sw) {
+      timed_gs<T>(c, g, v.X, v.B, 0, sw == 0 ? 1 : 0, nullptr, nullptr, 0, om);
+      timed_gs<T>(c, g, v.X, v.B, 1, 0, nullptr, nullptr, 0, om);
+    }
+    march_resid<T>(g, v.X, v.B, v.R, s);
+    restrict_rows<T>(L.n, L.rows, 0, P->d_scal, v.R, mg_view<T>(P->sizes[k + 1]).B, s);
   }
   for (int k = S - 2; k >= 0; --k) {
     SizeLvl& L = P->sizes[k];
-    GridArgs g = args_size(c, P, L);
-    prolong_add_rows<double>(P->sizes[k + 1].n, L.rows, 0, P->d_scal, P->sizes[k + 1].X, L.X, s);
-    march_gs<double>(g, L.X, L.B, 1, 0, nullptr, nullptr, 0, s);
-    march_gs<double>(g, L.X, L.B, 0, 0, P->d_poff, P->d_partial, L.top_begin, s);
+    MgView<T> v = mg_view<T>(L);
+    GridArgs g = args(L);
+    prolong_add_rows<T>(P->sizes[k + 1].n, L.rows, 0, P->d_scal, mg_view<T>(P->sizes[k + 1]).X,
+                        v.X, s);
+    for (int sw = 0; sw < nu; ++sw) {
+      const bool last = sw == nu - 1;
+      timed_gs<T>(c, g, v.X, v.B, 1, 0, nullptr, nullptr, 0, om);
+      timed_gs<T>(c, g, v.X, v.B, 0, 0, last ? P->d_poff : nullptr, last ? P->d_partial : nullptr,
+                  L.top_begin, om);
+    }
   }
+}
+
+void precondition(mlsgd_ctx* c, Plan* P) {
+  if (c->mixed)
+    vcycle<float>(c, P);
+  else
+    vcycle<double>(c, P);
 }
 
 int read_count(mlsgd_ctx* c) {
   HIPCHK(hipMemcpyAsync(c->h_count, c->d_count, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
+  if (c->tm.used) timing_collect(c);
   return *c->h_count;
 }
 
@@ -370,8 +500,15 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
   cg_scalar(PH_INIT_BB, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
             c->d_count, s);
   for (int restart = 0; restart < 3; ++restart) {
+    if (mg && c->mixed) {
+      for (auto& gr : P->groups) {
+        SizeLvl& L = P->sizes[gr.sl];
+        to_f32((long long)gr.count * cube(gr.n), rows_of(L.B, gr),
+               L.Bf + (size_t)gr.p0 * cube(gr.n), s);
+      }
+    }
     if (mg) {
-      vcycle(c, P);
+      precondition(c, P);
       cg_scalar(PH_RZ0, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
                 c->d_count, s);
     } else {
@@ -382,16 +519,23 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
       for (auto& gr : P->groups) {
         GridArgs g = args_group(c, P, gr, true);
         SizeLvl& L = P->sizes[gr.sl];
-        const double* z = mg ? rows_of(L.X, gr) : rows_of(L.B, gr);
-        march_matvec<double>(g, z, gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q, P->d_poff,
-                             P->d_partial, s);
+        if (mg && c->mixed) {
+          const float* z = L.Xf + (size_t)gr.p0 * cube(gr.n);
+          march_matvec<double, float>(g, z, gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q, P->d_poff,
+                                      P->d_partial, s);
+        } else {
+          const double* z = mg ? rows_of(L.X, gr) : rows_of(L.B, gr);
+          march_matvec<double, double>(g, z, gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q, P->d_poff,
+                                       P->d_partial, s);
+        }
       }
       cg_scalar(PH_ALPHA, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
                 c->d_count, s);
       for (auto& gr : P->groups) {
         GridArgs g = args_group(c, P, gr, true);
+        float* r32 = (mg && c->mixed) ? P->sizes[gr.sl].Bf + (size_t)gr.p0 * cube(gr.n) : nullptr;
         group_update(g, gr.x, gr.p[gr.pcur ^ 1], rows_of(P->sizes[gr.sl].B, gr), gr.q,
-                     P->d_poff, P->d_partial, s);
+                     P->d_poff, P->d_partial, r32, s);
         gr.pcur ^= 1;
       }
       cg_scalar(PH_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
@@ -399,7 +543,7 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
       HIPCHK(hipGetLastError());
       if (read_count(c) == 0) break;
       if (mg) {
-        vcycle(c, P);
+        precondition(c, P);
         cg_scalar(PH_RZ, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
                   c->d_count, s);
       } else {
@@ -757,13 +901,21 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     require(pb->kl_sigma2 >= 0.0 && std::isfinite(pb->kl_sigma2), "kl_sigma2 must be >= 0");
     require(pb->theta >= 0.0 && std::isfinite(pb->theta), "theta must be >= 0");
     require(pb->alpha >= 0.0 && std::isfinite(pb->alpha), "alpha must be >= 0");
-    require(pb->precision == MLSGD_FP64, "this build supports precision MLSGD_FP64");
+    require(pb->precision == MLSGD_FP64 || pb->precision == MLSGD_MIXED_FP32,
+            "precision must be MLSGD_FP64 or MLSGD_MIXED_FP32");
+    require(pb->precision == MLSGD_FP64 || pb->solver == MLSGD_SOLVER_MGPCG,
+            "mixed precision needs the multigrid solver");
     require(pb->solver == MLSGD_SOLVER_CG || pb->solver == MLSGD_SOLVER_MGPCG, "unknown solver");
     require(pb->rtol > 0.0 && pb->rtol < 1.0, "rtol must be in (0, 1)");
     require(pb->max_iters >= 1, "max_iters must be >= 1");
     require(pb->y_d != nullptr, "y_d is null");
     c->pb = *pb;
     c->stream = (hipStream_t)stream;
+    c->mixed = pb->precision == MLSGD_MIXED_FP32;
+    if (const char* e = getenv("MLSGD_NU")) c->nu = std::max(1, atoi(e));
+    if (const char* e = getenv("MLSGD_OMEGA")) c->omega = atof(e);
+    if (const char* e = getenv("MLSGD_CACHE64")) c->cache64 = atoi(e) != 0;
+    if (const char* e = getenv("MLSGD_CACHE32")) c->cache32 = atoi(e) != 0;
     c->nfin = pb->grid_n[pb->n_levels - 1];
     const size_t NF = cube(c->nfin);
     c->d_f = (double*)dalloc(c.get(), sizeof(double) * NF);
@@ -809,10 +961,34 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
   return MLSGD_OK;
 }
 
+int mlsgd_kernel_timing(mlsgd_ctx* c, int enable, int n, double* ms_total, int64_t* launches,
+                        double* bytes) {
+  if (!c) return MLSGD_EINVAL;
+  return guard_impl(c, [&]() -> int {
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (c->tm.used) timing_collect(c);
+    if (ms_total) *ms_total = c->tm.ms;
+    if (launches) *launches = c->tm.launches;
+    if (bytes) *bytes = c->tm.total_bytes;
+    if (enable >= 0) {
+      c->tm.on = enable != 0;
+      c->tm.n = n;
+      c->tm.ms = 0.0;
+      c->tm.total_bytes = 0.0;
+      c->tm.launches = 0;
+    }
+    return MLSGD_OK;
+  });
+}
+
 int mlsgd_destroy(mlsgd_ctx* c) {
   if (!c) return MLSGD_OK;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   (void)hipDeviceSynchronize();
+  for (auto& pr : c->tm.pool) {
+    (void)hipEventDestroy(pr.first);
+    (void)hipEventDestroy(pr.second);
+  }
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->h_epi_out) (void)hipHostFree(c->h_epi_out);
   if (c->h_count) (void)hipHostFree(c->h_count);

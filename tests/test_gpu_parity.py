@@ -190,3 +190,23 @@ def test_errors(mm):
         ctx2.mlmc_gradient(u + 1.0, [4])
     ctx.close()
     ctx2.close()
+
+
+@pytest.mark.parametrize("theta,sigma2", [(1.0, 1.0), (10.0, 2.0)])
+def test_mixed_precision_gradient(mm, orc, theta, sigma2):
+    """FP32 V-cycles inside the FP64 Krylov iteration: the estimate still
+    matches the FP64 oracle (bar 1e-8 relative L2)."""
+    print("mixed gradient", theta, sigma2, flush=True)
+    grid, M = [9, 17, 33], [24, 8, 4]
+    nL = grid[-1]
+    yd = inputs.target_sin(nL)
+    u = inputs.control_xyz(nL) + 20.0 * yd
+    ctx = _ctx(mm, grid, theta=theta, alpha=1e-3, sigma2=sigma2, rtol=1e-12,
+               precision=mm.MIXED_FP32)
+    g, st = ctx.mlmc_gradient(u, M, first=[2, 0, 5])
+    pb = orc.make_problem(grid, theta=theta, alpha=1e-3, sigma2=sigma2, rtol=1e-14)
+    go, so = orc.mlmc_gradient(pb, None, u, yd, M, first=[2, 0, 5])
+    assert st["nonconverged"] == 0
+    assert _rel(g.cpu().numpy(), go) <= 1e-8
+    assert st["J"] == pytest.approx(so["J"], rel=1e-10)
+    ctx.close()
