@@ -57,9 +57,19 @@ void march_matvec(const GridArgs& g, const TZ* z, const T* p_old, T* p_new, T* q
 template <typename T>
 void march_gs(const GridArgs& g, T* x, const T* b, int color, int x_zero,
               const int* poff, double* partial, int top_begin, double omega, hipStream_t s);
+// One damped Jacobi (Chebyshev) step out of place: xout = x + omega D^-1 (b - A x)
+// with x = xin + P xc (xc nullable; x_zero: x = 0).  partial: <b, xout>.
 template <typename T>
-void coef_cache(int n, int rows, const double* coef, int K, const double* cosT, T* out,
-                hipStream_t s);
+void march_jac(const GridArgs& g, const T* xin, const T* xc, const T* b, T* xout, int x_zero,
+               double omega, const int* poff, double* partial, int top_begin, hipStream_t s);
+// Fused red-black sweep, out of place, cached coefficient required:
+// xout = GS(xin + P xc) (xc nullable; x_zero: xin ignored and taken as 0).
+template <typename T>
+void rb_sweep(const GridArgs& g, const T* xin, const T* xc, const T* b, T* xout,
+              int first_color, int x_zero, const int* poff, double* partial, int top_begin,
+              double omega, hipStream_t s);
+void coef_cache(int n, int rows, const double* coef, int K, const double* cosT, double* out64,
+                float* out32, hipStream_t s);
 
 // ---- batched grid transfers (rows of one grid size) ----
 template <typename T>

@@ -112,8 +112,87 @@ Tiling make_tiling(int n) {
 // OP_MATVEC: p = z + beta p (on the fly, halo included), q = A p, <p, q>
 // OP_GS    : one colour of a red-black Gauss-Seidel sweep in place with
 //            relaxation omega (x_zero: start from x = 0; partial: <b, x>)
+// OP_JAC   : one damped Jacobi step out of place, x' = x + omega D^-1 (b - A x)
+//            (the steps of the Chebyshev smoother; x_zero: x = 0; partial:
+//            <b, x'>); OP_JACP also adds the trilinear prolongation of the
+//            coarse rows in2 to every loaded x (coarse-grid correction)
 // ---------------------------------------------------------------------------
-enum MarchOp { OP_RESID = 0, OP_MATVEC = 1, OP_GS = 2 };
+template <typename T>
+__device__ __forceinline__ T prolong_val(int nc, const T* __restrict__ c, int ix, int iy, int iz) {
+  const int ax = ix >> 1, bx = (ix + 1) >> 1;
+  const int ay = iy >> 1, by = (iy + 1) >> 1;
+  const int az = iz >> 1, bz = (iz + 1) >> 1;
+  auto cv = [&](int a, int b, int d) { return c[((size_t)a * nc + b) * nc + d]; };
+  T v = cv(ax, ay, az);
+  if (iz & 1) v += cv(ax, ay, bz);
+  if (iy & 1) {
+    v += cv(ax, by, az);
+    if (iz & 1) v += cv(ax, by, bz);
+  }
+  if (ix & 1) {
+    v += cv(bx, ay, az);
+    if (iz & 1) v += cv(bx, ay, bz);
+    if (iy & 1) {
+      v += cv(bx, by, az);
+      if (iz & 1) v += cv(bx, by, bz);
+    }
+  }
+  const T w = ((ix & 1) ? T(0.5) : T(1)) * ((iy & 1) ? T(0.5) : T(1)) * ((iz & 1) ? T(0.5) : T(1));
+  return w * v;
+}
+
+// Trilinear prolongation along one fine (y, z) column while marching in x:
+// the (y, z)-bilinear value of each coarse plane is formed once (up to four
+// taps) and kept for the three fine planes that use it.
+template <typename T>
+struct ProlongCol {
+  const T* c;      // coarse row + (y, z) offset of the lower tap
+  int ncnc, dy, dz;  // plane stride; upper-tap offsets (0: no second tap in y / z)
+  int j1;
+  T v0, v1;        // bilinear values of coarse planes j1 - 1 and j1
+  __device__ void init(const T* crow, int nc, int jy, int jz) {
+    ncnc = nc * nc;
+    c = crow + (jy >> 1) * nc + (jz >> 1);
+    dy = (jy & 1) ? nc : 0;
+    dz = (jz & 1) ? 1 : 0;
+    j1 = -2;
+    v0 = v1 = T(0);
+  }
+  __device__ T bilinear(int j) const {
+    const T* p = c + (size_t)j * ncnc;
+    T v = p[0];
+    if (dz) v = T(0.5) * (v + p[dz]);
+    if (dy) {
+      T w = p[dy];
+      if (dz) w = T(0.5) * (w + p[dy + dz]);
+      v = T(0.5) * (v + w);
+    }
+    return v;
+  }
+  // value of coarse plane j; planes are requested in non-decreasing order
+  __device__ T plane(int j) {
+    if (j == j1) return v1;
+    if (j == j1 - 1) return v0;
+    if (j == j1 + 1) {
+      v0 = v1;
+    } else {
+      v0 = j > 0 ? bilinear(j - 1) : T(0);
+    }
+    v1 = bilinear(j);
+    j1 = j;
+    return v1;
+  }
+  __device__ T at(int ix) {
+    const int j = ix >> 1;
+    if (ix & 1) {
+      const T hi = plane(j + 1);
+      return T(0.5) * (v0 + hi);
+    }
+    return plane(j);
+  }
+};
+
+enum MarchOp { OP_RESID = 0, OP_MATVEC = 1, OP_GS = 2, OP_JAC = 3, OP_JACP = 4 };
 
 template <typename T, typename TI, int TY, int TZ, int OP, bool CACHED>
 __global__ void __launch_bounds__(TY* TZ)
@@ -178,11 +257,19 @@ __global__ void __launch_bounds__(TY* TZ)
   T beta = T(0);
   if (OP == OP_MATVEC) beta = (T)g.scal[prob].beta;
 
-  auto ld = [&](int ix, int jy, int jz) -> T {
+  ProlongCol<T> pco, pch;   // prolongation state of the own and the halo column
+  if (OP == OP_JACP) {
+    const int nc = (n - 1) / 2 + 1;
+    const T* crow = in2 + (size_t)row * ((size_t)nc * nc * nc);
+    pco.init(crow, nc, min(iy, n - 1), min(iz, n - 1));
+    pch.init(crow, nc, hy, hz);
+  }
+  auto ld = [&](int ix, int jy, int jz, ProlongCol<T>& pc) -> T {
     if (x_zero) return T(0);
     if (ix <= 0 || ix >= n - 1 || jy <= 0 || jy >= n - 1 || jz <= 0 || jz >= n - 1) return T(0);
     const size_t idx = base + ((size_t)ix * n + jy) * n + jz;
     if (OP == OP_MATVEC) return (T)in[idx] + beta * in2[idx];
+    if (OP == OP_JACP) return (T)in[idx] + pc.at(ix);
     return (T)in[idx];
   };
 
@@ -236,37 +323,48 @@ __global__ void __launch_bounds__(TY* TZ)
   const int x1 = min(x0 + g.t.xchunk, n - 1);
   const T ih2 = (T)g.ih2;
 
-  T xm = T(0), xcur = T(0), bm = T(1), bc = T(1);
+  // Software pipeline: x and 1/a of the own column and of the halo slot are
+  // fetched two planes ahead, the right-hand side one plane ahead, so no
+  // plane waits on a memory round trip of its own.
+  T xm = T(0), xcur = T(0), xp = T(0), bm = T(1), bc = T(1), bp = T(1);
   if (inside) {
-    xm = ld(x0 - 1, iy, iz);
-    xcur = ld(x0, iy, iz);
+    xm = ld(x0 - 1, iy, iz, pco);
+    xcur = ld(x0, iy, iz, pco);
+    xp = ld(x0 + 1, iy, iz, pco);
     bm = coefb(x0 - 1, iy, iz, Sm);
     bc = coefb(x0, iy, iz, Sm);
+    bp = coefb(x0 + 1, iy, iz, Sm);
   }
   T fxm = face(bm, bc);
-  T hcur = T(0), hbc = T(1);
+  T hcur = T(0), hnext = T(0), hbc = T(1), hbn = T(1);
   if (has_halo) {
-    hcur = ld(x0, hy, hz);
+    hcur = ld(x0, hy, hz, pch);
     hbc = coefb(x0, hy, hz, Sh);
+    if (x0 + 1 < x1) {
+      hnext = ld(x0 + 1, hy, hz, pch);
+      hbn = coefb(x0 + 1, hy, hz, Sh);
+    }
   }
+  constexpr bool USES_B = (OP == OP_RESID || OP == OP_GS || OP == OP_JAC || OP == OP_JACP);
+  T bv = T(0);
+  if (USES_B && own) bv = rhs[base + ((size_t)x0 * n + iy) * n + iz];
   double dot = 0.0;
   const int cidx = (ly + 1) * PZ + (lz + 1);
   const int hidx = hly * PZ + hlz;
 
   for (int ix = x0; ix < x1; ++ix) {
     const int buf = ix & 1;
-    // prefetch the next plane of the own column and of the halo slot
-    const T xp = inside ? ld(ix + 1, iy, iz) : T(0);
-    const T hnext = (has_halo && ix + 1 < x1) ? ld(ix + 1, hy, hz) : T(0);
-    T bp = T(1), hbn = T(1);
-    if (CACHED) {
-      if (inside) bp = coefb(ix + 1, iy, iz, Sm);
-      if (has_halo && ix + 1 < x1) hbn = coefb(ix + 1, hy, hz, Sh);
+    // prefetch: plane ix+2 of the columns, plane ix+1 of the right-hand side
+    T xpp = T(0), bpp = T(1), hnn = T(0), hbnn = T(1), bvn = T(0);
+    if (inside && ix + 2 <= n - 1) {
+      xpp = ld(ix + 2, iy, iz, pco);
+      bpp = coefb(ix + 2, iy, iz, Sm);
     }
-    T bv = T(0);
-    if (OP == OP_RESID || OP == OP_GS) {
-      if (own) bv = rhs[base + ((size_t)ix * n + iy) * n + iz];
+    if (has_halo && ix + 2 < x1) {
+      hnn = ld(ix + 2, hy, hz, pch);
+      hbnn = coefb(ix + 2, hy, hz, Sh);
     }
+    if (USES_B && own && ix + 1 < x1) bvn = rhs[base + ((size_t)(ix + 1) * n + iy) * n + iz];
     sx[buf][cidx] = inside ? xcur : T(0);
     sb[buf][cidx] = inside ? bc : T(1);
     if (tid < NH) {
@@ -274,7 +372,6 @@ __global__ void __launch_bounds__(TY* TZ)
       sb[buf][hidx] = has_halo ? hbc : T(1);
     }
     __syncthreads();
-    if (!CACHED) bp = inside ? coefb(ix + 1, iy, iz, Sm) : T(1);
     const T fxp = face(bc, bp);
     if (own) {
       const T xym = sx[buf][cidx - PZ], xyp = sx[buf][cidx + PZ];
@@ -291,6 +388,10 @@ __global__ void __launch_bounds__(TY* TZ)
         out[idx] = q;
         out2[idx] = xcur;
         dot += (double)xcur * (double)q;
+      } else if (OP == OP_JAC || OP == OP_JACP) {
+        const T val = xcur + omega * (bv - ih2 * (diag * xcur - off)) * drcp(ih2 * diag);
+        out[idx] = val;
+        if (partial) dot += (double)bv * (double)val;
       } else {  // OP_GS
         T val = xcur;
         const bool upd = ((ix + iy + iz) & 1) == color;
@@ -310,15 +411,20 @@ __global__ void __launch_bounds__(TY* TZ)
     }
     xm = xcur;
     xcur = xp;
+    xp = xpp;
     bm = bc;
     bc = bp;
+    bp = bpp;
     fxm = fxp;
-    if (has_halo && ix + 1 < x1) {
-      hcur = hnext;
-      hbc = CACHED ? hbn : coefb(ix + 1, hy, hz, Sh);
-    }
+    hcur = hnext;
+    hnext = hnn;
+    hbc = hbn;
+    hbn = hbnn;
+    bv = bvn;
   }
-  const bool want = (OP == OP_MATVEC) || (OP == OP_GS && partial != nullptr && prob >= top_begin);
+  const bool want = (OP == OP_MATVEC) ||
+                    ((OP == OP_GS || OP == OP_JAC || OP == OP_JACP) && partial != nullptr &&
+                     prob >= top_begin);
   if (want) {
     const double s = block_sum<NT>(dot, sred);
     if (threadIdx.x == 0) partial[poff[prob] + tile] = s;
@@ -387,34 +493,328 @@ template void march_gs<double>(const GridArgs&, double*, const double*, int, int
                                double*, int, double, hipStream_t);
 template void march_gs<float>(const GridArgs&, float*, const float*, int, int, const int*,
                               double*, int, double, hipStream_t);
-
-// Per-estimate cache of the reciprocal coefficient 1/a = exp(-log a) at every
-// vertex of every row of one grid size (the KL sum written out separably).
 template <typename T>
-__global__ void k_coef_cache(int n, int rows, const double* __restrict__ coef, int K,
-                             const double* __restrict__ cosT, T* __restrict__ out) {
-  const long long per = (long long)n * n * n;
-  const long long total = per * rows;
-  const int K3 = K * K * K;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    const int row = (int)(i / per);
-    const long long v = i - (long long)row * per;
-    const int ix = (int)(v / ((long long)n * n)), iy = (int)((v / n) % n), iz = (int)(v % n);
-    const double* c = coef + (size_t)row * K3;
-    double l = 0.0;
-    for (int k1 = 0; k1 < K; ++k1) {
-      double a1 = 0.0;
-      for (int k2 = 0; k2 < K; ++k2) {
-        double a2 = 0.0;
-        for (int k3 = 0; k3 < K; ++k3) a2 += c[(k1 * K + k2) * K + k3] * cosT[k3 * n + iz];
-        a1 += a2 * cosT[k2 * n + iy];
-      }
-      l += a1 * cosT[k1 * n + ix];
+void march_jac(const GridArgs& g, const T* xin, const T* xc, const T* b, T* xout, int x_zero,
+               double omega, const int* poff, double* partial, int top_begin, hipStream_t s) {
+  if (xc && !x_zero)
+    launch_march<T, T, OP_JACP>(g, xin, xc, b, xout, nullptr, poff, partial, 0, 0, top_begin,
+                                (T)omega, s);
+  else
+    launch_march<T, T, OP_JAC>(g, xin, nullptr, b, xout, nullptr, poff, partial, 0, x_zero,
+                               top_begin, (T)omega, s);
+}
+template void march_jac<double>(const GridArgs&, const double*, const double*, const double*,
+                                double*, int, double, const int*, double*, int, hipStream_t);
+template void march_jac<float>(const GridArgs&, const float*, const float*, const float*, float*,
+                               int, double, const int*, double*, int, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Fused red-black Gauss-Seidel sweep (both colours in one pass, out of place).
+//
+// x_out = GS_second(GS_first(x_in)) with relaxation omega, where x_in is the
+// previous iterate (zero on a zero start) plus, optionally, the trilinear
+// prolongation of a coarse correction folded into every load.  The pass is a
+// wavefront along x: at plane s the first colour is updated on the patch and
+// on a one-point ring around it (the ring values belong to neighbouring
+// patches and are recomputed here from the same inputs, so every patch sees
+// identical values), then the second colour is updated on plane s-1 of the
+// patch and written out.  LDS holds three planes (values and 1/a) with a
+// two-point ring; each thread keeps its own column's planes s-2..s+1 in
+// registers, and threads below 2(TY+TZ)+4 also own one ring column and one
+// outer-ring slot.  The coefficient is read from the per-estimate cache.
+// ---------------------------------------------------------------------------
+template <typename T, int TY, int TZ, bool XZERO, bool PROLONG>
+__global__ void __launch_bounds__(TY* TZ)
+    k_rbsweep(GridArgs g, const T* __restrict__ xin, const T* __restrict__ xc,
+              const T* __restrict__ rhs, T* __restrict__ xout, int first_color,
+              const int* __restrict__ poff, double* __restrict__ partial, int top_begin,
+              T omega) {
+  constexpr int NT = TY * TZ;
+  constexpr int PZ = TZ + 4;
+  constexpr int PLANE = (TY + 4) * PZ;
+  constexpr int NRING = 2 * (TZ + 2) + 2 * TY;   // one-point ring incl. its 4 corners
+  constexpr int NR2 = 2 * (TZ + TY);             // two-point ring without corners
+  static_assert(NRING <= NT && NR2 <= NT, "tile too small for its rings");
+  __shared__ T sv[3][PLANE];
+  __shared__ T sb[3][PLANE];
+  __shared__ double sred[NT / 64];
+
+  const int n = g.n;
+  const int nn = n * n;
+  const int nc = (n - 1) / 2 + 1;
+  const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int tpr = g.t.tiles_per_row;
+  const int row = bid / tpr;
+  const int tile = bid - row * tpr;
+  int tt = tile;
+  const int ty = tt % g.t.nty;
+  tt /= g.t.nty;
+  const int tz = tt % g.t.ntz;
+  const int xcix = tt / g.t.ntz;
+  const int prob = g.row0 + row;
+  if (g.scal && !g.scal[prob].active) return;  // uniform per workgroup
+
+  const size_t stride = (size_t)g.stride;
+  const T* __restrict__ xr = xin + (size_t)row * stride;
+  const T* __restrict__ br = rhs + (size_t)row * stride;
+  T* __restrict__ outr = xout + (size_t)row * stride;
+  const T* __restrict__ cache = (const T*)g.cache + (size_t)prob * stride;
+  const T* __restrict__ xcr = PROLONG ? xc + (size_t)row * ((size_t)nc * nc * nc) : nullptr;
+  const int tid = threadIdx.x;
+  const int y0 = 1 + ty * TY, z0 = 1 + tz * TZ;
+  const int c1 = first_color ^ 1;
+
+  // own tile position
+  const int ly = tid / TZ, lz = tid - (tid / TZ) * TZ;
+  const int oy = y0 + ly, oz = z0 + lz;
+  const int oidx = (ly + 2) * PZ + (lz + 2);
+  // one-point ring column (LDS coordinates in [1, TY+2] x [1, TZ+2])
+  int rly = 0, rlz = 0;
+  if (tid < NRING) {
+    if (tid < TZ + 2) {
+      rly = 1; rlz = tid + 1;
+    } else if (tid < 2 * (TZ + 2)) {
+      rly = TY + 2; rlz = tid - (TZ + 2) + 1;
+    } else if (tid < 2 * (TZ + 2) + TY) {
+      rly = tid - 2 * (TZ + 2) + 2; rlz = 1;
+    } else {
+      rly = tid - 2 * (TZ + 2) - TY + 2; rlz = TZ + 2;
     }
-    out[i] = (T)exp(-l);
+  }
+  const int ry = y0 - 2 + rly, rz = z0 - 2 + rlz;
+  const int ridx = rly * PZ + rlz;
+  const bool ring_corner = (rly == 1 || rly == TY + 2) && (rlz == 1 || rlz == TZ + 2);
+  // two-point ring slot
+  int qly = 0, qlz = 0;
+  if (tid < NR2) {
+    if (tid < TZ) {
+      qly = 0; qlz = tid + 2;
+    } else if (tid < 2 * TZ) {
+      qly = TY + 3; qlz = tid - TZ + 2;
+    } else if (tid < 2 * TZ + TY) {
+      qly = tid - 2 * TZ + 2; qlz = 0;
+    } else {
+      qly = tid - 2 * TZ - TY + 2; qlz = TZ + 3;
+    }
+  }
+  const int qy = y0 - 2 + qly, qz = z0 - 2 + qlz;
+  const int qidx = qly * PZ + qlz;
+
+  // column properties: inside the grid (coefficient exists), interior (unknown)
+  const bool own_grid = oy <= n - 1 && oz <= n - 1;
+  const bool own_int = oy <= n - 2 && oz <= n - 2;
+  const bool ring_on = tid < NRING && ry >= 0 && rz >= 0 && ry <= n - 1 && rz <= n - 1;
+  const bool ring_upd = ring_on && !ring_corner && ry >= 1 && rz >= 1 && ry <= n - 2 && rz <= n - 2;
+  const bool r2_on = tid < NR2 && qy >= 0 && qz >= 0 && qy <= n - 1 && qz <= n - 1;
+  const bool r2_int = r2_on && qy >= 1 && qz >= 1 && qy <= n - 2 && qz <= n - 2;
+  const int ocol = oy * n + oz, rcol = ry * n + rz, qcol = qy * n + qz;
+  const int opar = (oy + oz) & 1, rpar = (ry + rz) & 1;
+
+  // previous iterate (+ prolonged coarse correction) on plane ix of a column
+  auto ldx = [&](int ix, bool colint, int col, int jy, int jz) -> T {
+    if (XZERO || !colint || ix < 1 || ix > n - 2) return T(0);
+    T v = xr[ix * nn + col];
+    if (PROLONG) v += prolong_val<T>(nc, xcr, ix, jy, jz);
+    return v;
+  };
+  auto ldb = [&](int ix, bool colin, int col) -> T {
+    if (!colin || ix < 0 || ix > n - 1) return T(1);
+    return cache[ix * nn + col];
+  };
+  const T ih2 = (T)g.ih2;
+
+  const int x0 = 1 + xcix * g.t.xchunk;
+  const int x1 = min(x0 + g.t.xchunk, n - 1);
+
+  // own column queue: values at s-2 .. s+1 and 1/a at s-2 .. s+1
+  const int s0 = x0 - 1;
+  T q0 = T(0), q1 = ldx(s0 - 1, own_int, ocol, oy, oz), q2 = ldx(s0, own_int, ocol, oy, oz),
+    q3 = ldx(s0 + 1, own_int, ocol, oy, oz);
+  T b0 = T(1), b1 = ldb(s0 - 1, own_grid, ocol), b2 = ldb(s0, own_grid, ocol),
+    b3 = ldb(s0 + 1, own_grid, ocol);
+  // ring column queue: old values and 1/a at s-1 .. s+1
+  const bool rint = ring_on && ry >= 1 && rz >= 1 && ry <= n - 2 && rz <= n - 2;
+  T r0 = ldx(s0 - 1, rint, rcol, ry, rz), r1 = ldx(s0, rint, rcol, ry, rz),
+    r2 = ldx(s0 + 1, rint, rcol, ry, rz);
+  T rb0 = ldb(s0 - 1, ring_on, rcol), rb1 = ldb(s0, ring_on, rcol), rb2 = ldb(s0 + 1, ring_on, rcol);
+  // outer-ring slot: plane s
+  T qv = ldx(s0, r2_int, qcol, qy, qz), qb = ldb(s0, r2_on, qcol);
+  // right-hand sides: own column at s (first colour) and s-1 (second colour), ring at s
+  auto ldr = [&](int ix, bool colint, int col) -> T {
+    if (!colint || ix < 1 || ix > n - 2) return T(0);
+    return br[ix * nn + col];
+  };
+  T bo_s = ldr(s0, own_int, ocol), bo_m = ldr(s0 - 1, own_int, ocol);
+  T br_s = ldr(s0, ring_upd, rcol);
+  double dot = 0.0;
+  const bool want_dot = partial != nullptr && prob >= top_begin;
+
+  for (int s = s0; s <= x1; ++s) {
+    const int buf = (s - s0) % 3;
+    const int pbuf = (s - s0 + 2) % 3;   // plane s-1
+    // prefetch: columns at s+2, outer ring at s+1, right-hand sides at s+1
+    const T nq = ldx(s + 2, own_int, ocol, oy, oz);
+    const T nb = ldb(s + 2, own_grid, ocol);
+    const T nr = ldx(s + 2, rint, rcol, ry, rz);
+    const T nrb = ldb(s + 2, ring_on, rcol);
+    const T nqv = ldx(s + 1, r2_int, qcol, qy, qz);
+    const T nqb = ldb(s + 1, r2_on, qcol);
+    const T nbo = ldr(s + 1, own_int, ocol);
+    const T nbr = ldr(s + 1, ring_upd, rcol);
+
+    // plane s (old values) into LDS
+    sv[buf][oidx] = q2;
+    sb[buf][oidx] = b2;
+    if (tid < NRING) {
+      sv[buf][ridx] = r1;
+      sb[buf][ridx] = rb1;
+    }
+    if (tid < NR2) {
+      sv[buf][qidx] = qv;
+      sb[buf][qidx] = qb;
+    }
+    __syncthreads();
+    const int spar = s & 1;
+    // first colour on plane s: patch and ring (writes only first-colour
+    // points, reads only second-colour neighbours: no barrier needed)
+    if (own_int && s >= 1 && s <= n - 2 && (spar ^ opar) == first_color) {
+      const T bc = b2;
+      const T fxm = face(bc, b1), fxp = face(bc, b3);
+      const T fym = face(bc, sb[buf][oidx - PZ]), fyp = face(bc, sb[buf][oidx + PZ]);
+      const T fzm = face(bc, sb[buf][oidx - 1]), fzp = face(bc, sb[buf][oidx + 1]);
+      const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
+      const T off = ((fxm * q1 + fxp * q3) + (fym * sv[buf][oidx - PZ] + fyp * sv[buf][oidx + PZ])) +
+                    (fzm * sv[buf][oidx - 1] + fzp * sv[buf][oidx + 1]);
+      const T gs = (bo_s + ih2 * off) * drcp(ih2 * diag);
+      q2 = q2 + omega * (gs - q2);
+      sv[buf][oidx] = q2;
+    }
+    if (ring_upd && s >= 1 && s <= n - 2 && (spar ^ rpar) == first_color) {
+      const T bc = rb1;
+      const T fxm = face(bc, rb0), fxp = face(bc, rb2);
+      const T fym = face(bc, sb[buf][ridx - PZ]), fyp = face(bc, sb[buf][ridx + PZ]);
+      const T fzm = face(bc, sb[buf][ridx - 1]), fzp = face(bc, sb[buf][ridx + 1]);
+      const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
+      const T off = ((fxm * r0 + fxp * r2) + (fym * sv[buf][ridx - PZ] + fyp * sv[buf][ridx + PZ])) +
+                    (fzm * sv[buf][ridx - 1] + fzp * sv[buf][ridx + 1]);
+      const T gs = (br_s + ih2 * off) * drcp(ih2 * diag);
+      sv[buf][ridx] = r1 + omega * (gs - r1);
+    }
+    // second colour on plane s-1 of the patch (its first-colour neighbours
+    // on plane s-1 were published by the previous plane's barrier; plane s
+    // is the thread's own q2), then write plane s-1 out
+    const int sm1 = s - 1;
+    if (own_int && sm1 >= x0 && sm1 <= x1 - 1) {
+      T val = q1;
+      if ((((sm1 & 1) ^ opar)) == c1) {
+        const T bc = b1;
+        const T fxm = face(bc, b0), fxp = face(bc, b2);
+        const T fym = face(bc, sb[pbuf][oidx - PZ]), fyp = face(bc, sb[pbuf][oidx + PZ]);
+        const T fzm = face(bc, sb[pbuf][oidx - 1]), fzp = face(bc, sb[pbuf][oidx + 1]);
+        const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
+        const T off = ((fxm * q0 + fxp * q2) + (fym * sv[pbuf][oidx - PZ] + fyp * sv[pbuf][oidx + PZ])) +
+                      (fzm * sv[pbuf][oidx - 1] + fzp * sv[pbuf][oidx + 1]);
+        const T gs = (bo_m + ih2 * off) * drcp(ih2 * diag);
+        val = q1 + omega * (gs - q1);
+      }
+      outr[sm1 * nn + ocol] = val;
+      if (want_dot) dot += (double)bo_m * (double)val;
+      q1 = val;
+    }
+    // rotate
+    q0 = q1; q1 = q2; q2 = q3; q3 = nq;
+    b0 = b1; b1 = b2; b2 = b3; b3 = nb;
+    r0 = r1; r1 = r2; r2 = nr;
+    rb0 = rb1; rb1 = rb2; rb2 = nrb;
+    qv = nqv; qb = nqb;
+    bo_m = bo_s; bo_s = nbo; br_s = nbr;
+  }
+  if (want_dot) {
+    const double sum = block_sum<NT>(dot, sred);
+    if (threadIdx.x == 0) partial[poff[prob] + tile] = sum;
   }
 }
+
+template <typename T>
+void rb_sweep(const GridArgs& g, const T* xin, const T* xc, const T* b, T* xout, int first_color,
+              int x_zero, const int* poff, double* partial, int top_begin, double omega,
+              hipStream_t s) {
+  if (g.rows <= 0) return;
+  const int nblk = g.rows * g.t.tiles_per_row;
+#define MLSGD_LAUNCH4(TY_, TZ_, XZ_, PR_)                                                   \
+  hipLaunchKernelGGL((k_rbsweep<T, TY_, TZ_, XZ_, PR_>), dim3(nblk), dim3(TY_ * TZ_), 0, s, g, \
+                     xin, xc, b, xout, first_color, poff, partial, top_begin, (T)omega)
+#define MLSGD_LAUNCH(TY_, TZ_)                 \
+  if (x_zero)                                  \
+    MLSGD_LAUNCH4(TY_, TZ_, true, false);      \
+  else if (xc)                                 \
+    MLSGD_LAUNCH4(TY_, TZ_, false, true);      \
+  else                                         \
+    MLSGD_LAUNCH4(TY_, TZ_, false, false)
+  if (g.t.TZ == 8) {
+    MLSGD_LAUNCH(8, 8);
+  } else if (g.t.TZ == 16) {
+    MLSGD_LAUNCH(16, 16);
+  } else if (g.t.TZ == 32) {
+    MLSGD_LAUNCH(8, 32);
+  } else if (g.t.TY == 8) {
+    MLSGD_LAUNCH(8, 64);
+  } else {
+    MLSGD_LAUNCH(4, 64);
+  }
+#undef MLSGD_LAUNCH
+#undef MLSGD_LAUNCH4
+}
+template void rb_sweep<double>(const GridArgs&, const double*, const double*, const double*,
+                               double*, int, int, const int*, double*, int, double, hipStream_t);
+template void rb_sweep<float>(const GridArgs&, const float*, const float*, const float*, float*,
+                              int, int, const int*, double*, int, double, hipStream_t);
+
+// Per-estimate cache of the reciprocal coefficient 1/a = exp(-log a) at every
+// vertex of every row of one grid size.  A thread owns one (y, z) column:
+// S[k1] = sum_{k2,k3} c[k1,k2,k3] cos(pi k2 y) cos(pi k3 z) once, then K FMAs
+// and one FP64 exp per vertex along x (the KL sum written separably).  The
+// FP64 and/or FP32 copies are written in the same pass.
+__global__ void __launch_bounds__(256)
+    k_coef_cache(int n, int rows, const double* __restrict__ coef, int K,
+                 const double* __restrict__ cosT, double* __restrict__ out64,
+                 float* __restrict__ out32) {
+  __shared__ double sc[KMAX * KMAX * KMAX];
+  const int cols = n * n;
+  const int cpb = (cols + 255) / 256;
+  const int row = blockIdx.x / cpb;
+  const int col = (blockIdx.x - row * cpb) * 256 + threadIdx.x;
+  const int K3 = K * K * K;
+  for (int j = threadIdx.x; j < K3; j += 256) sc[j] = coef[(size_t)row * K3 + j];
+  __syncthreads();
+  if (col >= cols) return;
+  const int iy = col / n, iz = col - (col / n) * n;
+  double S[KMAX];
+#pragma unroll
+  for (int k1 = 0; k1 < KMAX; ++k1) {
+    double acc = 0.0;
+    if (k1 < K) {
+      for (int k2 = 0; k2 < K; ++k2) {
+        double t = 0.0;
+        for (int k3 = 0; k3 < K; ++k3) t += sc[(k1 * K + k2) * K + k3] * cosT[k3 * n + iz];
+        acc += t * cosT[k2 * n + iy];
+      }
+    }
+    S[k1] = acc;
+  }
+  const size_t base = (size_t)row * ((size_t)n * n * n) + col;
+  for (int ix = 0; ix < n; ++ix) {
+    double l = 0.0;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k)
+      if (k < K) l += cosT[k * n + ix] * S[k];
+    const double b = exp(-l);
+    const size_t i = base + (size_t)ix * cols;
+    if (out64) out64[i] = b;
+    if (out32) out32[i] = (float)b;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Batched grid transfers.  Full weighting R = P^T / 8 (weights 1/4, 1/2, 1/4
 // per axis) from fine interior to coarse interior, and trilinear
@@ -496,18 +896,13 @@ static int grid_for(long long total, int bs) {
   return (int)b;
 }
 
-template <typename T>
-void coef_cache(int n, int rows, const double* coef, int K, const double* cosT, T* out,
-                hipStream_t s) {
-  if (rows <= 0) return;
-  const long long total = (long long)n * n * n * rows;
-  hipLaunchKernelGGL(k_coef_cache<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, n, rows, coef,
-                     K, cosT, out);
+void coef_cache(int n, int rows, const double* coef, int K, const double* cosT, double* out64,
+                float* out32, hipStream_t s) {
+  if (rows <= 0 || (!out64 && !out32)) return;
+  const int cpb = (n * n + 255) / 256;
+  hipLaunchKernelGGL(k_coef_cache, dim3(rows * cpb), dim3(256), 0, s, n, rows, coef, K, cosT,
+                     out64, out32);
 }
-template void coef_cache<double>(int, int, const double*, int, const double*, double*,
-                                 hipStream_t);
-template void coef_cache<float>(int, int, const double*, int, const double*, float*,
-                                hipStream_t);
 
 template <typename T>
 void restrict_rows(int nf, int rows, int row0, const CgScal* scal, const T* fine, T* coarse,
@@ -761,14 +1156,19 @@ void group_misfit(const GridArgs& g, double* y, const double* yd, double* b_rows
 // Per-problem scalar steps, one workgroup for all problems (fixed summation
 // order; integer count reduced in LDS).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(1024)
+// One thread per problem; the count of problems still active is gathered
+// with integer atomics (exact, order-independent) into a counter zeroed by
+// the caller's k_zero_int.
+__global__ void __launch_bounds__(256)
     k_cg_scalar(int phase, CgScal* scal, int nprob, const int* __restrict__ poff,
                 const int* __restrict__ pcnt, const double* __restrict__ partial, double rtol,
                 int max_iters, int* active_count) {
-  __shared__ int scount[1024];
+  __shared__ int scount[256];
   int cnt = 0;
   const double rt2 = rtol * rtol;
-  for (int p = threadIdx.x; p < nprob; p += 1024) {
+  {
+    const int p = blockIdx.x * 256 + threadIdx.x;
+    if (p < nprob) {
     double sum = 0.0;
     if (partial) {
       const int o = poff[p], c = pcnt[p];
@@ -837,21 +1237,27 @@ __global__ void __launch_bounds__(1024)
     }
     scal[p] = sc;
     cnt += sc.active;
+    }
   }
   scount[threadIdx.x] = cnt;
   __syncthreads();
-  for (int o = 512; o > 0; o >>= 1) {
+  for (int o = 128; o > 0; o >>= 1) {
     if (threadIdx.x < o) scount[threadIdx.x] += scount[threadIdx.x + o];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && active_count) *active_count = scount[0];
+  if (threadIdx.x == 0 && active_count && scount[0]) atomicAdd(active_count, scount[0]);
+}
+
+__global__ void k_zero_int(int* x) {
+  if (threadIdx.x == 0) *x = 0;
 }
 
 void cg_scalar(int phase, CgScal* scal, int nprob, const int* poff, const int* pcnt,
                const double* partial, double rtol, int max_iters, int* active_count,
                hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_scalar, dim3(1), dim3(1024), 0, s, phase, scal, nprob, poff, pcnt,
-                     partial, rtol, max_iters, active_count);
+  if (active_count) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, active_count);
+  hipLaunchKernelGGL(k_cg_scalar, dim3((nprob + 255) / 256), dim3(256), 0, s, phase, scal, nprob,
+                     poff, pcnt, partial, rtol, max_iters, active_count);
 }
 
 __global__ void __launch_bounds__(1024)

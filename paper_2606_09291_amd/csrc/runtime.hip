@@ -63,6 +63,7 @@ struct SizeLvl {
   float *Xf = nullptr, *Bf = nullptr, *Rf = nullptr;  // FP32 multigrid rows (mixed precision)
   float* Cf = nullptr;                              // FP32 cache of 1/a (null: regenerate)
   const double* cosT = nullptr;
+  int cur = 0;   // fused sweeps: which of X/R (Xf/Rf) holds the current iterate
 };
 
 // Problems sharing a top grid: Krylov vectors.
@@ -144,6 +145,8 @@ struct mlsgd_ctx {
   bool cache64 = true;      // cache 1/a per estimate for FP64 sweeps
   bool cache32 = true;      // cache 1/a per estimate for FP32 sweeps
   bool mixed = false;       // FP32 V-cycles inside the FP64 Krylov iteration
+  int smoother = 2;         // 0 red-black GS (two in-place passes), 1 fused red-black, 2 Chebyshev
+  double cheb_lo = 1.0 / 6.0;  // Chebyshev interval [cheb_lo * 2, 2] for D^-1 A
   // event timing of the smoothing passes on one grid size (roofline figures)
   struct Timing {
     bool on = false;
@@ -319,10 +322,7 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks) {
             c->stream);
   // the coefficient is regenerated from the draws once per call for the
   // cached sweeps (the Krylov matvec and residual always run in FP64)
-  for (auto& sl : P->sizes) {
-    if (sl.C) coef_cache<double>(sl.n, sl.rows, P->d_coef, K, sl.cosT, sl.C, c->stream);
-    if (sl.Cf) coef_cache<float>(sl.n, sl.rows, P->d_coef, K, sl.cosT, sl.Cf, c->stream);
-  }
+  for (auto& sl : P->sizes) coef_cache(sl.n, sl.rows, P->d_coef, K, sl.cosT, sl.C, sl.Cf, c->stream);
   HIPCHK(hipGetLastError());
   return P;
 }
@@ -431,6 +431,209 @@ void timing_collect(mlsgd_ctx* c) {
   tm.bytes.clear();
 }
 
+// Algorithmic bytes of one fused red-black sweep over `rows` rows: previous
+// iterate read (not on a zero start), b read, 1/a read, new iterate written,
+// and, when the coarse correction is folded in, the coarse rows read once.
+template <typename T>
+double sweep_bytes(int n, int rows, bool x_zero, bool prolong) {
+  const double N = (double)rows * (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
+  const double e = (double)sizeof(T);
+  double b = 3.0 * e + (x_zero ? 0.0 : e);
+  if (prolong) b += e / 8.0;
+  return N * b;
+}
+
+template <typename T>
+void timed_sweep(mlsgd_ctx* c, const GridArgs& g, const T* xin, const T* xc, const T* b, T* xout,
+                 int first_color, int x_zero, const int* poff, double* partial, int top_begin,
+                 double om) {
+  mlsgd_ctx::Timing& tm = c->tm;
+  const bool rec = tm.on && g.n == tm.n && g.rows > 0;
+  if (rec) {
+    if (tm.used == tm.pool.size()) {
+      hipEvent_t a, e;
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&e));
+      tm.pool.push_back({a, e});
+    }
+    HIPCHK(hipEventRecord(tm.pool[tm.used].first, c->stream));
+  }
+  rb_sweep<T>(g, xin, xc, b, xout, first_color, x_zero, poff, partial, top_begin, om, c->stream);
+  if (rec) {
+    HIPCHK(hipEventRecord(tm.pool[tm.used].second, c->stream));
+    tm.bytes.push_back(sweep_bytes<T>(g.n, g.rows, x_zero != 0, xc != nullptr));
+    ++tm.used;
+  }
+}
+
+template <typename F>
+void timed_launch(mlsgd_ctx* c, const GridArgs& g, double bytes, F&& fn) {
+  mlsgd_ctx::Timing& tm = c->tm;
+  const bool rec = tm.on && g.n == tm.n && g.rows > 0;
+  if (rec) {
+    if (tm.used == tm.pool.size()) {
+      hipEvent_t a, e;
+      HIPCHK(hipEventCreate(&a));
+      HIPCHK(hipEventCreate(&e));
+      tm.pool.push_back({a, e});
+    }
+    HIPCHK(hipEventRecord(tm.pool[tm.used].first, c->stream));
+  }
+  fn();
+  if (rec) {
+    HIPCHK(hipEventRecord(tm.pool[tm.used].second, c->stream));
+    tm.bytes.push_back(bytes);
+    ++tm.used;
+  }
+}
+
+// Chebyshev step sizes: omega_j = 1 / (j-th root of T_deg mapped to [a, b]),
+// largest root first; [a, b] = [2 lo, 2] bounds the upper spectrum of D^-1 A
+// (2 is the Gershgorin bound of the diagonally scaled operator).
+std::vector<double> cheb_omegas(int deg, double lo) {
+  const double b = 2.0, a = 2.0 * lo;
+  std::vector<double> w(deg);
+  for (int j = 0; j < deg; ++j) {
+    const double root = 0.5 * (a + b) + 0.5 * (b - a) * std::cos(M_PI * (2.0 * j + 1.0) / (2.0 * deg));
+    w[j] = 1.0 / root;
+  }
+  return w;
+}
+
+// Algorithmic bytes of one Jacobi step: x read (not from zero), b, 1/a, x'
+// written, coarse rows once when the correction is folded in.
+template <typename T>
+double jac_bytes(int n, int rows, bool x_zero, bool prolong, bool cached) {
+  const double N = (double)rows * (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
+  const double e = (double)sizeof(T);
+  double b = 2.0 * e + (x_zero ? 0.0 : e) + (cached ? e : 0.0);
+  if (prolong) b += e / 8.0;
+  return N * b;
+}
+
+// Symmetric V(1,1) cycle with degree-nu Chebyshev smoothing (a polynomial in
+// D^-1 A, so pre- and post-smoother commute and the cycle is symmetric):
+// pre-smoothing from a zero guess, residual, full weighting, coarse cycle,
+// post-smoothing whose first step folds in the prolonged coarse correction
+// and whose last step forms <r, z> for the problems whose top grid it is.
+// The single unknown of the 3^3 grid is solved exactly by one Jacobi step.
+template <typename T>
+void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
+  const int S = (int)P->sizes.size();
+  const int deg = c->nu;
+  const std::vector<double> om = cheb_omegas(deg, c->cheb_lo);
+  auto args = [&](SizeLvl& L) {
+    return sizeof(T) == 8 ? args_size(c, P, L) : args_size32(c, P, L);
+  };
+  for (int k = 0; k < S; ++k) {
+    SizeLvl& L = P->sizes[k];
+    MgView<T> v = mg_view<T>(L);
+    T* A[2] = {v.X, v.R};
+    GridArgs g = args(L);
+    const bool cached = g.cache != nullptr;
+    if (k == S - 1) {
+      timed_launch(c, g, jac_bytes<T>(L.n, L.rows, true, false, cached), [&] {
+        march_jac<T>(g, nullptr, nullptr, v.B, A[0], 1, 1.0, P->d_poff, P->d_partial, L.top_begin,
+                     c->stream);
+      });
+      L.cur = 0;
+      break;
+    }
+    int cur = 0;
+    timed_launch(c, g, jac_bytes<T>(L.n, L.rows, true, false, cached), [&] {
+      march_jac<T>(g, nullptr, nullptr, v.B, A[0], 1, om[0], nullptr, nullptr, 0, c->stream);
+    });
+    for (int j = 1; j < deg; ++j) {
+      timed_launch(c, g, jac_bytes<T>(L.n, L.rows, false, false, cached), [&] {
+        march_jac<T>(g, A[cur], nullptr, v.B, A[cur ^ 1], 0, om[j], nullptr, nullptr, 0,
+                     c->stream);
+      });
+      cur ^= 1;
+    }
+    march_resid<T>(g, A[cur], v.B, A[cur ^ 1], c->stream);
+    restrict_rows<T>(L.n, L.rows, 0, P->d_scal, A[cur ^ 1], mg_view<T>(P->sizes[k + 1]).B,
+                     c->stream);
+    L.cur = cur;
+  }
+  for (int k = S - 2; k >= 0; --k) {
+    SizeLvl& L = P->sizes[k];
+    MgView<T> v = mg_view<T>(L);
+    T* A[2] = {v.X, v.R};
+    SizeLvl& Lc = P->sizes[k + 1];
+    MgView<T> vc = mg_view<T>(Lc);
+    const T* xc = Lc.cur ? vc.R : vc.X;
+    GridArgs g = args(L);
+    const bool cached = g.cache != nullptr;
+    int cur = L.cur;
+    for (int j = 0; j < deg; ++j) {
+      const bool last = j == deg - 1;
+      const T* corr = j == 0 ? xc : nullptr;
+      timed_launch(c, g, jac_bytes<T>(L.n, L.rows, false, j == 0, cached), [&] {
+        march_jac<T>(g, A[cur], corr, v.B, A[cur ^ 1], 0, om[deg - 1 - j],
+                     last ? P->d_poff : nullptr, last ? P->d_partial : nullptr, L.top_begin,
+                     c->stream);
+      });
+      cur ^= 1;
+    }
+    L.cur = cur;
+  }
+}
+
+// Symmetric V(nu,nu) cycle with fused red-black sweeps (cached coefficient):
+// pre-smoothing red-first sweeps from a zero guess, residual, full weighting,
+// coarse cycle, then black-first post-smoothing sweeps whose first one folds
+// the prolonged coarse correction into its loads; the last one forms <r, z>
+// for the problems whose top grid it is.  Each grid alternates its iterate
+// between the X and R rows; `cur` records where it ended.
+template <typename T>
+void vcycle_fused(mlsgd_ctx* c, Plan* P) {
+  const int S = (int)P->sizes.size();
+  const int nu = c->nu;
+  const double om = c->omega;
+  auto args = [&](SizeLvl& L) {
+    return sizeof(T) == 8 ? args_size(c, P, L) : args_size32(c, P, L);
+  };
+  for (int k = 0; k < S; ++k) {
+    SizeLvl& L = P->sizes[k];
+    MgView<T> v = mg_view<T>(L);
+    T* A[2] = {v.X, v.R};
+    GridArgs g = args(L);
+    if (k == S - 1) {
+      timed_sweep<T>(c, g, nullptr, nullptr, v.B, A[0], 0, 1, P->d_poff, P->d_partial,
+                     L.top_begin, 1.0);
+      L.cur = 0;
+      break;
+    }
+    int cur = 0;
+    timed_sweep<T>(c, g, nullptr, nullptr, v.B, A[0], 0, 1, nullptr, nullptr, 0, om);
+    for (int sw = 1; sw < nu; ++sw) {
+      timed_sweep<T>(c, g, A[cur], nullptr, v.B, A[cur ^ 1], 0, 0, nullptr, nullptr, 0, om);
+      cur ^= 1;
+    }
+    march_resid<T>(g, A[cur], v.B, A[cur ^ 1], c->stream);
+    restrict_rows<T>(L.n, L.rows, 0, P->d_scal, A[cur ^ 1], mg_view<T>(P->sizes[k + 1]).B,
+                     c->stream);
+    L.cur = cur;
+  }
+  for (int k = S - 2; k >= 0; --k) {
+    SizeLvl& L = P->sizes[k];
+    MgView<T> v = mg_view<T>(L);
+    T* A[2] = {v.X, v.R};
+    SizeLvl& Lc = P->sizes[k + 1];
+    MgView<T> vc = mg_view<T>(Lc);
+    const T* xc = Lc.cur ? vc.R : vc.X;
+    GridArgs g = args(L);
+    int cur = L.cur;
+    for (int sw = 0; sw < nu; ++sw) {
+      const bool last = sw == nu - 1;
+      timed_sweep<T>(c, g, A[cur], sw == 0 ? xc : nullptr, v.B, A[cur ^ 1], 1, 0,
+                     last ? P->d_poff : nullptr, last ? P->d_partial : nullptr, L.top_begin, om);
+      cur ^= 1;
+    }
+    L.cur = cur;
+  }
+}
+
 template <typename T>
 void vcycle(mlsgd_ctx* c, Plan* P) {
   hipStream_t s = c->stream;
@@ -472,10 +675,41 @@ void vcycle(mlsgd_ctx* c, Plan* P) {
 }
 
 void precondition(mlsgd_ctx* c, Plan* P) {
-  if (c->mixed)
-    vcycle<float>(c, P);
-  else
-    vcycle<double>(c, P);
+  const bool cached = c->mixed ? c->cache32 : c->cache64;
+  const int sm = (c->smoother == 1 && !cached) ? 0 : c->smoother;
+  if (c->mixed) {
+    if (sm == 2)
+      vcycle_cheb<float>(c, P);
+    else if (sm == 1)
+      vcycle_fused<float>(c, P);
+    else
+      vcycle<float>(c, P);
+  } else {
+    if (sm == 2)
+      vcycle_cheb<double>(c, P);
+    else if (sm == 1)
+      vcycle_fused<double>(c, P);
+    else
+      vcycle<double>(c, P);
+  }
+}
+
+// true when the preconditioner leaves z in X or R according to `cur`
+bool out_of_place(const mlsgd_ctx* c) {
+  const bool cached = c->mixed ? c->cache32 : c->cache64;
+  return c->smoother == 2 || (c->smoother == 1 && cached);
+}
+
+// z rows of a group after the preconditioner (where the cycle left them)
+const double* z64(mlsgd_ctx* c, Plan* P, const Group& gr) {
+  SizeLvl& L = P->sizes[gr.sl];
+  const double* A = (out_of_place(c) && L.cur) ? L.R : L.X;
+  return A + (size_t)gr.p0 * cube(gr.n);
+}
+const float* z32(mlsgd_ctx* c, Plan* P, const Group& gr) {
+  SizeLvl& L = P->sizes[gr.sl];
+  const float* A = (out_of_place(c) && L.cur) ? L.Rf : L.Xf;
+  return A + (size_t)gr.p0 * cube(gr.n);
 }
 
 int read_count(mlsgd_ctx* c) {
@@ -520,11 +754,11 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
         GridArgs g = args_group(c, P, gr, true);
         SizeLvl& L = P->sizes[gr.sl];
         if (mg && c->mixed) {
-          const float* z = L.Xf + (size_t)gr.p0 * cube(gr.n);
+          const float* z = z32(c, P, gr);
           march_matvec<double, float>(g, z, gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q, P->d_poff,
                                       P->d_partial, s);
         } else {
-          const double* z = mg ? rows_of(L.X, gr) : rows_of(L.B, gr);
+          const double* z = mg ? z64(c, P, gr) : rows_of(L.B, gr);
           march_matvec<double, double>(g, z, gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q, P->d_poff,
                                        P->d_partial, s);
         }
@@ -912,10 +1146,18 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     c->pb = *pb;
     c->stream = (hipStream_t)stream;
     c->mixed = pb->precision == MLSGD_MIXED_FP32;
+    // measured defaults (Chebyshev smoothing; degree and interval per precision)
+    c->nu = c->mixed ? 3 : 2;
+    c->cheb_lo = c->mixed ? 0.1 : 0.25;
     if (const char* e = getenv("MLSGD_NU")) c->nu = std::max(1, atoi(e));
     if (const char* e = getenv("MLSGD_OMEGA")) c->omega = atof(e);
     if (const char* e = getenv("MLSGD_CACHE64")) c->cache64 = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_CACHE32")) c->cache32 = atoi(e) != 0;
+    if (const char* e = getenv("MLSGD_SMOOTHER")) {
+      const std::string v(e);
+      c->smoother = v == "rbgs" ? 0 : v == "rbfused" ? 1 : 2;
+    }
+    if (const char* e = getenv("MLSGD_CHEB_LO")) c->cheb_lo = atof(e);
     c->nfin = pb->grid_n[pb->n_levels - 1];
     const size_t NF = cube(c->nfin);
     c->d_f = (double*)dalloc(c.get(), sizeof(double) * NF);

@@ -210,3 +210,31 @@ def test_mixed_precision_gradient(mm, orc, theta, sigma2):
     assert _rel(g.cpu().numpy(), go) <= 1e-8
     assert st["J"] == pytest.approx(so["J"], rel=1e-10)
     ctx.close()
+
+
+@pytest.mark.parametrize("env", [
+    {"MLSGD_SMOOTHER": "rbgs", "MLSGD_CACHE64": "0", "MLSGD_CACHE32": "0"},  # regenerated in-sweep
+    {"MLSGD_SMOOTHER": "rbgs", "MLSGD_NU": "1"},                             # RB-GS V(1,1)
+    {"MLSGD_SMOOTHER": "rbgs", "MLSGD_OMEGA": "1.15", "MLSGD_NU": "3"},      # over-relaxed V(3,3)
+    {"MLSGD_SMOOTHER": "rbfused", "MLSGD_NU": "2"},                          # fused red-black sweeps
+    {"MLSGD_SMOOTHER": "cheb", "MLSGD_NU": "3", "MLSGD_CHEB_LO": "0.25"},    # Chebyshev degree 3
+    {"MLSGD_SMOOTHER": "cheb", "MLSGD_CACHE64": "0", "MLSGD_CACHE32": "0"},  # Chebyshev, regenerated
+])
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_solver_variants(mm, orc, monkeypatch, env, precision):
+    """Every smoother / coefficient variant reaches the same estimate."""
+    print("variant", env, precision, flush=True)
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    grid, M = [9, 17, 33], [16, 6, 3]
+    nL = grid[-1]
+    yd = inputs.target_sin(nL)
+    u = inputs.control_xyz(nL) + 15.0 * yd
+    prec = mm.FP64 if precision == "fp64" else mm.MIXED_FP32
+    ctx = _ctx(mm, grid, theta=2.0, alpha=1e-3, sigma2=2.0, rtol=1e-12, precision=prec)
+    g, st = ctx.mlmc_gradient(u, M, first=[1, 1, 1])
+    pb = orc.make_problem(grid, theta=2.0, alpha=1e-3, sigma2=2.0, rtol=1e-14)
+    go, so = orc.mlmc_gradient(pb, None, u, yd, M, first=[1, 1, 1])
+    assert st["nonconverged"] == 0
+    assert _rel(g.cpu().numpy(), go) <= (1e-9 if precision == "fp64" else 1e-8)
+    ctx.close()
