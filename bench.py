@@ -25,7 +25,7 @@ if ROOT not in sys.path:
 
 METRIC = "MLMC gradient estimates/s + state/adjoint solves/s, mixed vs FP64, % HBM peak"
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_gs_pass_129.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_jacobi_step_129.json")
 
 
 def parse():
@@ -36,6 +36,11 @@ def parse():
     ap.add_argument("--workload", default="mlmc_129")
     ap.add_argument("--mixed-workload", default="mlmc_129_mixed")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-per-sample", action="store_true")
+    ap.add_argument("--mlsgd", action="store_true",
+                    help="run the adaptive MLSGD optimisation on the 257^3 workload instead")
+    ap.add_argument("--mlsgd-steps", type=int, default=50)
+    ap.add_argument("--thetas", default="1,5,10")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -116,6 +121,69 @@ def same_samples_error(m, w_fast, w_ref, dev):
     return float(torch.linalg.norm(g1 - g2) / torch.linalg.norm(g2))
 
 
+def per_sample_fp64(m, w, dev, reps=2):
+    """The plain FP64 GPU solver without batching: state and adjoint solves of
+    one sample per call (same kernels, one problem per launch sequence), timed
+    per grid and extrapolated to the workload's sample counts."""
+    import dataclasses
+    import torch
+    w64 = dataclasses.replace(w, precision="fp64")
+    ctx = make_ctx(m, w64, dev)
+    u = torch.as_tensor(w64.u0(), device=dev).contiguous()
+    per = []
+    for i in range(len(w64.grid_n)):
+        t_level = 0.0
+        for coarse in ([0, 1] if i > 0 else [0]):
+            ctx.solve_state_adjoint(i, coarse, 0, 1, u, want_y=False)   # warm the plan
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            for r in range(reps):
+                ctx.solve_state_adjoint(i, coarse, 1 + r, 1, u, want_y=False)
+            torch.cuda.synchronize()
+            t_level += (time.perf_counter() - t) / reps
+        per.append(t_level)
+    ctx.close()
+    est = sum(mm * tp for mm, tp in zip(w64.M, per))
+    return {"value": 1.0 / est, "unit": "gradient estimates/s",
+            "seconds_per_sample_by_level": per,
+            "sample": f"{reps} samples per grid after one warm-up call, extrapolated to M={list(w64.M)}"}
+
+
+def run_mlsgd(args):
+    """Adaptive MLSGD (Algorithm 1): projected steps with step size 1/(1+j),
+    batch sizes chosen by the controller after every step."""
+    import torch
+    import paper_2606_09291_amd as m
+    from paper_2606_09291_amd import inputs
+    w = inputs.WORKLOADS["adaptive_257"]
+    dev = torch.device("cuda:0")
+    out = {"workload": w.name, "runs": []}
+    for th in [float(x) for x in args.thetas.split(",")]:
+        import dataclasses
+        wt = dataclasses.replace(w, theta=th)
+        ctx = make_ctx(m, wt, dev)
+        u = torch.as_tensor(wt.u0(), device=dev).contiguous()
+        ctx.set_batch(wt.M)
+        recs = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(args.mlsgd_steps):
+            st = ctx.step(u, 1.0 / (1.0 + j), adapt=True)
+            g = st["grad"]
+            recs.append({"step": j, "J": g["J"], "grad_norm": g["grad_norm"], "M": st["M_next"],
+                         "err_sam": st["err_sam"], "err_num": st["err_num"], "eps": st["eps"],
+                         "iters": [g["iters_state"], g["iters_adjoint"]], "ms": g["ms_total"]})
+            log(args, f"theta {th} step {j}: J {g['J']:.6e} |g| {g['grad_norm']:.4e} "
+                      f"M_next {st['M_next']} {g['ms_total']:.1f} ms")
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        ctx.close()
+        out["runs"].append({"theta": th, "seconds": dt, "steps": args.mlsgd_steps,
+                            "final_J": recs[-1]["J"], "final_grad_norm": recs[-1]["grad_norm"],
+                            "records": recs})
+    print(json.dumps(out), flush=True)
+
+
 def cpu_baseline(w, threads):
     """The oracle timed on the host cores: per level i, P pairs of level i
     (fine + coarse state and adjoint solves) run on P threads; the per-pair
@@ -185,6 +253,9 @@ def main():
     if args.copy_calibration:
         copy_calibration(args)
         return
+    if args.mlsgd:
+        run_mlsgd(args)
+        return
     import torch
     import paper_2606_09291_amd as m
     from paper_2606_09291_amd import inputs
@@ -226,7 +297,8 @@ def main():
         "iters_adjoint": max(s["iters_adjoint"] for s in stats),
         "max_relres": max(s["max_relres"] for s in stats),
         "roofline": {
-            "kernel": f"red-black smoothing pass (k_march OP_GS) on the {nfin}^3 rows",
+            "kernel": (f"Chebyshev smoothing step (k_march OP_JAC, damped Jacobi, cached 1/a) "
+                       f"on the {nfin}^3 rows"),
             "bound": "hbm",
             "achieved": achieved,
             "peak": HBM_PEAK_GBS,
@@ -262,6 +334,23 @@ def main():
             "smoothing_pass_frac": bpl_m / (avg_m * 1e-3) / 1e9 / HBM_PEAK_GBS,
             "speedup_vs_fp64_batched": vm / value,
         }
+        wb = inputs.WORKLOADS["mlmc_129_bf16"]
+        log(args, "bfloat16-smoother workload")
+        rb = run(args, m, wb, dev, args.steps, args.warmup)
+        vb = args.steps / rb["dt"]
+        out["mixed_bf16"] = {
+            "workload": wb.name, "value": vb, "unit": "gradient estimates/s",
+            "ms_per_step": 1e3 * rb["dt"] / args.steps,
+            "iters_state": max(s["iters_state"] for s in rb["stats"]),
+            "iters_adjoint": max(s["iters_adjoint"] for s in rb["stats"]),
+            "grad_rel_err_vs_fp64_same_samples": same_samples_error(m, wb, wb, dev),
+        }
+    if not args.no_per_sample:
+        log(args, "per-sample FP64 comparator")
+        ps = per_sample_fp64(m, inputs.WORKLOADS[args.mixed_workload], dev)
+        out["fp64_per_sample"] = ps
+        if "mixed" in out:
+            out["mixed"]["speedup_vs_fp64_per_sample"] = out["mixed"]["value"] / ps["value"]
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         log(args, f"cpu baseline with {threads} threads")

@@ -47,6 +47,7 @@ class OrStats(ctypes.Structure):
         ("m2_dX", ctypes.c_double * OR_MAX_LEVELS),
         ("m2_dY", ctypes.c_double * OR_MAX_LEVELS),
         ("mean_phi_f", ctypes.c_double * OR_MAX_LEVELS),
+        ("norm2_EX", ctypes.c_double),
     ]
 
     def as_dict(self, L):
@@ -58,6 +59,7 @@ class OrStats(ctypes.Structure):
             "norm2_mean_dX": list(self.norm2_mean_dX)[:L],
             "m2_dX": list(self.m2_dX)[:L], "m2_dY": list(self.m2_dY)[:L],
             "mean_phi_f": list(self.mean_phi_f)[:L],
+            "norm2_EX": self.norm2_EX,
         }
 
 
@@ -201,7 +203,7 @@ def make_problem(grid_n, seed=0, K=4, sigma2=1.0, theta=1.0, alpha=1e-3,
     pb.method = method
     pb.rtol = rtol
     pb.maxit = maxit
-    pb.nthreads = nthreads if nthreads else (os.cpu_count() or 1)
+    pb.nthreads = nthreads if nthreads else min(16, os.cpu_count() or 1)
     pb.common_xi = 1 if common_xi else 0
     return pb
 

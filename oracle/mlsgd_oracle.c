@@ -868,6 +868,7 @@ int or_mlmc_gradient(const or_problem* pb, const double* f, const double* u,
   }
   int nL = pb->n[L - 1];
   size_t NL = (size_t)nL * nL * nL;
+  st.norm2_EX = norm2_h(nL, acc);
   double denom;
   if (th > 0.0) {
     double floor_ = exp(-th * s);

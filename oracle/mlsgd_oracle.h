@@ -68,6 +68,7 @@ typedef struct or_stats {
   double m2_dX[OR_MAX_LEVELS];         /* sum_m || dX_m - E_i[dX] ||^2_h */
   double m2_dY[OR_MAX_LEVELS];         /* sum_m | dY_m - E_i[dY] |^2 */
   double mean_phi_f[OR_MAX_LEVELS];    /* mean misfit on the fine grid */
+  double norm2_EX;                     /* |E^ML[X]|_h^2, shifted units */
 } or_stats;
 
 void or_philox4x64_10(const uint64_t ctr[4], const uint64_t key[2], uint64_t out[4]);

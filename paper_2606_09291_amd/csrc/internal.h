@@ -46,6 +46,7 @@ struct GridArgs {
   const CgScal* scal;   // per problem; inactive problems are skipped (nullable)
   double ih2;           // 1/h^2
   const void* cache;    // [problem][n^3] cached 1/a of the compute type, or null
+  int cache_bf16;       // FP32 sweeps: the cache holds bfloat16 values
 };
 
 // ---- stencil kernels (marching LDS tiles, coefficient regenerated) ----
@@ -69,7 +70,7 @@ void rb_sweep(const GridArgs& g, const T* xin, const T* xc, const T* b, T* xout,
               int first_color, int x_zero, const int* poff, double* partial, int top_begin,
               double omega, hipStream_t s);
 void coef_cache(int n, int rows, const double* coef, int K, const double* cosT, double* out64,
-                float* out32, hipStream_t s);
+                float* out32, uint16_t* out16, hipStream_t s);
 
 // ---- batched grid transfers (rows of one grid size) ----
 template <typename T>

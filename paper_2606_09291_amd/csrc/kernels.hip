@@ -36,6 +36,13 @@ __device__ __forceinline__ double drcp(double d) {
 }
 __device__ __forceinline__ float drcp(float d) { return __builtin_amdgcn_rcpf(d); }
 
+// bfloat16 storage: round to nearest even from FP32, widen by a shift.
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  const uint32_t u = __float_as_uint(f);
+  return (uint16_t)((u + 0x7FFFu + ((u >> 16) & 1u)) >> 16);
+}
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
 // Harmonic face coefficient from the reciprocal vertex coefficients
 // b = 1/a:  2 a_v a_w / (a_v + a_w) = 2 / (b_v + b_w).
 template <typename T>
@@ -82,13 +89,19 @@ Tiling make_tiling(int n) {
   } else {
     static const int ty64 = [] {
       const char* e = getenv("MLSGD_TY64");
-      return (e && atoi(e) == 4) ? 4 : 8;
+      const int v = e ? atoi(e) : 8;
+      return (v == 4 || v == 16) ? v : 8;
     }();
     t.TY = ty64; t.TZ = 64;
   }
+  static const int xch = [] {
+    const char* e = getenv("MLSGD_XCHUNK");
+    const int v = e ? atoi(e) : 32;
+    return v >= 8 ? v : 32;
+  }();
   t.nty = cdiv(m, t.TY);
   t.ntz = cdiv(m, t.TZ);
-  t.xchunk = m <= 32 ? m : 32;
+  t.xchunk = m <= xch ? m : xch;
   t.nxc = cdiv(m, t.xchunk);
   t.tiles_per_row = t.nty * t.ntz * t.nxc;
   return t;
@@ -194,11 +207,12 @@ struct ProlongCol {
 
 enum MarchOp { OP_RESID = 0, OP_MATVEC = 1, OP_GS = 2, OP_JAC = 3, OP_JACP = 4 };
 
-template <typename T, typename TI, int TY, int TZ, int OP, bool CACHED>
+template <typename T, typename TI, int TY, int TZ, int OP, int CK>
 __global__ void __launch_bounds__(TY* TZ)
     k_march(GridArgs g, const TI* in, const T* in2, const T* rhs, T* out, T* out2,
             const int* __restrict__ poff, double* __restrict__ partial, int color,
             int x_zero, int top_begin, T omega) {
+  constexpr bool CACHED = CK != 0;   // 0: regenerate, 1: cache of type T, 2: bfloat16 cache
   constexpr int NT = TY * TZ;
   constexpr int PZ = TZ + 2;
   constexpr int PLANE = (TY + 2) * PZ;
@@ -229,6 +243,7 @@ __global__ void __launch_bounds__(TY* TZ)
 
   const size_t base = (size_t)row * (size_t)g.stride;
   const T* __restrict__ cache = (const T*)g.cache + (size_t)prob * (size_t)g.stride;
+  const uint16_t* __restrict__ cache16 = (const uint16_t*)g.cache + (size_t)prob * (size_t)g.stride;
   const double* __restrict__ cosT = g.cosT;
   const int tid = threadIdx.x;
   const int ly = tid / TZ, lz = tid - (tid / TZ) * TZ;
@@ -300,7 +315,8 @@ __global__ void __launch_bounds__(TY* TZ)
   };
   // reciprocal coefficient 1/a = exp(-log a) at (ix, jy, jz)
   auto coefb = [&](int ix, int jy, int jz, const T* S) -> T {
-    if (CACHED) return cache[((size_t)ix * n + jy) * n + jz];
+    if (CK == 1) return cache[((size_t)ix * n + jy) * n + jz];
+    if (CK == 2) return (T)from_bf16(cache16[((size_t)ix * n + jy) * n + jz]);
     T l = T(0);
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
@@ -431,13 +447,13 @@ __global__ void __launch_bounds__(TY* TZ)
   }
 }
 
-template <typename T, typename TI, int OP, bool CACHED>
+template <typename T, typename TI, int OP, int CK>
 static void launch_march2(const GridArgs& g, const TI* in, const T* in2, const T* rhs, T* out,
                           T* out2, const int* poff, double* partial, int color, int x_zero,
                           int top_begin, T omega, hipStream_t s) {
   const int nblk = g.rows * g.t.tiles_per_row;
 #define MLSGD_LAUNCH(TY_, TZ_)                                                              \
-  hipLaunchKernelGGL((k_march<T, TI, TY_, TZ_, OP, CACHED>), dim3(nblk), dim3(TY_ * TZ_), 0, s, \
+  hipLaunchKernelGGL((k_march<T, TI, TY_, TZ_, OP, CK>), dim3(nblk), dim3(TY_ * TZ_), 0, s, \
                      g, in, in2, rhs, out, out2, poff, partial, color, x_zero, top_begin, omega)
   if (g.t.TZ == 8) {
     MLSGD_LAUNCH(8, 8);
@@ -447,6 +463,8 @@ static void launch_march2(const GridArgs& g, const TI* in, const T* in2, const T
     MLSGD_LAUNCH(8, 32);
   } else if (g.t.TY == 8) {
     MLSGD_LAUNCH(8, 64);
+  } else if (g.t.TY == 16) {
+    MLSGD_LAUNCH(16, 64);
   } else {
     MLSGD_LAUNCH(4, 64);
   }
@@ -458,12 +476,15 @@ static void launch_march(const GridArgs& g, const TI* in, const T* in2, const T*
                          T* out2, const int* poff, double* partial, int color, int x_zero,
                          int top_begin, T omega, hipStream_t s) {
   if (g.rows <= 0) return;
-  if (g.cache)
-    launch_march2<T, TI, OP, true>(g, in, in2, rhs, out, out2, poff, partial, color, x_zero,
-                                   top_begin, omega, s);
+  if (!g.cache)
+    launch_march2<T, TI, OP, 0>(g, in, in2, rhs, out, out2, poff, partial, color, x_zero,
+                                top_begin, omega, s);
+  else if (sizeof(T) == 4 && g.cache_bf16)
+    launch_march2<T, TI, OP, 2>(g, in, in2, rhs, out, out2, poff, partial, color, x_zero,
+                                top_begin, omega, s);
   else
-    launch_march2<T, TI, OP, false>(g, in, in2, rhs, out, out2, poff, partial, color, x_zero,
-                                    top_begin, omega, s);
+    launch_march2<T, TI, OP, 1>(g, in, in2, rhs, out, out2, poff, partial, color, x_zero,
+                                top_begin, omega, s);
 }
 
 template <typename T>
@@ -778,7 +799,7 @@ template void rb_sweep<float>(const GridArgs&, const float*, const float*, const
 __global__ void __launch_bounds__(256)
     k_coef_cache(int n, int rows, const double* __restrict__ coef, int K,
                  const double* __restrict__ cosT, double* __restrict__ out64,
-                 float* __restrict__ out32) {
+                 float* __restrict__ out32, uint16_t* __restrict__ out16) {
   __shared__ double sc[KMAX * KMAX * KMAX];
   const int cols = n * n;
   const int cpb = (cols + 255) / 256;
@@ -812,6 +833,7 @@ __global__ void __launch_bounds__(256)
     const size_t i = base + (size_t)ix * cols;
     if (out64) out64[i] = b;
     if (out32) out32[i] = (float)b;
+    if (out16) out16[i] = to_bf16((float)b);
   }
 }
 
@@ -897,11 +919,11 @@ static int grid_for(long long total, int bs) {
 }
 
 void coef_cache(int n, int rows, const double* coef, int K, const double* cosT, double* out64,
-                float* out32, hipStream_t s) {
-  if (rows <= 0 || (!out64 && !out32)) return;
+                float* out32, uint16_t* out16, hipStream_t s) {
+  if (rows <= 0 || (!out64 && !out32 && !out16)) return;
   const int cpb = (n * n + 255) / 256;
   hipLaunchKernelGGL(k_coef_cache, dim3(rows * cpb), dim3(256), 0, s, n, rows, coef, K, cosT,
-                     out64, out32);
+                     out64, out32, out16);
 }
 
 template <typename T>

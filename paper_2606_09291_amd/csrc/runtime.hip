@@ -62,6 +62,7 @@ struct SizeLvl {
   double* C = nullptr;                              // FP64 cache of 1/a (null: regenerate)
   float *Xf = nullptr, *Bf = nullptr, *Rf = nullptr;  // FP32 multigrid rows (mixed precision)
   float* Cf = nullptr;                              // FP32 cache of 1/a (null: regenerate)
+  uint16_t* Cb = nullptr;                           // bfloat16 cache of 1/a (BF16 smoothing)
   const double* cosT = nullptr;
   int cur = 0;   // fused sweeps: which of X/R (Xf/Rf) holds the current iterate
 };
@@ -145,6 +146,7 @@ struct mlsgd_ctx {
   bool cache64 = true;      // cache 1/a per estimate for FP64 sweeps
   bool cache32 = true;      // cache 1/a per estimate for FP32 sweeps
   bool mixed = false;       // FP32 V-cycles inside the FP64 Krylov iteration
+  bool bf16 = false;        // mixed, with the smoother's coefficient stored as bfloat16
   int smoother = 2;         // 0 red-black GS (two in-place passes), 1 fused red-black, 2 Chebyshev
   double cheb_lo = 1.0 / 6.0;  // Chebyshev interval [cheb_lo * 2, 2] for D^-1 A
   // event timing of the smoothing passes on one grid size (roofline figures)
@@ -274,7 +276,8 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks) {
           s.Xf = cv.take<float>(e);
           s.Bf = cv.take<float>(e);
           s.Rf = cv.take<float>(e);
-          if (c->cache32) s.Cf = cv.take<float>(e);
+          if (c->cache32 && c->bf16) s.Cb = cv.take<uint16_t>(e);
+          else if (c->cache32) s.Cf = cv.take<float>(e);
         }
         if (c->cache64) s.C = cv.take<double>(e);
       }
@@ -322,7 +325,8 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks) {
             c->stream);
   // the coefficient is regenerated from the draws once per call for the
   // cached sweeps (the Krylov matvec and residual always run in FP64)
-  for (auto& sl : P->sizes) coef_cache(sl.n, sl.rows, P->d_coef, K, sl.cosT, sl.C, sl.Cf, c->stream);
+  for (auto& sl : P->sizes)
+    coef_cache(sl.n, sl.rows, P->d_coef, K, sl.cosT, sl.C, sl.Cf, sl.Cb, c->stream);
   HIPCHK(hipGetLastError());
   return P;
 }
@@ -340,13 +344,15 @@ GridArgs args_size(mlsgd_ctx* c, Plan* P, const SizeLvl& s) {
   g.scal = P->d_scal;
   g.ih2 = (double)(s.n - 1) * (double)(s.n - 1);
   g.cache = s.C;
+  g.cache_bf16 = 0;
   return g;
 }
 
 // launch arguments of the FP32 multigrid sweeps on one grid size
 GridArgs args_size32(mlsgd_ctx* c, Plan* P, const SizeLvl& s) {
   GridArgs g = args_size(c, P, s);
-  g.cache = s.Cf;
+  g.cache = s.Cb ? (const void*)s.Cb : (const void*)s.Cf;
+  g.cache_bf16 = s.Cb ? 1 : 0;
   return g;
 }
 
@@ -503,10 +509,11 @@ std::vector<double> cheb_omegas(int deg, double lo) {
 // Algorithmic bytes of one Jacobi step: x read (not from zero), b, 1/a, x'
 // written, coarse rows once when the correction is folded in.
 template <typename T>
-double jac_bytes(int n, int rows, bool x_zero, bool prolong, bool cached) {
+double jac_bytes(int n, int rows, bool x_zero, bool prolong, const GridArgs& g) {
   const double N = (double)rows * (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
   const double e = (double)sizeof(T);
-  double b = 2.0 * e + (x_zero ? 0.0 : e) + (cached ? e : 0.0);
+  const double ce = g.cache ? (g.cache_bf16 ? 2.0 : e) : 0.0;
+  double b = 2.0 * e + (x_zero ? 0.0 : e) + ce;
   if (prolong) b += e / 8.0;
   return N * b;
 }
@@ -530,9 +537,8 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
     MgView<T> v = mg_view<T>(L);
     T* A[2] = {v.X, v.R};
     GridArgs g = args(L);
-    const bool cached = g.cache != nullptr;
     if (k == S - 1) {
-      timed_launch(c, g, jac_bytes<T>(L.n, L.rows, true, false, cached), [&] {
+      timed_launch(c, g, jac_bytes<T>(L.n, L.rows, true, false, g), [&] {
         march_jac<T>(g, nullptr, nullptr, v.B, A[0], 1, 1.0, P->d_poff, P->d_partial, L.top_begin,
                      c->stream);
       });
@@ -540,11 +546,11 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
       break;
     }
     int cur = 0;
-    timed_launch(c, g, jac_bytes<T>(L.n, L.rows, true, false, cached), [&] {
+    timed_launch(c, g, jac_bytes<T>(L.n, L.rows, true, false, g), [&] {
       march_jac<T>(g, nullptr, nullptr, v.B, A[0], 1, om[0], nullptr, nullptr, 0, c->stream);
     });
     for (int j = 1; j < deg; ++j) {
-      timed_launch(c, g, jac_bytes<T>(L.n, L.rows, false, false, cached), [&] {
+      timed_launch(c, g, jac_bytes<T>(L.n, L.rows, false, false, g), [&] {
         march_jac<T>(g, A[cur], nullptr, v.B, A[cur ^ 1], 0, om[j], nullptr, nullptr, 0,
                      c->stream);
       });
@@ -563,16 +569,21 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
     MgView<T> vc = mg_view<T>(Lc);
     const T* xc = Lc.cur ? vc.R : vc.X;
     GridArgs g = args(L);
-    const bool cached = g.cache != nullptr;
     int cur = L.cur;
     for (int j = 0; j < deg; ++j) {
       const bool last = j == deg - 1;
       const T* corr = j == 0 ? xc : nullptr;
-      timed_launch(c, g, jac_bytes<T>(L.n, L.rows, false, j == 0, cached), [&] {
+      if (corr) {   // the step with the folded correction is a separate kernel; not timed
         march_jac<T>(g, A[cur], corr, v.B, A[cur ^ 1], 0, om[deg - 1 - j],
                      last ? P->d_poff : nullptr, last ? P->d_partial : nullptr, L.top_begin,
                      c->stream);
-      });
+      } else {
+        timed_launch(c, g, jac_bytes<T>(L.n, L.rows, false, false, g), [&] {
+          march_jac<T>(g, A[cur], nullptr, v.B, A[cur ^ 1], 0, om[deg - 1 - j],
+                       last ? P->d_poff : nullptr, last ? P->d_partial : nullptr, L.top_begin,
+                       c->stream);
+        });
+      }
       cur ^= 1;
     }
     L.cur = cur;
@@ -676,7 +687,8 @@ void vcycle(mlsgd_ctx* c, Plan* P) {
 
 void precondition(mlsgd_ctx* c, Plan* P) {
   const bool cached = c->mixed ? c->cache32 : c->cache64;
-  const int sm = (c->smoother == 1 && !cached) ? 0 : c->smoother;
+  // the fused red-black kernel reads a cache of the compute type only
+  const int sm = (c->smoother == 1 && (!cached || c->bf16)) ? 0 : c->smoother;
   if (c->mixed) {
     if (sm == 2)
       vcycle_cheb<float>(c, P);
@@ -697,7 +709,7 @@ void precondition(mlsgd_ctx* c, Plan* P) {
 // true when the preconditioner leaves z in X or R according to `cur`
 bool out_of_place(const mlsgd_ctx* c) {
   const bool cached = c->mixed ? c->cache32 : c->cache64;
-  return c->smoother == 2 || (c->smoother == 1 && cached);
+  return c->smoother == 2 || (c->smoother == 1 && cached && !c->bf16);
 }
 
 // z rows of a group after the preconditioner (where the cycle left them)
@@ -1041,17 +1053,23 @@ int run_estimate(mlsgd_ctx* c, const double* u, int L, const int64_t* M, const i
 }
 
 // Adaptive controller (Sec. 4.1): second-order power sums v^2 per level,
-// optimal batch sizes for a sampling error eps^2/2, sampling-error estimate.
-// Units: the paper's unshifted X, Y (statistics are rescaled by e^{theta s}).
-// Costs: the deterministic model C_i = (fine + coarse interior unknowns) per
-// sample, so the batch sequence is reproducible.
-void controller(mlsgd_ctx* c, const mlsgd_grad_stats& g, int L, const int64_t* M,
-                mlsgd_step_stats* out, int64_t* M_next) {
+// optimal batch sizes for a sampling error eps^2/2, sampling-error estimate,
+// squared-bias estimate and the level update.  Units: the paper's unshifted
+// X, Y (statistics are rescaled by e^{theta s}).  Costs: the deterministic
+// model C_i = interior unknowns (fine + coarse) per sample, so the batch
+// sequence is reproducible.  eps = 0.9 |g| of the gradient just computed.
+// M is capped by what fits a 32 GiB share of device memory per level.
+struct CtrlOut {
+  int64_t M[MLSGD_MAX_LEVELS];
+  int L;
+  double err_sam, err_num, eps, alpha_hat;
+};
+
+CtrlOut controller(const mlsgd_ctx* c, const mlsgd_grad_stats& g, int L, const int64_t* M) {
+  CtrlOut o{};
   const double th = c->pb.theta;
   const double sc = std::exp(th * g.s);
-  const double EY = g.EY_shifted * sc;
-  // C_hat = |E^ML X|^2 / E^ML[Y]^2 (the shift cancels in the ratio)
-  const double Chat = g.norm2_EX / (g.EY_shifted * g.EY_shifted);
+  const double Chat = g.norm2_EX / (g.EY_shifted * g.EY_shifted);  // the shift cancels
   double v2[MLSGD_MAX_LEVELS], C[MLSGD_MAX_LEVELS];
   for (int i = 0; i < L; ++i) {
     v2[i] = (g.m2_dX[i] + Chat * g.m2_dY[i]) * sc * sc;
@@ -1059,23 +1077,28 @@ void controller(mlsgd_ctx* c, const mlsgd_grad_stats& g, int L, const int64_t* M
     const double ncs = i > 0 ? (double)(c->pb.grid_n[i - 1] - 2) : 0.0;
     C[i] = nf * nf * nf + ncs * ncs * ncs;
   }
-  const double gn = g.grad_norm;
-  const double eps = 0.9 * (c->prev_gnorm > 0 ? c->prev_gnorm : gn);
+  const double eps = 0.9 * g.grad_norm;
+  o.eps = eps;
   double sum = 0.0;
-  for (int i = 0; i < L; ++i) sum += std::sqrt(v2[i] * C[i] / (double)std::max<int64_t>(M[i] - 1, 1));
+  for (int i = 0; i < L; ++i)
+    sum += std::sqrt(v2[i] * C[i] / (double)std::max<int64_t>(M[i] - 1, 1));
   double err_sam = 0.0;
   for (int i = 0; i < L; ++i) {
     const double Mi = (double)M[i];
     err_sam += v2[i] / (Mi * std::max(Mi - 1.0, 1.0));
     double mo = (2.0 / (eps * eps)) *
                 std::sqrt(v2[i] / ((double)std::max<int64_t>(M[i] - 1, 1) * C[i])) * sum;
-    if (!std::isfinite(mo) || mo > 1e9) mo = 1e9;
-    M_next[i] = std::max<int64_t>(2, (int64_t)std::ceil(mo));
+    const double n = (double)c->pb.grid_n[i];
+    const double per_sample = 14.0 * 8.0 * n * n * n;            // arrays a sample occupies
+    const double mmax = std::max(2.0, std::floor(32.0 * (1ull << 30) / per_sample));
+    if (!std::isfinite(mo) || mo > mmax) mo = mmax;
+    o.M[i] = std::max<int64_t>(2, (int64_t)std::ceil(mo));
   }
-  // squared-bias estimate with rate alpha_hat from a least-squares fit of
-  // log2 sqrt(|E dX_i|^2 + C_hat |E dY_i|^2) over levels 1..L-1 (fallback 2)
+  o.err_sam = err_sam;
+  // alpha_hat: least-squares slope of log2 sqrt(|E dX_i|^2 + C_hat |E dY_i|^2)
+  // over levels 1..L-1 (fallback 2)
   double ahat = 2.0;
-  if (L >= 3) {
+  {
     double sx = 0, sy = 0, sxx = 0, sxy = 0;
     int cnt = 0;
     for (int i = 1; i < L; ++i) {
@@ -1089,20 +1112,23 @@ void controller(mlsgd_ctx* c, const mlsgd_grad_stats& g, int L, const int64_t* M
       if (std::isfinite(slope) && -slope > 0.5) ahat = -slope;
     }
   }
+  o.alpha_hat = ahat;
+  // squared bias, Giles extrapolation of each level's correction to the finest
   double err_num = 0.0;
   for (int i = 1; i < L; ++i) {
     const double e2 = (g.norm2_mean_dX[i] + Chat * g.mean_dY[i] * g.mean_dY[i]) * sc * sc;
-    const double hr = std::pow(2.0, (double)(L - 1 - i));  // h_i / h_L
-    const double d = (std::pow(2.0, ahat) - 1.0);
-    err_num = std::max(err_num, e2 / (d * d) * std::pow(hr, -2.0 * ahat));
+    const double d = std::pow(2.0, ahat) - 1.0;
+    err_num = std::max(err_num, e2 / (d * d) * std::pow(2.0, -2.0 * ahat * (double)(L - 1 - i)));
   }
-  if (out) {
-    out->err_sam = err_sam;
-    out->err_num = err_num;
-    out->eps = eps;
+  o.err_num = err_num;
+  // level update: one more level when the bias dominates (capped at the grid list)
+  o.L = L;
+  if (err_num > 0.5 * eps * eps && L < c->pb.n_levels) {
+    o.M[L] = std::max<int64_t>(2, o.M[L - 1] / 4);
+    o.L = L + 1;
   }
+  return o;
 }
-
 
 int guard_impl(mlsgd_ctx* c, const std::function<int()>& fn) {
   try {
@@ -1135,8 +1161,9 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     require(pb->kl_sigma2 >= 0.0 && std::isfinite(pb->kl_sigma2), "kl_sigma2 must be >= 0");
     require(pb->theta >= 0.0 && std::isfinite(pb->theta), "theta must be >= 0");
     require(pb->alpha >= 0.0 && std::isfinite(pb->alpha), "alpha must be >= 0");
-    require(pb->precision == MLSGD_FP64 || pb->precision == MLSGD_MIXED_FP32,
-            "precision must be MLSGD_FP64 or MLSGD_MIXED_FP32");
+    require(pb->precision == MLSGD_FP64 || pb->precision == MLSGD_MIXED_FP32 ||
+                pb->precision == MLSGD_MIXED_BF16,
+            "precision must be MLSGD_FP64, MLSGD_MIXED_FP32 or MLSGD_MIXED_BF16");
     require(pb->precision == MLSGD_FP64 || pb->solver == MLSGD_SOLVER_MGPCG,
             "mixed precision needs the multigrid solver");
     require(pb->solver == MLSGD_SOLVER_CG || pb->solver == MLSGD_SOLVER_MGPCG, "unknown solver");
@@ -1145,7 +1172,8 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     require(pb->y_d != nullptr, "y_d is null");
     c->pb = *pb;
     c->stream = (hipStream_t)stream;
-    c->mixed = pb->precision == MLSGD_MIXED_FP32;
+    c->mixed = pb->precision == MLSGD_MIXED_FP32 || pb->precision == MLSGD_MIXED_BF16;
+    c->bf16 = pb->precision == MLSGD_MIXED_BF16;
     // measured defaults (Chebyshev smoothing; degree and interval per precision)
     c->nu = c->mixed ? 3 : 2;
     c->cheb_lo = c->mixed ? 0.1 : 0.25;
@@ -1356,14 +1384,17 @@ int mlsgd_step(mlsgd_ctx* c, double* u, double tau, int adapt, mlsgd_step_stats*
     box_step(c->nfin, u, c->d_grad, tau, c->pb.u_lo, c->pb.u_hi, box ? 1 : 0, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
-    int64_t Mn[MLSGD_MAX_LEVELS];
-    for (int i = 0; i < MLSGD_MAX_LEVELS; ++i) Mn[i] = c->cur_M[i];
     mlsgd_step_stats loc{};
-    if (adapt) controller(c, g, c->cur_L, c->cur_M, &loc, Mn);
     for (int i = 0; i < c->cur_L; ++i) c->cur_off[i] += c->cur_M[i];
     c->prev_gnorm = g.grad_norm;
-    if (adapt)
-      for (int i = 0; i < c->cur_L; ++i) c->cur_M[i] = Mn[i];
+    if (adapt) {
+      const CtrlOut o = controller(c, g, c->cur_L, c->cur_M);
+      loc.err_sam = o.err_sam;
+      loc.err_num = o.err_num;
+      loc.eps = o.eps;
+      for (int i = 0; i < o.L; ++i) c->cur_M[i] = o.M[i];
+      c->cur_L = o.L;
+    }
     if (st) {
       loc.grad = g;
       for (int i = 0; i < MLSGD_MAX_LEVELS; ++i) {

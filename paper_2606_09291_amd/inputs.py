@@ -51,6 +51,23 @@ def random_directions(n, count, seed):
     return [rng.standard_normal((n, n, n)) for _ in range(count)]
 
 
+def random_smooth_directions(n, count, seed, kmax=3):
+    """Seeded smooth directions: random combinations of the sine modes
+    prod_d sin(k_d pi x_d), k_d <= kmax (zero on the boundary)."""
+    rng = np.random.default_rng(seed)
+    X, Y, Z = coords(n)
+    modes = []
+    for a in range(1, kmax + 1):
+        for b in range(1, kmax + 1):
+            for c in range(1, kmax + 1):
+                modes.append(np.sin(a * np.pi * X) * np.sin(b * np.pi * Y) * np.sin(c * np.pi * Z))
+    out = []
+    for _ in range(count):
+        w = rng.standard_normal(len(modes))
+        out.append(sum(wi * m for wi, m in zip(w, modes)))
+    return out
+
+
 def grids(first_n, levels):
     """Nested vertex counts n_i = 2 (n_{i-1} - 1) + 1 starting at first_n."""
     out = [first_n]
@@ -103,11 +120,16 @@ WORKLOADS = {
         name="MLMC gradient, levels 9^3..129^3, sigma^2=2, theta=10, FP32 V-cycles in FP64 refinement",
         grid_n=grids(9, 5), M=[4096, 1024, 256, 64, 16], sigma2=2.0, theta=10.0,
         precision="mixed"),
+    "mlmc_129_bf16": Workload(
+        name="MLMC gradient, levels 9^3..129^3, sigma^2=2, theta=10, FP32 V-cycles with bfloat16 "
+             "smoother coefficients in FP64 refinement",
+        grid_n=grids(9, 5), M=[4096, 1024, 256, 64, 16], sigma2=2.0, theta=10.0,
+        precision="mixed_bf16"),
     "mlmc_257_batched": Workload(
         name="MLMC gradient, levels 9^3..257^3, M=8192/2048/512/128/32/8",
-        grid_n=grids(9, 6), M=[8192, 2048, 512, 128, 32, 8], precision="mixed"),
+        grid_n=grids(9, 6), M=[8192, 2048, 512, 128, 32, 8], precision="mixed", rtol=1e-10),
     "adaptive_257": Workload(
         name="adaptive MLSGD, levels 9^3..257^3, K=5, alpha=1e-4, f=1",
         grid_n=grids(9, 6), M=[8192, 2048, 512, 128, 32, 8], K=5, alpha=1e-4,
-        f_value=1.0, u_kind="zero", precision="mixed", steps=50),
+        f_value=1.0, u_kind="zero", precision="mixed", steps=50, rtol=1e-10),
 }

@@ -1,0 +1,67 @@
+"""Pins of the oracle's adaptive controller (Sec. 4.1) against what the
+formulas are designed to achieve, not against a retyped formula."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import controller as ctl
+
+
+def test_optimal_batch_hits_target_and_minimises_cost():
+    """Unrounded M_l meets sum V_l / M_l = eps^2/2 exactly, and any other batch
+    meeting the same sampling error costs more (Lagrange optimum)."""
+    rng = np.random.default_rng(0)
+    for _ in range(20):
+        L = rng.integers(2, 6)
+        M = [int(x) for x in rng.integers(4, 200, size=L)]
+        v2 = list(rng.uniform(0.1, 10.0, size=L))
+        C = list(rng.uniform(1.0, 1e5, size=L))
+        eps = rng.uniform(1e-3, 1.0)
+        raw = ctl.optimal_batch(v2, M, C, eps, ceil=False)
+        V = [v / (m - 1) for v, m in zip(v2, M)]
+        assert sum(Vi / Mi for Vi, Mi in zip(V, raw)) == pytest.approx(eps ** 2 / 2, rel=1e-12)
+        cost = sum(Mi * Ci for Mi, Ci in zip(raw, C))
+        for _ in range(10):
+            w = rng.uniform(0.5, 2.0, size=L)
+            alt = [r * wi for r, wi in zip(raw, w)]
+            s = sum(Vi / Mi for Vi, Mi in zip(V, alt)) / (eps ** 2 / 2)
+            alt = [a * s for a in alt]   # rescale to the same sampling error
+            assert sum(Mi * Ci for Mi, Ci in zip(alt, C)) >= cost * (1 - 1e-12)
+
+
+def test_rounded_batch_meets_target():
+    v2, M, C, eps = [4.0, 1.0, 0.25], [100, 50, 20], [1.0, 8.0, 64.0], 0.05
+    Mo = ctl.optimal_batch(v2, M, C, eps)
+    V = [v / (m - 1) for v, m in zip(v2, M)]
+    assert sum(Vi / Mi for Vi, Mi in zip(V, Mo)) <= eps ** 2 / 2
+    assert all(m >= 2 for m in Mo)
+
+
+def test_rate_fit_and_bias_on_geometric_decay():
+    """Level corrections e_l = c 2^{-a l}: alpha_hat = a exactly, and the bias
+    estimate equals the remaining geometric tail bound of the finest level,
+    e_{L-1}^2 / (2^a - 1)^2."""
+    for a in (1.0, 1.5, 2.0, 3.0):
+        L = 5
+        e = [3.0 * 2.0 ** (-a * i) for i in range(L)]
+        assert ctl.fit_rate(e) == pytest.approx(a, rel=1e-12)
+        e2 = [x * x for x in e]
+        b = ctl.bias_estimate(e2, a, L)
+        assert b == pytest.approx(e2[-1] / (2 ** a - 1) ** 2, rel=1e-12)
+    assert ctl.fit_rate([1.0, 0.0, 0.0]) == 2.0
+
+
+def test_sampling_error_and_level_growth():
+    stats = {"s": 0.1, "EY_shifted": 1.0, "norm2_EX": 0.5,
+             "m2_dX": [3.0, 1.0, 0.2], "m2_dY": [0.3, 0.1, 0.02],
+             "norm2_mean_dX": [1.0, 0.1, 0.05], "mean_dY": [1.0, 0.01, 0.005]}
+    out = ctl.control(stats, [20, 10, 5], [9, 17, 33, 65], theta=0.0, grad_norm=0.01,
+                      n_levels_max=4)
+    v2 = out["v2"]
+    assert out["err_sam"] == pytest.approx(sum(v / (m * (m - 1)) for v, m in zip(v2, [20, 10, 5])))
+    # weak decay 0.05 -> bias far above eps^2/2 = 4e-5: one more level
+    assert out["L"] == 4 and len(out["M_next"]) == 4
+    out2 = ctl.control(stats, [20, 10, 5], [9, 17, 33], theta=0.0, grad_norm=0.01,
+                       n_levels_max=3)
+    assert out2["L"] == 3

@@ -192,17 +192,19 @@ def test_errors(mm):
     ctx2.close()
 
 
-@pytest.mark.parametrize("theta,sigma2", [(1.0, 1.0), (10.0, 2.0)])
-def test_mixed_precision_gradient(mm, orc, theta, sigma2):
-    """FP32 V-cycles inside the FP64 Krylov iteration: the estimate still
-    matches the FP64 oracle (bar 1e-8 relative L2)."""
-    print("mixed gradient", theta, sigma2, flush=True)
+@pytest.mark.parametrize("theta,sigma2,prec", [(1.0, 1.0, "fp32"), (10.0, 2.0, "fp32"),
+                                              (10.0, 2.0, "bf16")])
+def test_mixed_precision_gradient(mm, orc, theta, sigma2, prec):
+    """FP32 V-cycles (bfloat16 smoother coefficients for "bf16") inside the
+    FP64 Krylov iteration: the estimate still matches the FP64 oracle (bar
+    1e-8 relative L2)."""
+    print("mixed gradient", theta, sigma2, prec, flush=True)
     grid, M = [9, 17, 33], [24, 8, 4]
     nL = grid[-1]
     yd = inputs.target_sin(nL)
     u = inputs.control_xyz(nL) + 20.0 * yd
     ctx = _ctx(mm, grid, theta=theta, alpha=1e-3, sigma2=sigma2, rtol=1e-12,
-               precision=mm.MIXED_FP32)
+               precision=mm.MIXED_FP32 if prec == "fp32" else mm.MIXED_BF16)
     g, st = ctx.mlmc_gradient(u, M, first=[2, 0, 5])
     pb = orc.make_problem(grid, theta=theta, alpha=1e-3, sigma2=sigma2, rtol=1e-14)
     go, so = orc.mlmc_gradient(pb, None, u, yd, M, first=[2, 0, 5])
@@ -237,4 +239,34 @@ def test_solver_variants(mm, orc, monkeypatch, env, precision):
     go, so = orc.mlmc_gradient(pb, None, u, yd, M, first=[1, 1, 1])
     assert st["nonconverged"] == 0
     assert _rel(g.cpu().numpy(), go) <= (1e-9 if precision == "fp64" else 1e-8)
+    ctx.close()
+
+
+def test_adaptive_controller_matches_oracle(mm, orc):
+    """mlsgd_step(adapt=1): batch sizes, sampling and bias estimates of the
+    library's controller on its own statistics equal the oracle controller on
+    the oracle's statistics of the same estimate (batch sizes may differ by one
+    where a ceiling argument sits at an integer within rounding)."""
+    import torch
+    from oracle import controller as ctl
+    grid, M = [9, 17, 33], [24, 12, 6]
+    nL = grid[-1]
+    yd = inputs.target_sin(nL)
+    u0 = inputs.control_xyz(nL) + 10.0 * yd
+    ctx = _ctx(mm, grid, theta=2.0, alpha=1e-3, sigma2=2.0)
+    u = torch.as_tensor(u0, device="cuda:0").contiguous()
+    ctx.set_batch(M)
+    st = ctx.step(u, 0.5, adapt=True)
+    pb = orc.make_problem(grid, theta=2.0, alpha=1e-3, sigma2=2.0, rtol=1e-14)
+    go, so = orc.mlmc_gradient(pb, None, u0, yd, M)
+    h = 1.0 / (nL - 1)
+    gn = math.sqrt(h ** 3 * float(np.sum(go[1:-1, 1:-1, 1:-1] ** 2)))
+    assert st["grad"]["grad_norm"] == pytest.approx(gn, rel=1e-9)
+    out = ctl.control(so, M, grid, theta=2.0, grad_norm=gn, n_levels_max=3)
+    assert st["eps"] == pytest.approx(out["eps"], rel=1e-9)
+    assert st["err_sam"] == pytest.approx(out["err_sam"], rel=1e-7)
+    assert st["err_num"] == pytest.approx(out["err_num"], rel=1e-6)
+    for a, b in zip(st["M_next"], out["M_next"]):
+        assert abs(a - b) <= 1
+    assert st["offset"] == M
     ctx.close()
