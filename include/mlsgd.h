@@ -190,9 +190,31 @@ int mlsgd_set_batch(mlsgd_ctx* ctx, int L, const int64_t* M,
 int mlsgd_step(mlsgd_ctx* ctx, double* u_inout, double tau, int adapt,
                mlsgd_step_stats* st);
 
-/* Event timing of the red-black smoothing passes on grid size n (the
- * dominant kernel of the solves), for roofline figures.  Each launch on that
- * grid is bracketed by HIP events on the context's stream.  The call first
+/* Solver tuning of a context (smoother, cycle and tile parameters).  The
+ * defaults come from measurement on MI355X; mlsgd_set_tuning replaces them,
+ * e.g. with the choice of the package's autotuner, and drops the cached
+ * layouts (the next call rebuilds them).  Any tuning reaches the same
+ * estimate to solver tolerance; only the speed differs. */
+#define MLSGD_SMOOTHER_RBGS 0       /* red-black Gauss-Seidel, two passes per sweep */
+#define MLSGD_SMOOTHER_RBGS_FUSED 1 /* red-black Gauss-Seidel, one fused pass per sweep */
+#define MLSGD_SMOOTHER_CHEBYSHEV 2  /* Chebyshev steps of D^-1 A on [2 cheb_lo, 2] */
+
+typedef struct mlsgd_tuning {
+  int32_t smoother;   /* MLSGD_SMOOTHER_* */
+  int32_t sweeps;     /* smoothing sweeps (Chebyshev degree) before and after the coarse correction */
+  double omega;       /* red-black relaxation weight, (0, 2) */
+  double cheb_lo;     /* lower end of the Chebyshev interval as a fraction of 2, (0, 1) */
+  int32_t tile_y;     /* y extent of the stencil tiles on grids with > 32 interior points: 4, 8, 16 */
+  int32_t xchunk;     /* x planes marched by one workgroup, 8..1024 */
+  int32_t cache;      /* 1: coefficient regenerated once per call into a cache; 0: in every sweep */
+} mlsgd_tuning;
+
+int mlsgd_get_tuning(const mlsgd_ctx* ctx, mlsgd_tuning* out);
+int mlsgd_set_tuning(mlsgd_ctx* ctx, const mlsgd_tuning* tuning);
+
+/* Event timing of the smoothing kernel on grid size n (the dominant kernel
+ * of the solves), for roofline figures.  Each launch of the plain smoothing
+ * step on that grid is bracketed by HIP events on the context's stream.  The call first
  * returns the totals accumulated so far (host outputs, nullable: summed
  * milliseconds, launch count, algorithmic bytes = interior points x bytes the
  * pass must move), then, if enable >= 0, resets them and switches timing on

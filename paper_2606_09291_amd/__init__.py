@@ -23,7 +23,10 @@ EXPORTS = [
     "mlsgd_create", "mlsgd_destroy", "mlsgd_last_error", "mlsgd_sample_fields",
     "mlsgd_philox_words", "mlsgd_solve_state_adjoint", "mlsgd_mlmc_gradient",
     "mlsgd_mlmc_objective", "mlsgd_set_batch", "mlsgd_step", "mlsgd_kernel_timing",
+    "mlsgd_get_tuning", "mlsgd_set_tuning",
 ]
+SMOOTHER_RBGS, SMOOTHER_RBGS_FUSED, SMOOTHER_CHEBYSHEV = 0, 1, 2
+TUNING_FILE = os.path.join(HERE, "tuning.json")
 
 
 class MlsgdError(RuntimeError):
@@ -84,6 +87,15 @@ class _GradStats(ctypes.Structure):
         return d
 
 
+class _Tuning(ctypes.Structure):
+    _fields_ = [("smoother", ctypes.c_int32), ("sweeps", ctypes.c_int32), ("omega", ctypes.c_double),
+                ("cheb_lo", ctypes.c_double), ("tile_y", ctypes.c_int32), ("xchunk", ctypes.c_int32),
+                ("cache", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
 class _StepStats(ctypes.Structure):
     _fields_ = [("grad", _GradStats), ("M_next", ctypes.c_int64 * MAX_LEVELS),
                 ("offset", ctypes.c_int64 * MAX_LEVELS), ("err_sam", ctypes.c_double),
@@ -119,6 +131,8 @@ def lib():
     L.mlsgd_step.argtypes = [vp, vp, ctypes.c_double, i32, P(_StepStats)]
     L.mlsgd_kernel_timing.argtypes = [vp, i32, i32, P(ctypes.c_double), P(i64),
                                       P(ctypes.c_double)]
+    L.mlsgd_get_tuning.argtypes = [vp, P(_Tuning)]
+    L.mlsgd_set_tuning.argtypes = [vp, P(_Tuning)]
     for name in EXPORTS:
         getattr(L, name)
     _lib = L
@@ -166,7 +180,7 @@ class Problem:
 class Context:
     """One libmlsgd context bound to a CUDA (HIP) device and stream."""
 
-    def __init__(self, problem: Problem, device="cuda:0", stream=None):
+    def __init__(self, problem: Problem, device="cuda:0", stream=None, use_tuned=True):
         torch = _torch()
         self.lib = lib()
         self.device = torch.device(device)
@@ -201,6 +215,10 @@ class Context:
         if rc != MLSGD_OK:
             raise MlsgdError(rc, "mlsgd_create failed (invalid problem or HIP error)")
         self._h = h
+        if use_tuned:
+            t = tuned_for(self.problem)
+            if t is not None:
+                self.set_tuning(**t)
 
     def close(self):
         if getattr(self, "_h", None):
@@ -302,6 +320,18 @@ class Context:
                 "eps": st.eps}
 
 
+    def get_tuning(self):
+        t = _Tuning()
+        self._check(self.lib.mlsgd_get_tuning(self._h, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **kw):
+        """Change solver/tile parameters (see mlsgd_tuning in include/mlsgd.h)."""
+        cur = self.get_tuning()
+        cur.update({k: v for k, v in kw.items() if k in cur})
+        t = _Tuning(**cur)
+        self._check(self.lib.mlsgd_set_tuning(self._h, ctypes.byref(t)))
+
     def kernel_timing(self, enable, n=0):
         """Read the smoothing-pass event totals, then (enable >= 0) reset and
         switch timing on for grid n (1) or off (0)."""
@@ -312,6 +342,24 @@ class Context:
                                           ctypes.byref(cnt), ctypes.byref(by))
         self._check(rc)
         return {"ms": ms.value, "launches": cnt.value, "bytes": by.value}
+
+
+def tuning_key(problem):
+    """Key of the autotuner's cache: precision, solver and grid list."""
+    return f"gfx950:p{int(problem.precision)}:s{int(problem.solver)}:" + "x".join(
+        str(int(n)) for n in problem.grid_n)
+
+
+def tuned_for(problem):
+    """Tuning chosen by the autotuner for this kind of problem, if any."""
+    import json
+    try:
+        with open(TUNING_FILE) as fh:
+            table = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    entry = table.get(tuning_key(problem))
+    return entry.get("tuning") if entry else None
 
 
 def philox_words(seed, level, sample, tag, nblocks, device="cuda:0"):

@@ -20,7 +20,9 @@ struct Tiling {
   int tiles_per_row;
 };
 
-Tiling make_tiling(int n);
+// tile_y: y extent of the tiles on grids with more than 32 interior points
+// (4, 8 or 16); xchunk: x planes per workgroup.
+Tiling make_tiling(int n, int tile_y, int xchunk);
 
 // Per-problem state of the batched Krylov solves (all FP64).
 struct CgScal {

@@ -77,7 +77,7 @@ __device__ __forceinline__ double block_sum(double v, double* sred) {
 
 static inline int cdiv(long long a, long long b) { return (int)((a + b - 1) / b); }
 
-Tiling make_tiling(int n) {
+Tiling make_tiling(int n, int tile_y, int xchunk) {
   const int m = n - 2;
   Tiling t;
   if (m <= 8) {
@@ -87,18 +87,10 @@ Tiling make_tiling(int n) {
   } else if (m <= 32) {
     t.TY = 8; t.TZ = 32;
   } else {
-    static const int ty64 = [] {
-      const char* e = getenv("MLSGD_TY64");
-      const int v = e ? atoi(e) : 8;
-      return (v == 4 || v == 16) ? v : 8;
-    }();
-    t.TY = ty64; t.TZ = 64;
+    t.TY = (tile_y == 4 || tile_y == 16) ? tile_y : 8;
+    t.TZ = 64;
   }
-  static const int xch = [] {
-    const char* e = getenv("MLSGD_XCHUNK");
-    const int v = e ? atoi(e) : 32;
-    return v >= 8 ? v : 32;
-  }();
+  const int xch = xchunk >= 8 ? xchunk : 32;
   t.nty = cdiv(m, t.TY);
   t.ntz = cdiv(m, t.TZ);
   t.xchunk = m <= xch ? m : xch;

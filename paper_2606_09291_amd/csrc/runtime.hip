@@ -149,6 +149,8 @@ struct mlsgd_ctx {
   bool bf16 = false;        // mixed, with the smoother's coefficient stored as bfloat16
   int smoother = 2;         // 0 red-black GS (two in-place passes), 1 fused red-black, 2 Chebyshev
   double cheb_lo = 1.0 / 6.0;  // Chebyshev interval [cheb_lo * 2, 2] for D^-1 A
+  int tile_y = 8;           // y extent of the stencil tiles on large grids
+  int xchunk = 32;          // x planes per workgroup
   // event timing of the smoothing passes on one grid size (roofline figures)
   struct Timing {
     bool on = false;
@@ -238,7 +240,7 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks) {
     for (int n = nmax;; n = (n - 1) / 2 + 1) {
       SizeLvl s;
       s.n = n;
-      s.t = make_tiling(n);
+      s.t = make_tiling(n, c->tile_y, c->xchunk);
       int rows = 0, top = 0;
       for (int q = 0; q < P->nprob; ++q) {
         if (P->h_n[q] >= n) rows = q + 1;
@@ -258,7 +260,7 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks) {
     P->h_poff.resize(np);
     long long off = 0;
     for (int q = 0; q < P->nprob; ++q) {
-      P->h_pcnt[q] = make_tiling(P->h_n[q]).tiles_per_row;
+      P->h_pcnt[q] = make_tiling(P->h_n[q], c->tile_y, c->xchunk).tiles_per_row;
       P->h_poff[q] = (int)off;
       off += P->h_pcnt[q];
     }
@@ -687,8 +689,9 @@ void vcycle(mlsgd_ctx* c, Plan* P) {
 
 void precondition(mlsgd_ctx* c, Plan* P) {
   const bool cached = c->mixed ? c->cache32 : c->cache64;
-  // the fused red-black kernel reads a cache of the compute type only
-  const int sm = (c->smoother == 1 && (!cached || c->bf16)) ? 0 : c->smoother;
+  // the fused red-black kernel reads a cache of the compute type only and
+  // exists for tiles of 4 or 8 rows
+  const int sm = (c->smoother == 1 && (!cached || c->bf16 || c->tile_y == 16)) ? 0 : c->smoother;
   if (c->mixed) {
     if (sm == 2)
       vcycle_cheb<float>(c, P);
@@ -709,7 +712,7 @@ void precondition(mlsgd_ctx* c, Plan* P) {
 // true when the preconditioner leaves z in X or R according to `cur`
 bool out_of_place(const mlsgd_ctx* c) {
   const bool cached = c->mixed ? c->cache32 : c->cache64;
-  return c->smoother == 2 || (c->smoother == 1 && cached && !c->bf16);
+  return c->smoother == 2 || (c->smoother == 1 && cached && !c->bf16 && c->tile_y != 16);
 }
 
 // z rows of a group after the preconditioner (where the cycle left them)
@@ -1186,6 +1189,8 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
       c->smoother = v == "rbgs" ? 0 : v == "rbfused" ? 1 : 2;
     }
     if (const char* e = getenv("MLSGD_CHEB_LO")) c->cheb_lo = atof(e);
+    if (const char* e = getenv("MLSGD_TY64")) c->tile_y = atoi(e);
+    if (const char* e = getenv("MLSGD_XCHUNK")) c->xchunk = atoi(e);
     c->nfin = pb->grid_n[pb->n_levels - 1];
     const size_t NF = cube(c->nfin);
     c->d_f = (double*)dalloc(c.get(), sizeof(double) * NF);
@@ -1247,6 +1252,44 @@ int mlsgd_kernel_timing(mlsgd_ctx* c, int enable, int n, double* ms_total, int64
       c->tm.total_bytes = 0.0;
       c->tm.launches = 0;
     }
+    return MLSGD_OK;
+  });
+}
+
+int mlsgd_get_tuning(const mlsgd_ctx* c, mlsgd_tuning* t) {
+  if (!c || !t) return MLSGD_EINVAL;
+  t->smoother = c->smoother;
+  t->sweeps = c->nu;
+  t->omega = c->omega;
+  t->cheb_lo = c->cheb_lo;
+  t->tile_y = c->tile_y;
+  t->xchunk = c->xchunk;
+  t->cache = c->mixed ? (c->cache32 ? 1 : 0) : (c->cache64 ? 1 : 0);
+  return MLSGD_OK;
+}
+
+int mlsgd_set_tuning(mlsgd_ctx* c, const mlsgd_tuning* t) {
+  if (!c) return MLSGD_EINVAL;
+  return guard_impl(c, [&]() -> int {
+    require(t != nullptr, "tuning is null");
+    require(t->smoother >= 0 && t->smoother <= 2, "unknown smoother");
+    require(t->sweeps >= 1 && t->sweeps <= 8, "sweeps must be in 1..8");
+    require(t->omega > 0.0 && t->omega < 2.0, "omega must be in (0, 2)");
+    require(t->cheb_lo > 0.0 && t->cheb_lo < 1.0, "cheb_lo must be in (0, 1)");
+    require(t->tile_y == 4 || t->tile_y == 8 || t->tile_y == 16, "tile_y must be 4, 8 or 16");
+    require(t->xchunk >= 8 && t->xchunk <= 1024, "xchunk must be in 8..1024");
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->smoother = t->smoother;
+    c->nu = t->sweeps;
+    c->omega = t->omega;
+    c->cheb_lo = t->cheb_lo;
+    c->tile_y = t->tile_y;
+    c->xchunk = t->xchunk;
+    if (c->mixed)
+      c->cache32 = t->cache != 0;
+    else
+      c->cache64 = t->cache != 0;
+    c->plans.clear();   // layouts depend on the tiling and the caches
     return MLSGD_OK;
   });
 }

@@ -1,0 +1,93 @@
+"""Autotuner: picks smoother, cycle and tile parameters for a workload by
+timing complete MLMC gradient estimates on the GPU, and records the winner in
+``tuning.json`` (keyed by precision, solver and grid list), which
+``Context`` applies on creation.
+
+    python -m paper_2606_09291_amd.tune --workload mlmc_129 [--reps 2]
+
+Every candidate computes the same estimate to solver tolerance; a candidate
+is kept only if its gradient agrees with the default's to 1e-10 relative L2.
+"""
+import argparse
+import itertools
+import json
+import os
+import sys
+import time
+
+
+def candidates(precision):
+    cand = []
+    for deg, lo in itertools.product([2, 3, 4], [0.1, 0.25]):
+        cand.append({"smoother": 2, "sweeps": deg, "cheb_lo": lo})
+    cand.append({"smoother": 0, "sweeps": 2, "omega": 1.0})
+    cand.append({"smoother": 1, "sweeps": 2, "omega": 1.0})
+    tiles = [{"tile_y": 8, "xchunk": 32}, {"tile_y": 8, "xchunk": 64}, {"tile_y": 4, "xchunk": 32},
+             {"tile_y": 16, "xchunk": 32}]
+    out = []
+    for c in cand:
+        for t in tiles:
+            d = dict(c)
+            d.update(t)
+            out.append(d)
+    return out
+
+
+def tune(workload, reps=2, device="cuda:0", log=print):
+    import torch
+    import paper_2606_09291_amd as m
+    from paper_2606_09291_amd import inputs
+    w = inputs.WORKLOADS[workload] if isinstance(workload, str) else workload
+    prec = {"fp64": m.FP64, "mixed": m.MIXED_FP32, "mixed_bf16": m.MIXED_BF16}[w.precision]
+    solver = m.SOLVER_CG if w.solver == "cg" else m.SOLVER_MGPCG
+    pb = m.Problem(grid_n=w.grid_n, y_d=w.y_d(), f=w.f() if w.f_value else None, seed=w.seed,
+                   K=w.K, sigma2=w.sigma2, theta=w.theta, alpha=w.alpha, precision=prec,
+                   solver=solver, rtol=w.rtol, max_iters=200)
+    ctx = m.Context(pb, device=device, use_tuned=False)
+    u = torch.as_tensor(w.u0(), device=device).contiguous()
+    base = ctx.get_tuning()
+    g_ref, _ = ctx.mlmc_gradient(u, w.M)
+    results = []
+    for cand in candidates(w.precision):
+        t = dict(base)
+        t.update(cand)
+        ctx.set_tuning(**t)
+        g, _ = ctx.mlmc_gradient(u, w.M)           # warm-up and plan build
+        err = float(torch.linalg.norm(g - g_ref) / torch.linalg.norm(g_ref))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for r in range(reps):
+            ctx.mlmc_gradient(u, w.M, first=[(r + 1) * mm for mm in w.M])
+        torch.cuda.synchronize()
+        ms = 1e3 * (time.perf_counter() - t0) / reps
+        results.append({"tuning": t, "ms": ms, "err": err})
+        log(f"{ms:8.2f} ms  err {err:.1e}  {cand}")
+    ctx.close()
+    ok = [r for r in results if r["err"] <= 1e-10]
+    best = min(ok, key=lambda r: r["ms"])
+    return pb, best, results
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="mlmc_129")
+    ap.add_argument("--reps", type=int, default=2)
+    ap.add_argument("--write", action="store_true", help="record the winner in tuning.json")
+    args = ap.parse_args()
+    import paper_2606_09291_amd as m
+    pb, best, results = tune(args.workload, args.reps, log=lambda s: print(s, file=sys.stderr,
+                                                                          flush=True))
+    key = m.tuning_key(pb)
+    print(json.dumps({"key": key, "best": best, "n_candidates": len(results)}), flush=True)
+    if args.write:
+        table = {}
+        if os.path.exists(m.TUNING_FILE):
+            with open(m.TUNING_FILE) as fh:
+                table = json.load(fh)
+        table[key] = {"tuning": best["tuning"], "ms": best["ms"], "workload": args.workload}
+        with open(m.TUNING_FILE, "w") as fh:
+            json.dump(table, fh, indent=1, sort_keys=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -270,3 +270,48 @@ def test_adaptive_controller_matches_oracle(mm, orc):
         assert abs(a - b) <= 1
     assert st["offset"] == M
     ctx.close()
+
+
+@pytest.mark.parametrize("tuning", [
+    {"tile_y": 8, "xchunk": 32}, {"tile_y": 4, "xchunk": 16}, {"tile_y": 16, "xchunk": 64},
+    {"tile_y": 8, "xchunk": 24, "smoother": 1, "sweeps": 2},
+    {"tile_y": 4, "xchunk": 40, "smoother": 0, "sweeps": 1}])
+def test_tiles_on_65_grid(mm, orc, tuning):
+    """Grids with 64-wide tiles (n >= 65), every tile height and several
+    x-chunk lengths (ragged last chunk) against the oracle."""
+    print("tiles", tuning, flush=True)
+    grid, M = [17, 33, 65], [6, 3, 2]
+    nL = grid[-1]
+    yd = inputs.target_sin(nL)
+    u = inputs.control_xyz(nL) + 15.0 * yd
+    ctx = _ctx(mm, grid, theta=1.0, alpha=1e-3, sigma2=2.0, rtol=1e-12)
+    ctx.set_tuning(**tuning)
+    assert ctx.get_tuning()["tile_y"] == tuning["tile_y"]
+    g, st = ctx.mlmc_gradient(u, M)
+    pb = orc.make_problem(grid, theta=1.0, alpha=1e-3, sigma2=2.0, rtol=1e-13)
+    go, so = orc.mlmc_gradient(pb, None, u, yd, M)
+    assert _rel(g.cpu().numpy(), go) <= 1e-9
+    ctx.close()
+
+
+@pytest.mark.parametrize("workload,bar", [("mlmc_129", 1e-9), ("mlmc_129_mixed", 1e-8)])
+def test_full_size_estimate_matches_oracle(mm, orc, workload, bar):
+    """The benchmark's workload at full size and in its launch configuration
+    (levels 9^3..129^3, M = 4096/1024/256/64/16) against the complete oracle
+    gradient computed on the host cores."""
+    import torch
+    import bench
+    w = inputs.WORKLOADS[workload]
+    print("full size", workload, flush=True)
+    ctx = bench.make_ctx(mm, w, torch.device("cuda:0"))
+    u = w.u0()
+    g, st = ctx.mlmc_gradient(u, w.M, first=[1] * len(w.M))
+    ctx.close()
+    pb = orc.make_problem(w.grid_n, K=w.K, sigma2=w.sigma2, theta=w.theta, alpha=w.alpha,
+                          rtol=1e-12)
+    go, so = orc.mlmc_gradient(pb, None, u, w.y_d(), w.M, first=[1] * len(w.M))
+    err = _rel(g.cpu().numpy(), go)
+    print("full-size relative L2 error", err, flush=True)
+    assert err <= bar
+    assert st["J"] == pytest.approx(so["J"], rel=1e-10)
+    assert st["EY_shifted"] == pytest.approx(so["EY_shifted"], rel=1e-10)
