@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--mixed-workload", default="mlmc_129_mixed")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-per-sample", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the single-level SGD and 257^3 batched legs")
     ap.add_argument("--mlsgd", action="store_true",
                     help="run the adaptive MLSGD optimisation on the 257^3 workload instead")
     ap.add_argument("--mlsgd-steps", type=int, default=50)
@@ -149,6 +151,32 @@ def per_sample_fp64(m, w, dev, reps=2):
             "sample": f"{reps} samples per grid after one warm-up call, extrapolated to M={list(w64.M)}"}
 
 
+def single_level_sgd(m, dev, steps=5):
+    """The single-level workload: 17^3, 64 fresh samples per step, CG to 1e-12,
+    theta = 1, alpha = 1e-3, u_0 = 0, five projected steps with tau = 10."""
+    import torch
+    from paper_2606_09291_amd import inputs
+    w = inputs.WORKLOADS["single_level_17"]
+    ctx = make_ctx(m, w, dev)
+    u = torch.zeros((w.grid_n[0],) * 3, dtype=torch.float64, device=dev)
+    ctx.set_batch(w.M)
+    ctx.step(u, w.tau)        # warm-up step (plan build)
+    u.zero_()
+    ctx.set_batch(w.M)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    recs = []
+    for j in range(steps):
+        st = ctx.step(u, w.tau)
+        recs.append({"J": st["grad"]["J"], "grad_norm": st["grad"]["grad_norm"],
+                     "iters": st["grad"]["iters_state"]})
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    return {"workload": w.name, "steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps,
+            "records": recs}
+
+
 def run_mlsgd(args):
     """Adaptive MLSGD (Algorithm 1): projected steps with step size 1/(1+j),
     batch sizes chosen by the controller after every step."""
@@ -219,10 +247,11 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
-def traffic_for(launch_points):
-    """HBM bytes per launch of the timed kernel from the committed counter
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factor), or
-    None when the kernels changed since the counters were taken."""
+def traffic_for(launch_bytes):
+    """HBM bytes per launch of the timed kernel: the committed counter summary
+    (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factors) gives traffic
+    over algorithmic bytes for these launches; None when the kernels changed
+    since the counters were taken."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -230,7 +259,7 @@ def traffic_for(launch_points):
         return None
     if t.get("source_hash") != source_hash():
         return None
-    return t.get("bytes_per_launch")
+    return t["traffic_over_algorithmic"] * launch_bytes
 
 
 def copy_calibration(args):
@@ -345,6 +374,19 @@ def main():
             "iters_adjoint": max(s["iters_adjoint"] for s in rb["stats"]),
             "grad_rel_err_vs_fp64_same_samples": same_samples_error(m, wb, wb, dev),
         }
+    if not args.no_extra:
+        log(args, "single-level SGD workload")
+        out["single_level_sgd"] = single_level_sgd(m, dev)
+        wb257 = inputs.WORKLOADS["mlmc_257_batched"]
+        log(args, "batched 9^3..257^3 workload")
+        r257 = run(args, m, wb257, dev, max(2, args.steps // 2), 1)
+        s257, u257 = problem_counts(wb257.grid_n, wb257.M)
+        v257 = max(2, args.steps // 2) / r257["dt"]
+        out["batched_257"] = {"workload": wb257.name, "value": v257, "unit": "gradient estimates/s",
+                              "ms_per_step": 1e3 / v257, "solves_per_s": s257 * v257,
+                              "unknown_solves_per_s": u257 * v257,
+                              "iters_state": max(x["iters_state"] for x in r257["stats"]),
+                              "iters_adjoint": max(x["iters_adjoint"] for x in r257["stats"])}
     if not args.no_per_sample:
         log(args, "per-sample FP64 comparator")
         ps = per_sample_fp64(m, inputs.WORKLOADS[args.mixed_workload], dev)

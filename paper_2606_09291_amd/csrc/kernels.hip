@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 namespace mlsgd {
 
@@ -146,55 +147,49 @@ __device__ __forceinline__ T prolong_val(int nc, const T* __restrict__ c, int ix
   return w * v;
 }
 
-// Trilinear prolongation along one fine (y, z) column while marching in x:
-// the (y, z)-bilinear value of each coarse plane is formed once (up to four
-// taps) and kept for the three fine planes that use it.
+// Trilinear prolongation along one fine (y, z) column while marching in x.
+// The workgroup stages each coarse plane of its tile's footprint once in an
+// LDS ring (four planes); a column forms the (y, z)-bilinear value of a
+// coarse plane from four LDS taps and keeps it for the three fine planes that
+// use it.  A missing second tap in y or z is read at offset 0:
+// 0.25 ((a + a) + (b + b)) equals 0.5 (a + b) exactly, so one formula serves
+// every column parity.  Calls to at() come with ix increasing by one.
 template <typename T>
-struct ProlongCol {
-  const T* c;      // coarse row + (y, z) offset of the lower tap
-  int ncnc, dy, dz;  // plane stride; upper-tap offsets (0: no second tap in y / z)
-  int j1;
-  T v0, v1;        // bilinear values of coarse planes j1 - 1 and j1
-  __device__ void init(const T* crow, int nc, int jy, int jz) {
-    ncnc = nc * nc;
-    c = crow + (jy >> 1) * nc + (jz >> 1);
-    dy = (jy & 1) ? nc : 0;
-    dz = (jz & 1) ? 1 : 0;
-    j1 = -2;
-    v0 = v1 = T(0);
+struct ProlongLds {
+  int lc, dyl, dzl, ja;  // slab offset of the lower taps, upper-tap offsets
+  T v0, v1;              // bilinear values of coarse planes ja, ja + 1
+  __device__ T bil(const T* ring, int cslab, int j) const {
+    const T* p = ring + (j & 3) * cslab + lc;
+    return T(0.25) * ((p[0] + p[dzl]) + (p[dyl] + p[dyl + dzl]));
   }
-  __device__ T bilinear(int j) const {
-    const T* p = c + (size_t)j * ncnc;
-    T v = p[0];
-    if (dz) v = T(0.5) * (v + p[dz]);
-    if (dy) {
-      T w = p[dy];
-      if (dz) w = T(0.5) * (w + p[dy + dz]);
-      v = T(0.5) * (v + w);
-    }
-    return v;
+  __device__ void init(const T* ring, int cslab, int czn, int cy0, int cz0, int jy, int jz,
+                       int ix0) {
+    lc = ((jy >> 1) - cy0) * czn + ((jz >> 1) - cz0);
+    dyl = (jy & 1) ? czn : 0;
+    dzl = (jz & 1) ? 1 : 0;
+    ja = ix0 >> 1;
+    v0 = bil(ring, cslab, ja);
+    v1 = bil(ring, cslab, ja + 1);
   }
-  // value of coarse plane j; planes are requested in non-decreasing order
-  __device__ T plane(int j) {
-    if (j == j1) return v1;
-    if (j == j1 - 1) return v0;
-    if (j == j1 + 1) {
-      v0 = v1;
-    } else {
-      v0 = j > 0 ? bilinear(j - 1) : T(0);
-    }
-    v1 = bilinear(j);
-    j1 = j;
-    return v1;
-  }
-  __device__ T at(int ix) {
+  __device__ T at(const T* ring, int cslab, int ix) {
     const int j = ix >> 1;
-    if (ix & 1) {
-      const T hi = plane(j + 1);
-      return T(0.5) * (v0 + hi);
+    if (j + (ix & 1) > ja + 1) {
+      v0 = v1;
+      ++ja;
+      v1 = bil(ring, cslab, ja + 1);
     }
-    return plane(j);
+    if (ix & 1) return T(0.5) * (v0 + v1);
+    return j == ja ? v0 : v1;
   }
+};
+
+// A value as loaded (r, and for OP_MATVEC the old direction, for OP_JACP the
+// prolonged correction, in c); it is combined one plane after the load was
+// issued, so the loads of the two-plane-ahead prefetch stay in flight.
+template <typename T, typename TI>
+struct Ld {
+  TI r;
+  T c;
 };
 
 enum MarchOp { OP_RESID = 0, OP_MATVEC = 1, OP_GS = 2, OP_JAC = 3, OP_JACP = 4 };
@@ -264,21 +259,53 @@ __global__ void __launch_bounds__(TY* TZ)
   T beta = T(0);
   if (OP == OP_MATVEC) beta = (T)g.scal[prob].beta;
 
-  ProlongCol<T> pco, pch;   // prolongation state of the own and the halo column
-  if (OP == OP_JACP) {
-    const int nc = (n - 1) / 2 + 1;
-    const T* crow = in2 + (size_t)row * ((size_t)nc * nc * nc);
-    pco.init(crow, nc, min(iy, n - 1), min(iz, n - 1));
-    pch.init(crow, nc, hy, hz);
-  }
-  auto ld = [&](int ix, int jy, int jz, ProlongCol<T>& pc) -> T {
-    if (x_zero) return T(0);
-    if (ix <= 0 || ix >= n - 1 || jy <= 0 || jy >= n - 1 || jz <= 0 || jz >= n - 1) return T(0);
-    const size_t idx = base + ((size_t)ix * n + jy) * n + jz;
-    if (OP == OP_MATVEC) return (T)in[idx] + beta * in2[idx];
-    if (OP == OP_JACP) return (T)in[idx] + pc.at(ix);
-    return (T)in[idx];
+  const int x0 = 1 + xc * g.t.xchunk;
+  const int x1 = min(x0 + g.t.xchunk, n - 1);
+  using LdT = Ld<T, TI>;
+  auto interior = [&](int ix, int jy, int jz) {
+    return ix > 0 && ix < n - 1 && jy > 0 && jy < n - 1 && jz > 0 && jz < n - 1;
   };
+  auto ldr = [&](int ix, int jy, int jz) -> LdT {
+    LdT v{TI(0), T(0)};
+    if (x_zero || !interior(ix, jy, jz)) return v;
+    const size_t idx = base + ((size_t)ix * n + jy) * n + jz;
+    v.r = in[idx];
+    if (OP == OP_MATVEC) v.c = in2[idx];
+    return v;
+  };
+  auto full = [&](const LdT& v) -> T {
+    if (OP == OP_MATVEC) return (T)v.r + beta * v.c;
+    if (OP == OP_JACP) return (T)v.r + v.c;
+    return (T)v.r;
+  };
+
+  // OP_JACP: coarse-plane ring.  Lane l < CSLAB owns slab point
+  // (cy0 + l / CZN, cz0 + l % CZN); plane J sits in slot J & 3.  Plane J is
+  // stored before the barrier of the first plane whose correction needs it
+  // and its global load is issued two planes earlier.
+  constexpr int CYN = TY / 2 + 2, CZN = TZ / 2 + 2;
+  constexpr int CSLAB = CYN * CZN;
+  static_assert(CSLAB <= NT, "coarse slab larger than the workgroup");
+  __shared__ T scs[OP == OP_JACP ? 4 * CSLAB : 1];
+  const int nc = (n - 1) / 2 + 1;
+  const T* crow = in2 + (size_t)row * ((size_t)nc * nc * nc);
+  const int cy0 = (y0 - 1) >> 1, cz0 = (z0 - 1) >> 1;
+  bool cld = false;
+  size_t coff = 0;
+  if (OP == OP_JACP && tid < CSLAB) {
+    const int gy = cy0 + tid / CZN, gz = cz0 + tid % CZN;
+    cld = gy <= nc - 1 && gz <= nc - 1;
+    coff = (size_t)gy * nc + gz;
+  }
+  auto cload = [&](int J) -> T {
+    return (cld && J <= nc - 1) ? crow[(size_t)J * nc * nc + coff] : T(0);
+  };
+  auto cstore = [&](int J, T v) {
+    if (tid < CSLAB) scs[(J & 3) * CSLAB + tid] = v;
+  };
+  ProlongLds<T> pco, pch;  // prolongation state of the own and the halo column
+  int chi = 0;             // highest coarse plane stored
+  T cnext = T(0);          // plane chi + 1, in flight
 
   auto compS = [&](int jy, int jz, T* S) {
     T cy[KMAX], cz[KMAX];
@@ -305,15 +332,28 @@ __global__ void __launch_bounds__(TY* TZ)
       S[k1] = acc;
     }
   };
-  // reciprocal coefficient 1/a = exp(-log a) at (ix, jy, jz)
-  auto coefb = [&](int ix, int jy, int jz, const T* S) -> T {
-    if (CK == 1) return cache[((size_t)ix * n + jy) * n + jz];
-    if (CK == 2) return (T)from_bf16(cache16[((size_t)ix * n + jy) * n + jz]);
-    T l = T(0);
+  // reciprocal coefficient 1/a = exp(-log a) at (ix, jy, jz), as stored
+  // (bfloat16 bits for the bfloat16 cache, widened by cvt when used)
+  using CR = typename std::conditional<CK == 2, uint16_t, T>::type;
+  const CR one = CK == 2 ? CR(0x3F80) : CR(1);
+  auto coefr = [&](int ix, int jy, int jz, const T* S) -> CR {
+    if constexpr (CK == 1) {
+      return cache[((size_t)ix * n + jy) * n + jz];
+    } else if constexpr (CK == 2) {
+      return cache16[((size_t)ix * n + jy) * n + jz];
+    } else {
+      T l = T(0);
 #pragma unroll
-    for (int k = 0; k < KMAX; ++k)
-      if (k < K) l += (T)cosT[k * n + ix] * S[k];
-    return dexp(-l);
+      for (int k = 0; k < KMAX; ++k)
+        if (k < K) l += (T)cosT[k * n + ix] * S[k];
+      return dexp(-l);
+    }
+  };
+  auto cvt = [&](CR v) -> T {
+    if constexpr (CK == 2)
+      return (T)from_bf16(v);
+    else
+      return v;
   };
 
   T Sm[KMAX], Sh[KMAX];
@@ -327,32 +367,61 @@ __global__ void __launch_bounds__(TY* TZ)
     if (has_halo) compS(hy, hz, Sh);
   }
 
-  const int x0 = 1 + xc * g.t.xchunk;
-  const int x1 = min(x0 + g.t.xchunk, n - 1);
   const T ih2 = (T)g.ih2;
 
   // Software pipeline: x and 1/a of the own column and of the halo slot are
-  // fetched two planes ahead, the right-hand side one plane ahead, so no
-  // plane waits on a memory round trip of its own.
-  T xm = T(0), xcur = T(0), xp = T(0), bm = T(1), bc = T(1), bp = T(1);
+  // fetched two planes ahead, the right-hand side one plane ahead; loaded
+  // values are combined (direction update, prolonged correction, widening)
+  // one plane after their loads were issued, so no plane waits on a memory
+  // round trip of its own.
+  T bm = T(1), bc = T(1);
+  LdT xmr{TI(0), T(0)}, xcr{TI(0), T(0)};
+  LdT xn{TI(0), T(0)};  // plane x + 1 of the own column, as loaded
+  CR bn = one;
   if (inside) {
-    xm = ld(x0 - 1, iy, iz, pco);
-    xcur = ld(x0, iy, iz, pco);
-    xp = ld(x0 + 1, iy, iz, pco);
-    bm = coefb(x0 - 1, iy, iz, Sm);
-    bc = coefb(x0, iy, iz, Sm);
-    bp = coefb(x0 + 1, iy, iz, Sm);
+    xmr = ldr(x0 - 1, iy, iz);
+    xcr = ldr(x0, iy, iz);
+    xn = ldr(x0 + 1, iy, iz);
+    bm = cvt(coefr(x0 - 1, iy, iz, Sm));
+    bc = cvt(coefr(x0, iy, iz, Sm));
+    bn = coefr(x0 + 1, iy, iz, Sm);
   }
-  T fxm = face(bm, bc);
-  T hcur = T(0), hnext = T(0), hbc = T(1), hbn = T(1);
+  LdT hcr{TI(0), T(0)}, hn{TI(0), T(0)};
+  T hbc = T(1);
+  CR hbn = one;
   if (has_halo) {
-    hcur = ld(x0, hy, hz, pch);
-    hbc = coefb(x0, hy, hz, Sh);
+    hcr = ldr(x0, hy, hz);
+    hbc = cvt(coefr(x0, hy, hz, Sh));
     if (x0 + 1 < x1) {
-      hnext = ld(x0 + 1, hy, hz, pch);
-      hbn = coefb(x0 + 1, hy, hz, Sh);
+      hn = ldr(x0 + 1, hy, hz);
+      hbn = coefr(x0 + 1, hy, hz, Sh);
     }
   }
+  // prolonged correction of plane ix of a column (zero where x is)
+  auto corr = [&](ProlongLds<T>& pc, int ix, int jy, int jz) -> T {
+    const T v = pc.at(scs, CSLAB, ix);
+    return (!x_zero && interior(ix, jy, jz)) ? v : T(0);
+  };
+  if (OP == OP_JACP) {
+    const int jlo = (x0 - 1) >> 1;
+    chi = (x0 + 3) >> 1;
+    for (int J = jlo; J <= chi; ++J) cstore(J, cload(J));
+    cnext = cload(chi + 1);
+    __syncthreads();
+    if (inside) {
+      pco.init(scs, CSLAB, CZN, cy0, cz0, iy, iz, x0 - 1);
+      xmr.c = corr(pco, x0 - 1, iy, iz);
+      xcr.c = corr(pco, x0, iy, iz);
+      xn.c = corr(pco, x0 + 1, iy, iz);
+    }
+    if (has_halo) {
+      pch.init(scs, CSLAB, CZN, cy0, cz0, hy, hz, x0);
+      hcr.c = corr(pch, x0, hy, hz);
+      if (x0 + 1 < x1) hn.c = corr(pch, x0 + 1, hy, hz);
+    }
+  }
+  T xm = full(xmr), xcur = full(xcr), hcur = full(hcr);
+  T fxm = face(bm, bc);
   constexpr bool USES_B = (OP == OP_RESID || OP == OP_GS || OP == OP_JAC || OP == OP_JACP);
   T bv = T(0);
   if (USES_B && own) bv = rhs[base + ((size_t)x0 * n + iy) * n + iz];
@@ -363,16 +432,25 @@ __global__ void __launch_bounds__(TY* TZ)
   for (int ix = x0; ix < x1; ++ix) {
     const int buf = ix & 1;
     // prefetch: plane ix+2 of the columns, plane ix+1 of the right-hand side
-    T xpp = T(0), bpp = T(1), hnn = T(0), hbnn = T(1), bvn = T(0);
-    if (inside && ix + 2 <= n - 1) {
-      xpp = ld(ix + 2, iy, iz, pco);
-      bpp = coefb(ix + 2, iy, iz, Sm);
+    const bool own_next = inside && ix + 2 <= n - 1;
+    const bool halo_next = has_halo && ix + 2 < x1;
+    LdT xnn{TI(0), T(0)}, hnn{TI(0), T(0)};
+    CR bnn = one, hbnn = one;
+    T bvn = T(0);
+    if (own_next) {
+      xnn = ldr(ix + 2, iy, iz);
+      bnn = coefr(ix + 2, iy, iz, Sm);
     }
-    if (has_halo && ix + 2 < x1) {
-      hnn = ld(ix + 2, hy, hz, pch);
-      hbnn = coefb(ix + 2, hy, hz, Sh);
+    if (halo_next) {
+      hnn = ldr(ix + 2, hy, hz);
+      hbnn = coefr(ix + 2, hy, hz, Sh);
     }
-    if (USES_B && own && ix + 1 < x1) bvn = rhs[base + ((size_t)(ix + 1) * n + iy) * n + iz];
+    if (USES_B && own && ix + 1 < x1) bvn = __builtin_nontemporal_load(&rhs[base + ((size_t)(ix + 1) * n + iy) * n + iz]);
+    if (OP == OP_JACP && ((ix + 3) >> 1) > chi) {
+      ++chi;
+      cstore(chi, cnext);
+      cnext = cload(chi + 1);
+    }
     sx[buf][cidx] = inside ? xcur : T(0);
     sb[buf][cidx] = inside ? bc : T(1);
     if (tid < NH) {
@@ -380,6 +458,12 @@ __global__ void __launch_bounds__(TY* TZ)
       sb[buf][hidx] = has_halo ? hbc : T(1);
     }
     __syncthreads();
+    if (OP == OP_JACP) {
+      if (own_next) xnn.c = corr(pco, ix + 2, iy, iz);
+      if (halo_next) hnn.c = corr(pch, ix + 2, hy, hz);
+    }
+    const T xp = full(xn);
+    const T bp = cvt(bn);
     const T fxp = face(bc, bp);
     if (own) {
       const T xym = sx[buf][cidx - PZ], xyp = sx[buf][cidx + PZ];
@@ -390,15 +474,15 @@ __global__ void __launch_bounds__(TY* TZ)
       const T off = ((fxm * xm + fxp * xp) + (fym * xym + fyp * xyp)) + (fzm * xzm + fzp * xzp);
       const size_t idx = base + ((size_t)ix * n + iy) * n + iz;
       if (OP == OP_RESID) {
-        out[idx] = bv - ih2 * (diag * xcur - off);
+        __builtin_nontemporal_store(bv - ih2 * (diag * xcur - off), &out[idx]);
       } else if (OP == OP_MATVEC) {
         const T q = ih2 * (diag * xcur - off);
-        out[idx] = q;
-        out2[idx] = xcur;
+        __builtin_nontemporal_store(q, &out[idx]);
+        __builtin_nontemporal_store(xcur, &out2[idx]);
         dot += (double)xcur * (double)q;
       } else if (OP == OP_JAC || OP == OP_JACP) {
         const T val = xcur + omega * (bv - ih2 * (diag * xcur - off)) * drcp(ih2 * diag);
-        out[idx] = val;
+        __builtin_nontemporal_store(val, &out[idx]);
         if (partial) dot += (double)bv * (double)val;
       } else {  // OP_GS
         T val = xcur;
@@ -419,14 +503,14 @@ __global__ void __launch_bounds__(TY* TZ)
     }
     xm = xcur;
     xcur = xp;
-    xp = xpp;
+    xn = xnn;
     bm = bc;
     bc = bp;
-    bp = bpp;
+    bn = bnn;
     fxm = fxp;
-    hcur = hnext;
-    hnext = hnn;
-    hbc = hbn;
+    hcur = full(hn);
+    hbc = cvt(hbn);
+    hn = hnn;
     hbn = hbnn;
     bv = bvn;
   }
@@ -1107,8 +1191,9 @@ enum GroupOp { G_DOT = 0, G_UPDATE = 1, G_MISFIT = 2 };
 
 template <int OP>
 __global__ void __launch_bounds__(256)
-    k_group(GridArgs g, double* a, const double* b, double* c, const double* d,
-            const int* __restrict__ poff, double* __restrict__ partial, float* cf) {
+    k_group(GridArgs g, double* __restrict__ a, const double* __restrict__ b,
+            double* __restrict__ c, const double* __restrict__ d, const int* __restrict__ poff,
+            double* __restrict__ partial, float* __restrict__ cf) {
   __shared__ double sred[4];
   const int tpr = g.t.tiles_per_row;
   const int row = blockIdx.x / tpr;
@@ -1125,12 +1210,37 @@ __global__ void __launch_bounds__(256)
   if (OP == G_DOT) {
     for (long long i = lo + threadIdx.x; i < hi; i += 256) acc += a[base + i] * b[base + i];
   } else if (OP == G_UPDATE) {
+    // x += alpha p, r -= alpha q; four elements per thread in flight (the
+    // per-thread summation order of <r, r> is the plain ascending one)
     const double al = g.scal[prob].alpha;
-    for (long long i = lo + threadIdx.x; i < hi; i += 256) {
-      a[base + i] += al * b[base + i];
-      const double r = c[base + i] - al * d[base + i];
-      c[base + i] = r;
-      if (cf) cf[base + i] = (float)r;
+    constexpr int U = 4;
+    long long i = lo + threadIdx.x;
+    for (; i + (U - 1) * 256 < hi; i += U * 256) {
+      double xa[U], pb[U], rc[U], qd[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const size_t k = base + i + u * 256;
+        xa[u] = a[k];
+        pb[u] = b[k];
+        rc[u] = c[k];
+        qd[u] = d[k];
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const size_t k = base + i + u * 256;
+        a[k] = xa[u] + al * pb[u];
+        const double r = rc[u] - al * qd[u];
+        c[k] = r;
+        if (cf) cf[k] = (float)r;
+        acc += r * r;
+      }
+    }
+    for (; i < hi; i += 256) {
+      const size_t k = base + i;
+      a[k] = a[k] + al * b[k];
+      const double r = c[k] - al * d[k];
+      c[k] = r;
+      if (cf) cf[k] = (float)r;
       acc += r * r;
     }
   } else {  // G_MISFIT: a = y (reset to 0 afterwards), b = y_d (shared), c = adjoint rhs rows
