@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--mixed-workload", default="mlmc_129_mixed")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-per-sample", action="store_true")
+    ap.add_argument("--graph", action="store_true",
+                    help="run the main workload as one replayed HIP graph per estimate")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the single-level SGD and 257^3 batched legs")
     ap.add_argument("--mlsgd", action="store_true",
@@ -78,10 +80,16 @@ def make_ctx(m, w, dev):
     return m.Context(pb, device=dev)
 
 
-def run(args, m, w, dev, steps, warmup, timing_n=None):
-    """Warm up, then time `steps` estimates with fresh samples each."""
+def run(args, m, w, dev, steps, warmup, timing_n=None, graph=False):
+    """Warm up, then time `steps` estimates with fresh samples each.  graph:
+    the first warm-up call captures the batch shape as a HIP graph and every
+    later call replays it (no event timing then)."""
     import torch
     ctx = make_ctx(m, w, dev)
+    if graph:
+        ctx.set_graph(True)
+        timing_n = None
+        warmup = max(warmup, 1)
     u = torch.as_tensor(w.u0(), device=dev).contiguous()
     L = len(w.grid_n)
     off = [0] * L
@@ -175,6 +183,34 @@ def single_level_sgd(m, dev, steps=5):
     ctx.close()
     return {"workload": w.name, "steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps,
             "records": recs}
+
+
+def odd_size_solves(m, dev, reps=3):
+    """The batch of 300 independent state solves on grids of random size in
+    {33, 41, 49, 57, 65} (f = 1, u = 0) that accompanies the 257^3 MLMC
+    workload, in its precision (mixed) and tolerance."""
+    import torch
+    from paper_2606_09291_amd import inputs
+    cfg = inputs.ODD_SOLVES
+    w = inputs.WORKLOADS["mlmc_257_batched"]
+    sizes = inputs.odd_sizes(cfg["count"], seed=cfg["seed"], level=cfg["level"],
+                             first=cfg["first"])
+    ctx = make_ctx(m, w, dev)
+    ctx.solve_sizes(sizes, level=cfg["level"], first=cfg["first"], f_value=cfg["f_value"])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for r in range(reps):
+        _, st = ctx.solve_sizes(sizes, level=cfg["level"], first=cfg["first"] + r * cfg["count"],
+                                f_value=cfg["f_value"])
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    ctx.close()
+    unknowns = sum((n - 2) ** 3 for n in sizes)
+    return {"workload": f"{len(sizes)} state solves, grids of random size in {list(inputs.ODD_SIZES)}, "
+                        f"f = 1, {w.precision}",
+            "solves_per_s": len(sizes) / dt, "ms_per_batch": 1e3 * dt,
+            "unknown_solves_per_s": unknowns / dt, "iterations": st["iterations"],
+            "max_relres": st["max_relres"]}
 
 
 def run_mlsgd(args):
@@ -294,13 +330,16 @@ def main():
     w = inputs.WORKLOADS[args.workload]
     nfin = w.grid_n[-1]
     log(args, f"workload {args.workload}: grids {w.grid_n} M {w.M} ({w.precision})")
-    r = run(args, m, w, dev, args.steps, args.warmup, timing_n=nfin)
+    r = run(args, m, w, dev, args.steps, args.warmup, timing_n=nfin, graph=args.graph)
     dt = r["dt"]
     stats = r["stats"]
     log(args, f"timed {args.steps} steps in {dt:.3f} s")
     solves, unknowns = problem_counts(w.grid_n, w.M)
     value = args.steps / dt
     tm = r["timing"]
+    if tm is None:   # graph replays carry no per-launch events: time the kernel host-driven
+        log(args, "host-driven pass for the kernel timing")
+        tm = run(args, m, w, dev, 2, 1, timing_n=nfin)["timing"]
     avg_ms = tm["ms"] / max(tm["launches"], 1)
     bytes_per_launch = tm["bytes"] / max(tm["launches"], 1)
     achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
@@ -387,6 +426,14 @@ def main():
                               "unknown_solves_per_s": u257 * v257,
                               "iters_state": max(x["iters_state"] for x in r257["stats"]),
                               "iters_adjoint": max(x["iters_adjoint"] for x in r257["stats"])}
+        log(args, "batched 9^3..257^3 workload, one replayed HIP graph per estimate")
+        k257 = max(2, args.steps // 2)
+        g257 = run(args, m, wb257, dev, k257, 1, graph=True)
+        vg = k257 / g257["dt"]
+        out["batched_257"]["graph"] = {
+            "value": vg, "ms_per_step": 1e3 / vg, "solves_per_s": s257 * vg}
+        log(args, "odd-size solve batch")
+        out["odd_size_solves"] = odd_size_solves(m, dev)
     if not args.no_per_sample:
         log(args, "per-sample FP64 comparator")
         ps = per_sample_fp64(m, inputs.WORKLOADS[args.mixed_workload], dev)

@@ -157,6 +157,24 @@ int mlsgd_solve_state_adjoint(mlsgd_ctx* ctx, int level, int coarse,
                               double* p_out, double* phi_out,
                               mlsgd_solve_stats* st);
 
+/* Batched state solves of independent problems whose grids differ in size
+ * (a batch of single-sample solves of the state equation, Sec. 2.1, on
+ * grids of caller-chosen size, beside the MLMC levels).
+ * Problem j uses grid n_list[j] (host array), the KL draw of sample first + j
+ * of `level` (any level index >= 0; it only keys the draw), the right-hand
+ * side f_value on the interior and the context's solver, precision, rtol
+ * and max_iters.  Each n must be odd, 5 <= n <= 1025, and coarsen by halving
+ * the cells to at most 9 vertices per axis (n - 1 = 2^a b with odd b <= 8);
+ * a coarsest grid above 3^3 is solved with the dense inverse of its
+ * operator.  y_out: device, nullable; problem j's n_j^3 solution (boundary
+ * 0) starts at offset sum_{i<j} n_i^3.  st: host, nullable (largest
+ * iteration count, count of misses, largest true relative residual).
+ * Errors: MLSGD_EINVAL for count < 1, a null n_list, first < 0, level < 0 or
+ * a grid outside the rule; MLSGD_ENOCONV when a solve misses rtol (y_out is
+ * still written). */
+int mlsgd_solve_sizes(mlsgd_ctx* ctx, int count, const int* n_list, int level, int64_t first,
+                      double f_value, double* y_out, mlsgd_solve_stats* st);
+
 /* One MLMC gradient estimate (Sec. 2.2, the estimator with truncated
  * denominator; Algorithm 1, GradientEstimate):
  *   grad = E^ML[X] / max{1, E^ML[Y]} + alpha u   on the finest grid,
@@ -211,6 +229,21 @@ typedef struct mlsgd_tuning {
 
 int mlsgd_get_tuning(const mlsgd_ctx* ctx, mlsgd_tuning* out);
 int mlsgd_set_tuning(mlsgd_ctx* ctx, const mlsgd_tuning* tuning);
+
+/* Graph mode (enable = 1): mlsgd_mlmc_gradient, mlsgd_mlmc_objective and
+ * mlsgd_step run each batch shape (L, M, gradient or objective) as one
+ * replayed HIP graph instead of a host-driven sequence of launches.  The
+ * first call of a shape runs as usual and records the iteration counts of
+ * its solves; the shape is then captured once with those counts plus a
+ * margin (converged problems idle through the extra iterations), followed by
+ * the true-residual check and one short restart block.  Later calls upload
+ * their draws and u, replay the graph and copy the gradient out; a replay
+ * whose solves miss rtol is recomputed by the host-driven path and the shape
+ * is captured again with a larger margin, so results always meet rtol.  The
+ * graph runs on the context's stream; capture uses a stream of its own.
+ * enable = 0 drops the captured graphs.  Not used while mlsgd_kernel_timing
+ * is on.  Errors: MLSGD_EINVAL for enable outside {0, 1}. */
+int mlsgd_set_graph(mlsgd_ctx* ctx, int enable);
 
 /* Event timing of the smoothing kernel on grid size n (the dominant kernel
  * of the solves), for roofline figures.  Each launch of the plain smoothing

@@ -21,9 +21,9 @@ SOLVER_CG, SOLVER_MGPCG = 0, 1
 
 EXPORTS = [
     "mlsgd_create", "mlsgd_destroy", "mlsgd_last_error", "mlsgd_sample_fields",
-    "mlsgd_philox_words", "mlsgd_solve_state_adjoint", "mlsgd_mlmc_gradient",
+    "mlsgd_philox_words", "mlsgd_solve_state_adjoint", "mlsgd_solve_sizes", "mlsgd_mlmc_gradient",
     "mlsgd_mlmc_objective", "mlsgd_set_batch", "mlsgd_step", "mlsgd_kernel_timing",
-    "mlsgd_get_tuning", "mlsgd_set_tuning",
+    "mlsgd_get_tuning", "mlsgd_set_tuning", "mlsgd_set_graph",
 ]
 SMOOTHER_RBGS, SMOOTHER_RBGS_FUSED, SMOOTHER_CHEBYSHEV = 0, 1, 2
 TUNING_FILE = os.path.join(HERE, "tuning.json")
@@ -124,6 +124,8 @@ def lib():
     L.mlsgd_philox_words.argtypes = [ctypes.c_uint64, i32, i64, i32, i32, vp, vp]
     L.mlsgd_solve_state_adjoint.argtypes = [vp, i32, i32, i64, i64, vp, vp, vp, vp,
                                             P(_SolveStats)]
+    L.mlsgd_solve_sizes.argtypes = [vp, i32, P(i32), i32, i64, ctypes.c_double, vp,
+                                    P(_SolveStats)]
     L.mlsgd_mlmc_gradient.argtypes = [vp, vp, i32, P(i64), P(i64), vp, P(_GradStats)]
     L.mlsgd_mlmc_objective.argtypes = [vp, vp, i32, P(i64), P(i64), P(ctypes.c_double),
                                        P(_GradStats)]
@@ -132,6 +134,7 @@ def lib():
     L.mlsgd_kernel_timing.argtypes = [vp, i32, i32, P(ctypes.c_double), P(i64),
                                       P(ctypes.c_double)]
     L.mlsgd_get_tuning.argtypes = [vp, P(_Tuning)]
+    L.mlsgd_set_graph.argtypes = [vp, i32]
     L.mlsgd_set_tuning.argtypes = [vp, P(_Tuning)]
     for name in EXPORTS:
         getattr(L, name)
@@ -273,6 +276,34 @@ class Context:
         stats = {"iterations": st.iterations, "nonconverged": st.nonconverged,
                  "max_relres": st.max_relres}
         return y, p, phi, stats
+
+    def solve_sizes(self, n_list, level=6, first=0, f_value=1.0, want_y=True,
+                    allow_noconv=False):
+        """Independent state solves on grids of the given sizes (mlsgd_solve_sizes).
+        Returns (list of n^3 solution tensors or None, stats)."""
+        torch = _torch()
+        ns = [int(n) for n in n_list]
+        arr = (ctypes.c_int32 * len(ns))(*ns)
+        tot = sum(n ** 3 for n in ns)
+        y = torch.empty((tot,), dtype=torch.float64, device=self.device) if want_y else None
+        st = _SolveStats()
+        rc = self.lib.mlsgd_solve_sizes(self._h, len(ns), arr, level, first, float(f_value),
+                                        ctypes.c_void_p(y.data_ptr() if y is not None else 0),
+                                        ctypes.byref(st))
+        self._check(rc, allow_noconv)
+        stats = {"iterations": st.iterations, "nonconverged": st.nonconverged,
+                 "max_relres": st.max_relres}
+        if y is None:
+            return None, stats
+        out, o = [], 0
+        for n in ns:
+            out.append(y[o:o + n ** 3].view(n, n, n))
+            o += n ** 3
+        return out, stats
+
+    def set_graph(self, enable=True):
+        """Run estimates as replayed HIP graphs (mlsgd_set_graph)."""
+        self._check(self.lib.mlsgd_set_graph(self._h, 1 if enable else 0))
 
     def mlmc_gradient(self, u, M, first=None, out=None, allow_noconv=False):
         torch = _torch()

@@ -82,6 +82,16 @@ template <typename T>
 void prolong_add_rows(int nc, int rows, int row0, const CgScal* scal, const T* coarse,
                       T* fine, hipStream_t s);
 
+// ---- dense coarsest-grid solve (hierarchies that stop above 3^3) ----
+void dense_coarse_inv(int n, int rows, const double* coef, int K, const double* cosT,
+                      double* ainv, hipStream_t s);
+template <typename T>
+void dense_apply(int n, int rows, const CgScal* scal, const double* ainv, const T* b, T* x,
+                 hipStream_t s);
+void scatter_rows(int n, int count, const long long* dst_off, const double* src, double* dst,
+                  hipStream_t s);
+void fill_interior(int n, double v, double* out, hipStream_t s);
+
 // ---- random field ----
 void kl_coeffs(const int* prob_level, const int64_t* prob_sample, int nprob,
                uint64_t seed, int K, double sigma2, double* coef, hipStream_t s);

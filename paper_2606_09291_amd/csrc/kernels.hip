@@ -1030,6 +1030,155 @@ template void prolong_add_rows<float>(int, int, int, const CgScal*, const float*
                                       hipStream_t);
 
 // ---------------------------------------------------------------------------
+// Dense coarsest-grid solve.  A hierarchy whose top grid is n = 2^a b + 1
+// with odd b > 1 cannot coarsen below b + 1 vertices per axis; that grid
+// keeps (b - 1)^3 interior unknowns (at most 7^3 here) and is solved exactly
+// with the inverse of its rediscretised operator, built per problem from the
+// KL draw and applied as a small dense product in every V-cycle.
+// ---------------------------------------------------------------------------
+constexpr int DENSE_NMAX = 9;
+
+// One workgroup per problem: 1/a at the coarsest vertices, the operator
+// (A y)_v = h^-2 sum_f a_f (y_v - y_w) with a_f = 2 / (b_v + b_w) on the
+// interior unknowns, Gauss-Jordan inversion in place (SPD: no pivoting),
+// then A^-1 <- (A^-1 + A^-T) / 2 so the coarse solve is exactly symmetric.
+__global__ void __launch_bounds__(256)
+    k_dense_coarse_inv(int n, const double* __restrict__ coef, int K,
+                       const double* __restrict__ cosT, double* __restrict__ ainv) {
+  __shared__ double sb[DENSE_NMAX * DENSE_NMAX * DENSE_NMAX];
+  __shared__ double sc[KMAX * KMAX * KMAX];
+  __shared__ double col[(DENSE_NMAX - 2) * (DENSE_NMAX - 2) * (DENSE_NMAX - 2)];
+  const int prob = blockIdx.x, tid = threadIdx.x;
+  const int m = n - 2, N = m * m * m, K3 = K * K * K;
+  double* A = ainv + (size_t)prob * N * N;
+  for (int j = tid; j < K3; j += 256) sc[j] = coef[(size_t)prob * K3 + j];
+  __syncthreads();
+  for (int v = tid; v < n * n * n; v += 256) {
+    const int ix = v / (n * n), iy = (v / n) % n, iz = v % n;
+    double l = 0.0;
+    for (int k1 = 0; k1 < K; ++k1)
+      for (int k2 = 0; k2 < K; ++k2)
+        for (int k3 = 0; k3 < K; ++k3)
+          l += sc[(k1 * K + k2) * K + k3] * cosT[k1 * n + ix] * cosT[k2 * n + iy] *
+               cosT[k3 * n + iz];
+    sb[v] = exp(-l);
+  }
+  for (int e = tid; e < N * N; e += 256) A[e] = 0.0;
+  __syncthreads();
+  const double ih2 = (double)(n - 1) * (double)(n - 1);
+  for (int i = tid; i < N; i += 256) {
+    const int ix = 1 + i / (m * m), iy = 1 + (i / m) % m, iz = 1 + i % m;
+    const int v = (ix * n + iy) * n + iz;
+    const int d[6][3] = {{-1, 0, 0}, {1, 0, 0}, {0, -1, 0}, {0, 1, 0}, {0, 0, -1}, {0, 0, 1}};
+    double diag = 0.0;
+    for (int f = 0; f < 6; ++f) {
+      const int jx = ix + d[f][0], jy = iy + d[f][1], jz = iz + d[f][2];
+      const double af = ih2 * face(sb[v], sb[(jx * n + jy) * n + jz]);
+      diag += af;
+      if (jx >= 1 && jx <= m && jy >= 1 && jy <= m && jz >= 1 && jz <= m)
+        A[(size_t)i * N + ((jx - 1) * m + (jy - 1)) * m + (jz - 1)] = -af;
+    }
+    A[(size_t)i * N + i] = diag;
+  }
+  __syncthreads();
+  for (int k = 0; k < N; ++k) {
+    for (int i = tid; i < N; i += 256) col[i] = A[(size_t)i * N + k];
+    __syncthreads();
+    const double p = 1.0 / col[k];
+    for (int j = tid; j < N; j += 256) A[(size_t)k * N + j] = (j == k ? 1.0 : A[(size_t)k * N + j]) * p;
+    __syncthreads();
+    for (int j = tid; j < N; j += 256) {  // each thread owns columns j
+      const double akj = A[(size_t)k * N + j];
+      for (int i = 0; i < N; ++i) {
+        if (i == k) continue;
+        A[(size_t)i * N + j] = (j == k ? 0.0 : A[(size_t)i * N + j]) - col[i] * akj;
+      }
+    }
+    __syncthreads();
+  }
+  for (int e = tid; e < N * N; e += 256) {
+    const int i = e / N, j = e - (e / N) * N;
+    if (i < j) {
+      const double s = 0.5 * (A[(size_t)i * N + j] + A[(size_t)j * N + i]);
+      A[(size_t)i * N + j] = s;
+      A[(size_t)j * N + i] = s;
+    }
+  }
+}
+
+void dense_coarse_inv(int n, int rows, const double* coef, int K, const double* cosT,
+                      double* ainv, hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_dense_coarse_inv, dim3(rows), dim3(256), 0, s, n, coef, K, cosT, ainv);
+}
+
+// x = A^-1 b on the interior of every active problem's coarsest row (the
+// inverse is symmetric, so thread i walks column i: coalesced reads).
+template <typename T>
+__global__ void __launch_bounds__(256)
+    k_dense_apply(int n, const CgScal* __restrict__ scal, const double* __restrict__ ainv,
+                  const T* __restrict__ b, T* __restrict__ x) {
+  __shared__ double sbv[(DENSE_NMAX - 2) * (DENSE_NMAX - 2) * (DENSE_NMAX - 2)];
+  const int prob = blockIdx.x, tid = threadIdx.x;
+  if (scal && !scal[prob].active) return;  // uniform per workgroup
+  const int m = n - 2, N = m * m * m;
+  const size_t base = (size_t)prob * n * n * n;
+  auto vtx = [&](int i) { return ((1 + i / (m * m)) * n + 1 + (i / m) % m) * n + 1 + i % m; };
+  for (int i = tid; i < N; i += 256) sbv[i] = (double)b[base + vtx(i)];
+  __syncthreads();
+  const double* A = ainv + (size_t)prob * N * N;
+  for (int i = tid; i < N; i += 256) {
+    double acc = 0.0;
+    for (int j = 0; j < N; ++j) acc += A[(size_t)j * N + i] * sbv[j];
+    x[base + vtx(i)] = (T)acc;
+  }
+}
+
+template <typename T>
+void dense_apply(int n, int rows, const CgScal* scal, const double* ainv, const T* b, T* x,
+                 hipStream_t s) {
+  if (rows <= 0) return;
+  hipLaunchKernelGGL(k_dense_apply<T>, dim3(rows), dim3(256), 0, s, n, scal, ainv, b, x);
+}
+template void dense_apply<double>(int, int, const CgScal*, const double*, const double*, double*,
+                                  hipStream_t);
+template void dense_apply<float>(int, int, const CgScal*, const double*, const float*, float*,
+                                 hipStream_t);
+
+// Rows [count][n^3] scattered to per-row destination offsets (packed output
+// of problems of different sizes).
+__global__ void k_scatter_rows(long long per, int count, const long long* __restrict__ dst_off,
+                               const double* __restrict__ src, double* __restrict__ dst) {
+  const long long total = per * count;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e / per;
+    dst[dst_off[r] + (e - r * per)] = src[e];
+  }
+}
+void scatter_rows(int n, int count, const long long* dst_off, const double* src, double* dst,
+                  hipStream_t s) {
+  const long long per = (long long)n * n * n, total = per * count;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(total, 256)), dim3(256), 0, s, per, count,
+                     dst_off, src, dst);
+}
+
+// Constant on the interior, zero on the boundary.
+__global__ void k_fill_interior(int n, double v, double* __restrict__ out) {
+  const long long N = (long long)n * n * n;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < N;
+       e += (long long)gridDim.x * blockDim.x) {
+    const int ix = (int)(e / ((long long)n * n)), iy = (int)((e / n) % n), iz = (int)(e % n);
+    out[e] = (ix > 0 && iy > 0 && iz > 0 && ix < n - 1 && iy < n - 1 && iz < n - 1) ? v : 0.0;
+  }
+}
+void fill_interior(int n, double v, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_interior, dim3(grid_for((long long)n * n * n, 256)), dim3(256), 0, s,
+                     n, v, out);
+}
+
+// ---------------------------------------------------------------------------
 // Random field: Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11) keyed by
 // (seed, 0) with counter (block, sample, level, tag); Box-Muller normals; KL
 // coefficients c_j = sqrt(sigma2 lam_k) xi_j, lam_k = (1 + |k|^2)^(-5/2).

@@ -99,6 +99,8 @@ struct Plan {
   double* d_partial = nullptr;
   double* d_phi = nullptr;
   double* d_w = nullptr;
+  double* ainv = nullptr;  // coarsest-grid inverses [rows][N][N] when the hierarchy stops above 3^3
+  int dense_N = 0;
   void* arena = nullptr;
   size_t arena_bytes = 0;
 };
@@ -129,10 +131,24 @@ struct mlsgd_ctx {
   int* d_count = nullptr;
   int* h_count = nullptr;                  // pinned
   struct StatDev { int iters, nonconv; double relres; };
-  StatDev* d_stat = nullptr;
-  StatDev* h_stat = nullptr;               // pinned
+  StatDev* d_stat = nullptr;               // [2]: state and adjoint solves
+  StatDev* h_stat = nullptr;               // pinned, [2]
+  // graph mode: each batch shape runs as one replayed HIP graph
+  struct GraphEntry {
+    hipGraphExec_t exec = nullptr;
+    int it_s = 0, it_a = 0;   // iteration counts the graph runs
+    int margin = 1;           // iterations beyond the learned counts
+  };
+  bool graph = false;
+  hipStream_t cap_stream = nullptr;        // capture stream (default priority)
+  double* d_u_graph = nullptr;             // u as the graph reads it
+  double* d_g_graph = nullptr;             // gradient as the graph writes it
+  std::map<std::string, GraphEntry> graphs;
   int* d_flag = nullptr;
   std::map<std::string, std::unique_ptr<Plan>> plans;
+  std::map<int, double*> const_rhs;        // constant interior right-hand sides per grid
+  long long* d_dst_off = nullptr;          // packed-output offsets of one solve batch
+  size_t dst_off_len = 0;
   std::vector<void*> allocs;
   // batch used by mlsgd_step
   int cur_L = 0;
@@ -200,8 +216,12 @@ struct Carver {
   }
 };
 
-// Build the layout for a list of blocks (grid sizes non-increasing).
-Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks) {
+void plan_fields(mlsgd_ctx* c, Plan* P);
+
+// Build (or reuse) the layout for a list of blocks (grid sizes
+// non-increasing) and upload this call's draws; `fields` also regenerates
+// the coefficient fields from them (kernels only: plan_fields).
+Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks, bool fields = true) {
   std::string key;
   for (const auto& b : blocks) key += std::to_string(b.n) + ":" + std::to_string(b.count) + ";";
   auto it = c->plans.find(key);
@@ -235,7 +255,8 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks) {
       for (int64_t m = 0; m < b.count; ++m, ++p) P->h_n[p] = b.n;
       P->groups.back().count += (int)b.count;
     }
-    // grid sizes from the largest top grid down to 3
+    // grid sizes from the largest top grid down to 3, or down to the first
+    // grid with an odd number of cells, which cannot be coarsened further
     int nmax = blocks.front().n;
     for (int n = nmax;; n = (n - 1) / 2 + 1) {
       SizeLvl s;
@@ -250,7 +271,16 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks) {
       s.top_begin = top;
       s.cosT = cos_for(c, n);
       P->sizes.push_back(s);
-      if (n <= 3) break;
+      if (n <= 3 || ((n - 1) & 1)) break;
+    }
+    {
+      const SizeLvl& co = P->sizes.back();
+      if (co.n > 3) {
+        require(co.n <= 9, "the grid hierarchy must coarsen to at most 9^3");
+        require(P->sizes.size() >= 2 && co.top_begin == co.rows,
+                "a top grid cannot be the dense coarsest grid");
+        P->dense_N = (co.n - 2) * (co.n - 2) * (co.n - 2);
+      }
     }
     for (auto& g : P->groups) {
       for (size_t k = 0; k < P->sizes.size(); ++k)
@@ -300,6 +330,8 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks) {
       P->d_partial = cv.take<double>((size_t)off);
       P->d_phi = cv.take<double>(np);
       P->d_w = cv.take<double>(np);
+      if (P->dense_N)
+        P->ainv = cv.take<double>((size_t)P->sizes.back().rows * P->dense_N * P->dense_N);
       if (pass == 0) {
         P->arena_bytes = cv.off + 256;
         P->arena = dalloc(c, P->arena_bytes);
@@ -323,14 +355,25 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks) {
                         hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipMemcpyAsync(P->d_sample, P->h_sample.data(), sizeof(int64_t) * P->nprob,
                         hipMemcpyHostToDevice, c->stream));
+  if (fields) plan_fields(c, P);
+  return P;
+}
+
+// KL coefficients of the uploaded draws, the per-grid coefficient caches and
+// the dense coarsest inverses.
+void plan_fields(mlsgd_ctx* c, Plan* P) {
+  const int K = c->pb.kl_K;
   kl_coeffs(P->d_level, P->d_sample, P->nprob, c->pb.seed, K, c->pb.kl_sigma2, P->d_coef,
             c->stream);
   // the coefficient is regenerated from the draws once per call for the
   // cached sweeps (the Krylov matvec and residual always run in FP64)
   for (auto& sl : P->sizes)
     coef_cache(sl.n, sl.rows, P->d_coef, K, sl.cosT, sl.C, sl.Cf, sl.Cb, c->stream);
+  if (P->dense_N) {
+    const SizeLvl& co = P->sizes.back();
+    dense_coarse_inv(co.n, co.rows, P->d_coef, K, co.cosT, P->ainv, c->stream);
+  }
   HIPCHK(hipGetLastError());
-  return P;
 }
 
 GridArgs args_size(mlsgd_ctx* c, Plan* P, const SizeLvl& s) {
@@ -540,10 +583,14 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
     T* A[2] = {v.X, v.R};
     GridArgs g = args(L);
     if (k == S - 1) {
-      timed_launch(c, g, jac_bytes<T>(L.n, L.rows, true, false, g), [&] {
-        march_jac<T>(g, nullptr, nullptr, v.B, A[0], 1, 1.0, P->d_poff, P->d_partial, L.top_begin,
-                     c->stream);
-      });
+      if (P->ainv) {
+        dense_apply<T>(L.n, L.rows, P->d_scal, P->ainv, v.B, A[0], c->stream);
+      } else {
+        timed_launch(c, g, jac_bytes<T>(L.n, L.rows, true, false, g), [&] {
+          march_jac<T>(g, nullptr, nullptr, v.B, A[0], 1, 1.0, P->d_poff, P->d_partial,
+                       L.top_begin, c->stream);
+        });
+      }
       L.cur = 0;
       break;
     }
@@ -612,8 +659,11 @@ void vcycle_fused(mlsgd_ctx* c, Plan* P) {
     T* A[2] = {v.X, v.R};
     GridArgs g = args(L);
     if (k == S - 1) {
-      timed_sweep<T>(c, g, nullptr, nullptr, v.B, A[0], 0, 1, P->d_poff, P->d_partial,
-                     L.top_begin, 1.0);
+      if (P->ainv)
+        dense_apply<T>(L.n, L.rows, P->d_scal, P->ainv, v.B, A[0], c->stream);
+      else
+        timed_sweep<T>(c, g, nullptr, nullptr, v.B, A[0], 0, 1, P->d_poff, P->d_partial,
+                       L.top_begin, 1.0);
       L.cur = 0;
       break;
     }
@@ -661,8 +711,12 @@ void vcycle(mlsgd_ctx* c, Plan* P) {
     MgView<T> v = mg_view<T>(L);
     GridArgs g = args(L);
     if (k == S - 1) {
-      timed_gs<T>(c, g, v.X, v.B, 0, 1, nullptr, nullptr, 0, 1.0);
-      timed_gs<T>(c, g, v.X, v.B, 1, 0, P->d_poff, P->d_partial, L.top_begin, 1.0);
+      if (P->ainv) {
+        dense_apply<T>(L.n, L.rows, P->d_scal, P->ainv, v.B, v.X, s);
+      } else {
+        timed_gs<T>(c, g, v.X, v.B, 0, 1, nullptr, nullptr, 0, 1.0);
+        timed_gs<T>(c, g, v.X, v.B, 1, 0, P->d_poff, P->d_partial, L.top_begin, 1.0);
+      }
       break;
     }
     for (int sw = 0; sw < nu; ++sw) {
@@ -823,6 +877,96 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
   *relres_out = c->h_stat->relres;
 }
 
+// The same batched PCG with a fixed iteration count and no host reads, so it
+// can be captured in a graph: `iters` iterations, the true-residual check,
+// one restart block of up to kRestartIters iterations for the problems
+// whose true residual drifted, the check again, and the per-problem
+// statistics into d_stat[slot].  Converged problems are inactive, so the
+// iterations beyond their convergence only launch early-exiting kernels.
+constexpr int kRestartIters = 2;
+
+void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
+  hipStream_t s = c->stream;
+  const bool mg = c->pb.solver == MLSGD_SOLVER_MGPCG;
+  const double rtol = c->pb.rtol;
+  const int maxit = c->pb.max_iters;
+  auto cg = [&](int phase, const double* partial) {
+    cg_scalar(phase, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, partial, rtol, maxit, c->d_count,
+              s);
+  };
+  auto start = [&]() {  // z = M r and rz for the active problems
+    if (mg && c->mixed) {
+      for (auto& gr : P->groups) {
+        SizeLvl& L = P->sizes[gr.sl];
+        to_f32((long long)gr.count * cube(gr.n), rows_of(L.B, gr),
+               L.Bf + (size_t)gr.p0 * cube(gr.n), s);
+      }
+    }
+    if (mg) {
+      precondition(c, P);
+      cg(PH_RZ0, P->d_partial);
+    } else {
+      cg(PH_RZ0_RR, nullptr);
+    }
+  };
+  auto iterate = [&](int count) {
+    for (int it = 0; it < count; ++it) {
+      for (auto& gr : P->groups) {
+        GridArgs g = args_group(c, P, gr, true);
+        SizeLvl& L = P->sizes[gr.sl];
+        if (mg && c->mixed) {
+          march_matvec<double, float>(g, z32(c, P, gr), gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q,
+                                      P->d_poff, P->d_partial, s);
+        } else {
+          const double* z = mg ? z64(c, P, gr) : rows_of(L.B, gr);
+          march_matvec<double, double>(g, z, gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q, P->d_poff,
+                                       P->d_partial, s);
+        }
+      }
+      cg(PH_ALPHA, P->d_partial);
+      for (auto& gr : P->groups) {
+        GridArgs g = args_group(c, P, gr, true);
+        float* r32 = (mg && c->mixed) ? P->sizes[gr.sl].Bf + (size_t)gr.p0 * cube(gr.n) : nullptr;
+        group_update(g, gr.x, gr.p[gr.pcur ^ 1], rows_of(P->sizes[gr.sl].B, gr), gr.q,
+                     P->d_poff, P->d_partial, r32, s);
+        gr.pcur ^= 1;
+      }
+      cg(PH_RR, P->d_partial);
+      if (mg) {
+        precondition(c, P);
+        cg(PH_RZ, P->d_partial);
+      } else {
+        cg(PH_RZ_RR, nullptr);
+      }
+    }
+  };
+  auto true_residual = [&]() {
+    for (auto& gr : P->groups) {
+      GridArgs g = args_group(c, P, gr, false);
+      march_resid<double>(g, gr.x, gr.b0, gr.q, s);
+      group_dot(g, gr.q, gr.q, P->d_poff, P->d_partial, s);
+    }
+    cg(PH_TRUE, P->d_partial);
+  };
+  for (auto& gr : P->groups) {
+    GridArgs g = args_group(c, P, gr, false);
+    double* r = rows_of(P->sizes[gr.sl].B, gr);
+    group_dot(g, r, r, P->d_poff, P->d_partial, s);
+  }
+  cg(PH_INIT_BB, P->d_partial);
+  start();
+  iterate(iters);
+  true_residual();
+  for (auto& gr : P->groups)
+    copy_rows_strided(gr.n, gr.count, gr.q, rows_of(P->sizes[gr.sl].B, gr), s);
+  start();
+  iterate(kRestartIters);
+  true_residual();
+  scal_to_stats(P->d_scal, P->nprob, rtol, &c->d_stat[slot].iters, &c->d_stat[slot].nonconv,
+                &c->d_stat[slot].relres, s);
+  HIPCHK(hipGetLastError());
+}
+
 // Right-hand sides R^(finest -> n)(f + u) on every level grid.
 void level_rhs(mlsgd_ctx* c, const double* u) {
   const int L = c->pb.n_levels;
@@ -837,7 +981,8 @@ void level_rhs(mlsgd_ctx* c, const double* u) {
 
 // State solves of every problem, then misfits Phi and the adjoint right-hand
 // sides y - y_d in the B rows (x reset to 0).
-void state_phase(mlsgd_ctx* c, Plan* P, int* it, int* nc, double* rr, double* y_out) {
+void state_phase(mlsgd_ctx* c, Plan* P, int* it, int* nc, double* rr, double* y_out,
+                 int fixed = 0) {
   hipStream_t s = c->stream;
   for (auto& gr : P->groups) {
     double* b = rows_of(P->sizes[gr.sl].B, gr);
@@ -846,7 +991,10 @@ void state_phase(mlsgd_ctx* c, Plan* P, int* it, int* nc, double* rr, double* y_
     rows_zero((long long)gr.count * cube(gr.n), gr.x, s);
   }
   HIPCHK(hipGetLastError());
-  krylov(c, P, it, nc, rr);
+  if (fixed > 0)
+    krylov_fixed(c, P, fixed, 0);
+  else
+    krylov(c, P, it, nc, rr);
   for (auto& gr : P->groups) {
     if (y_out) copy_rows_strided(gr.n, gr.count, gr.x, y_out, s);
     GridArgs g = args_group(c, P, gr, false);
@@ -934,68 +1082,81 @@ void ensure_epi(mlsgd_ctx* c, size_t part_len, size_t dx_len) {
 }
 
 // One estimate (gradient or objective only).
-int run_estimate(mlsgd_ctx* c, const double* u, int L, const int64_t* M, const int64_t* first,
-                 double* grad_out, double* J_out, mlsgd_grad_stats* st) {
-  require(L >= 1 && L <= c->pb.n_levels, "L out of range");
-  require(M != nullptr, "M is null");
-  for (int i = 0; i < L; ++i) {
-    require(M[i] >= 1, "sample counts must be >= 1");
-    if (first) require(first[i] >= 0, "sample offsets must be >= 0");
-  }
-  check_u(c, u);
-  hipStream_t s = c->stream;
-  HIPCHK(hipEventRecord(c->ev[0], s));
-  level_rhs(c, u);
-  Plan* P = get_plan(c, mlmc_blocks(c, L, M, first));
-  int it_s = 0, nc_s = 0, it_a = 0, nc_a = 0;
-  double rr_s = 0, rr_a = 0;
-  state_phase(c, P, &it_s, &nc_s, &rr_s, nullptr);
-  if (grad_out) krylov(c, P, &it_a, &nc_a, &rr_a);
-  HIPCHK(hipEventRecord(c->ev[1], s));
+// Host side of one estimate: plan and draws, epilogue metadata and buffers.
+struct EstPrep {
+  Plan* P = nullptr;
+  std::vector<LevelRows> lr;
+  std::vector<EpiLevel> ev;
+  long long g_off = 0;
+};
 
-  // epilogue
-  const int nL = c->pb.grid_n[L - 1];
-  std::vector<LevelRows> lr = level_rows(P, c, L, M);
-  std::vector<EpiLevel> ev(L);
+EstPrep estimate_prep(mlsgd_ctx* c, int L, const int64_t* M, const int64_t* first,
+                      bool fields) {
+  EstPrep e;
+  e.P = get_plan(c, mlmc_blocks(c, L, M, first), fields);
+  e.lr = level_rows(e.P, c, L, M);
+  e.ev.resize(L);
   size_t part_len = RED_BLOCKS, dx_len = 0;
   for (int i = 0; i < L; ++i) {
     const int nf = c->pb.grid_n[i];
-    ev[i].M = (int)M[i];
-    ev[i].fine_off = lr[i].fine_prob;
-    ev[i].coarse_off = lr[i].coarse_prob;
-    ev[i].nf = nf;
-    ev[i].m2_off = (long long)part_len;
-    ev[i].m2_cnt = level_sample_blocks((int)M[i]) * level_m2_chunks(nf);
-    part_len += ev[i].m2_cnt;
-    ev[i].nm_off = (long long)part_len;
+    e.ev[i].M = (int)M[i];
+    e.ev[i].fine_off = e.lr[i].fine_prob;
+    e.ev[i].coarse_off = e.lr[i].coarse_prob;
+    e.ev[i].nf = nf;
+    e.ev[i].m2_off = (long long)part_len;
+    e.ev[i].m2_cnt = level_sample_blocks((int)M[i]) * level_m2_chunks(nf);
+    part_len += e.ev[i].m2_cnt;
+    e.ev[i].nm_off = (long long)part_len;
     part_len += RED_BLOCKS;
     dx_len = std::max(dx_len, (size_t)level_sample_blocks((int)M[i]) * cube(nf));
   }
-  const long long g_off = (long long)part_len;
+  e.g_off = (long long)part_len;
   part_len += RED_BLOCKS;
   ensure_epi(c, part_len, dx_len);
+  HIPCHK(hipMemcpyAsync(c->d_epi_lev, e.ev.data(), sizeof(EpiLevel) * L, hipMemcpyHostToDevice,
+                        c->stream));
+  return e;
+}
+
+// Device side of one estimate on c->stream.  fixed_s > 0 (graph mode): the
+// coefficient fields are regenerated here, the solves run fixed iteration
+// counts and nothing is read back, so the whole sequence is kernels only.
+void estimate_enqueue(mlsgd_ctx* c, const EstPrep& e, int L, const int64_t* M, const double* u,
+                      double* grad_out, int fixed_s, int fixed_a, int* it_s, int* nc_s,
+                      double* rr_s, int* it_a, int* nc_a, double* rr_a) {
+  hipStream_t s = c->stream;
+  Plan* P = e.P;
+  level_rhs(c, u);
+  if (fixed_s > 0) plan_fields(c, P);
+  state_phase(c, P, it_s, nc_s, rr_s, nullptr, fixed_s);
+  if (grad_out) {
+    if (fixed_a > 0)
+      krylov_fixed(c, P, fixed_a, 1);
+    else
+      krylov(c, P, it_a, nc_a, rr_a);
+  }
+  if (fixed_s <= 0) HIPCHK(hipEventRecord(c->ev[1], s));
   shift_weights(P->nprob, P->d_phi, c->pb.theta, P->d_w, &c->d_epi_out->s, s);
   add_mask(c->nfin, nullptr, u, c->d_umask, s);
   dot_blocks((long long)cube(c->nfin), c->d_umask, c->d_umask, c->d_epi_part, s);
   if (grad_out) {
     for (int i = 0; i < L; ++i) {
       const int nf = c->pb.grid_n[i];
-      const double* pf = lr[i].gf->x + (size_t)lr[i].fine_row * cube(nf);
-      const double* wf = P->d_w + lr[i].fine_prob;
+      const double* pf = e.lr[i].gf->x + (size_t)e.lr[i].fine_row * cube(nf);
+      const double* wf = P->d_w + e.lr[i].fine_prob;
       const double* pc = nullptr;
       const double* wc = nullptr;
       if (i > 0) {
-        pc = lr[i].gc->x + (size_t)lr[i].coarse_row * cube(c->pb.grid_n[i - 1]);
-        wc = P->d_w + lr[i].coarse_prob;
+        pc = e.lr[i].gc->x + (size_t)e.lr[i].coarse_row * cube(c->pb.grid_n[i - 1]);
+        wc = P->d_w + e.lr[i].coarse_prob;
       }
       double* mean = c->mean_lvl[nf];
       level_dx_partial(nf, (int)M[i], pf, wf, pc, wc, c->d_dxpart, s);
       level_dx_mean(nf, (int)M[i], c->d_dxpart, mean, s);
-      level_dx_m2(nf, (int)M[i], pf, wf, pc, wc, mean, c->d_epi_part + ev[i].m2_off, s);
-      dot_blocks((long long)cube(nf), mean, mean, c->d_epi_part + ev[i].nm_off, s);
+      level_dx_m2(nf, (int)M[i], pf, wf, pc, wc, mean, c->d_epi_part + e.ev[i].m2_off, s);
+      dot_blocks((long long)cube(nf), mean, mean, c->d_epi_part + e.ev[i].nm_off, s);
     }
   }
-  HIPCHK(hipMemcpyAsync(c->d_epi_lev, ev.data(), sizeof(EpiLevel) * L, hipMemcpyHostToDevice, s));
   // the fine-grid misfit scale is the one of the level's own grid; u norm on the finest grid
   epilogue_scalars(L, c->d_epi_lev, P->d_phi, P->d_w, c->d_epi_part, 0, c->nfin, c->pb.theta,
                    c->pb.alpha, grad_out ? 1 : 0, c->d_epi_out, s);
@@ -1009,17 +1170,27 @@ int run_estimate(mlsgd_ctx* c, const double* u, int L, const int64_t* M, const i
       if (i < L) axpy_full(n, 1.0, c->mean_lvl[n], dst, s);
       acc = dst;
     }
-    dot_blocks((long long)cube(c->nfin), acc, acc, c->d_epi_part + g_off, s);
-    finish_norm(c->nfin, c->d_epi_part + g_off, &c->d_epi_out->exnorm2, s);
+    dot_blocks((long long)cube(c->nfin), acc, acc, c->d_epi_part + e.g_off, s);
+    finish_norm(c->nfin, c->d_epi_part + e.g_off, &c->d_epi_out->exnorm2, s);
     final_grad(c->nfin, acc, u, c->d_epi_out, c->pb.alpha, grad_out, s);
-    dot_blocks((long long)cube(c->nfin), grad_out, grad_out, c->d_epi_part + g_off, s);
-    finish_norm(c->nfin, c->d_epi_part + g_off, &c->d_epi_out->gnorm2, s);
+    dot_blocks((long long)cube(c->nfin), grad_out, grad_out, c->d_epi_part + e.g_off, s);
+    finish_norm(c->nfin, c->d_epi_part + e.g_off, &c->d_epi_out->gnorm2, s);
   }
-  (void)nL;
   HIPCHK(hipGetLastError());
-  HIPCHK(hipEventRecord(c->ev[2], s));
-  HIPCHK(hipMemcpyAsync(c->h_epi_out, c->d_epi_out, sizeof(EpiOut), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipStreamSynchronize(s));
+}
+
+void validate_batch(mlsgd_ctx* c, int L, const int64_t* M, const int64_t* first) {
+  require(L >= 1 && L <= c->pb.n_levels, "L out of range");
+  require(M != nullptr, "M is null");
+  for (int i = 0; i < L; ++i) {
+    require(M[i] >= 1, "sample counts must be >= 1");
+    if (first) require(first[i] >= 0, "sample offsets must be >= 0");
+  }
+}
+
+// Statistics of a finished estimate from the epilogue record.
+int finish_stats(mlsgd_ctx* c, int L, bool grad, double* J_out, mlsgd_grad_stats* st, int it_s,
+                 int it_a, int nc, double rr) {
   const EpiOut& eo = *c->h_epi_out;
   if (J_out) *J_out = eo.J;
   if (st) {
@@ -1030,8 +1201,8 @@ int run_estimate(mlsgd_ctx* c, const double* u, int L, const int64_t* M, const i
     st->truncated = eo.truncated;
     st->iters_state = it_s;
     st->iters_adjoint = it_a;
-    st->nonconverged = nc_s + nc_a;
-    st->max_relres = std::max(rr_s, rr_a);
+    st->nonconverged = nc;
+    st->max_relres = rr;
     for (int i = 0; i < L; ++i) {
       st->mean_dY[i] = eo.mean_dY[i];
       st->norm2_mean_dX[i] = eo.norm2_mean_dX[i];
@@ -1039,8 +1210,8 @@ int run_estimate(mlsgd_ctx* c, const double* u, int L, const int64_t* M, const i
       st->m2_dY[i] = eo.m2_dY[i];
       st->mean_phi_f[i] = eo.mean_phi_f[i];
     }
-    st->grad_norm = grad_out ? std::sqrt(eo.gnorm2) : 0.0;
-    st->norm2_EX = grad_out ? eo.exnorm2 : 0.0;
+    st->grad_norm = grad ? std::sqrt(eo.gnorm2) : 0.0;
+    st->norm2_EX = grad ? eo.exnorm2 : 0.0;
     float ms1 = 0, ms2 = 0;
     HIPCHK(hipEventElapsedTime(&ms1, c->ev[0], c->ev[1]));
     HIPCHK(hipEventElapsedTime(&ms2, c->ev[0], c->ev[2]));
@@ -1048,11 +1219,120 @@ int run_estimate(mlsgd_ctx* c, const double* u, int L, const int64_t* M, const i
     st->ms_total = ms2;
   }
   if (!std::isfinite(eo.J)) throw Fail{MLSGD_ENONFINITE, "non-finite objective"};
-  if (nc_s + nc_a > 0) {
+  if (nc > 0) {
     c->err = "some solves missed rtol";
     return MLSGD_ENOCONV;
   }
   return MLSGD_OK;
+}
+
+int run_estimate_eager(mlsgd_ctx* c, const double* u, int L, const int64_t* M,
+                       const int64_t* first, double* grad_out, double* J_out,
+                       mlsgd_grad_stats* st) {
+  validate_batch(c, L, M, first);
+  check_u(c, u);
+  hipStream_t s = c->stream;
+  HIPCHK(hipEventRecord(c->ev[0], s));
+  EstPrep e = estimate_prep(c, L, M, first, true);
+  int it_s = 0, nc_s = 0, it_a = 0, nc_a = 0;
+  double rr_s = 0, rr_a = 0;
+  estimate_enqueue(c, e, L, M, u, grad_out, 0, 0, &it_s, &nc_s, &rr_s, &it_a, &nc_a, &rr_a);
+  HIPCHK(hipEventRecord(c->ev[2], s));
+  HIPCHK(hipMemcpyAsync(c->h_epi_out, c->d_epi_out, sizeof(EpiOut), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return finish_stats(c, L, grad_out != nullptr, J_out, st, it_s, it_a, nc_s + nc_a,
+                      std::max(rr_s, rr_a));
+}
+
+void drop_graphs(mlsgd_ctx* c) {
+  for (auto& kv : c->graphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  c->graphs.clear();
+}
+
+// Graph mode: the first call of a batch shape runs eagerly and learns the
+// iteration counts; the shape is then captured once (fixed counts plus a
+// margin) and every later call uploads its draws and u and replays it.  A
+// replay whose solves miss rtol is redone eagerly and the shape is captured
+// again with a larger margin.
+int run_estimate_graph(mlsgd_ctx* c, const double* u, int L, const int64_t* M,
+                       const int64_t* first, double* grad_out, double* J_out,
+                       mlsgd_grad_stats* st) {
+  validate_batch(c, L, M, first);
+  std::string key = std::to_string(L) + (grad_out ? "g|" : "j|");
+  for (int i = 0; i < L; ++i) key += std::to_string(M[i]) + ",";
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end() || !it->second.exec) {
+    const int margin = it == c->graphs.end() ? 1 : it->second.margin;
+    mlsgd_grad_stats loc{};
+    const int rc = run_estimate_eager(c, u, L, M, first, grad_out, J_out, &loc);
+    if (st) *st = loc;
+    if (rc != MLSGD_OK) return rc;
+    mlsgd_ctx::GraphEntry ge;
+    ge.margin = margin;
+    ge.it_s = loc.iters_state + margin;
+    ge.it_a = grad_out ? loc.iters_adjoint + margin : 0;
+    EstPrep e = estimate_prep(c, L, M, first, false);
+    hipStream_t saved = c->stream;
+    HIPCHK(hipStreamSynchronize(saved));
+    c->stream = c->cap_stream;
+    hipGraph_t g = nullptr;
+    HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeRelaxed));
+    try {
+      int d0 = 0, d1 = 0, d2 = 0, d3 = 0;
+      double r0 = 0, r1 = 0;
+      estimate_enqueue(c, e, L, M, c->d_u_graph, grad_out ? c->d_g_graph : nullptr, ge.it_s,
+                       std::max(ge.it_a, 1), &d0, &d1, &r0, &d2, &d3, &r1);
+    } catch (...) {
+      (void)hipStreamEndCapture(c->cap_stream, &g);
+      if (g) (void)hipGraphDestroy(g);
+      c->stream = saved;
+      throw;
+    }
+    const hipError_t ec = hipStreamEndCapture(c->cap_stream, &g);
+    c->stream = saved;
+    if (ec != hipSuccess) throw Fail{MLSGD_EHIP, std::string("graph capture: ") + hipGetErrorString(ec)};
+    const hipError_t ei = hipGraphInstantiate(&ge.exec, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (ei != hipSuccess)
+      throw Fail{MLSGD_EHIP, std::string("graph instantiate: ") + hipGetErrorString(ei)};
+    c->graphs[key] = ge;
+    return rc;
+  }
+  mlsgd_ctx::GraphEntry& ge = it->second;
+  check_u(c, u);
+  hipStream_t s = c->stream;
+  HIPCHK(hipMemcpyAsync(c->d_u_graph, u, sizeof(double) * cube(c->nfin), hipMemcpyDeviceToDevice,
+                        s));
+  (void)estimate_prep(c, L, M, first, false);
+  HIPCHK(hipEventRecord(c->ev[0], s));
+  HIPCHK(hipGraphLaunch(ge.exec, s));
+  HIPCHK(hipEventRecord(c->ev[1], s));
+  HIPCHK(hipEventRecord(c->ev[2], s));
+  HIPCHK(hipMemcpyAsync(c->h_epi_out, c->d_epi_out, sizeof(EpiOut), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(c->h_stat, c->d_stat, 2 * sizeof(mlsgd_ctx::StatDev),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const mlsgd_ctx::StatDev st_s = c->h_stat[0], st_a = c->h_stat[1];
+  const int nc = st_s.nonconv + (grad_out ? st_a.nonconv : 0);
+  if (nc > 0) {  // the learned counts were too small for these draws
+    HIPCHK(hipGraphExecDestroy(ge.exec));
+    ge.exec = nullptr;
+    ge.margin += 1;
+    return run_estimate_eager(c, u, L, M, first, grad_out, J_out, st);
+  }
+  if (grad_out)
+    HIPCHK(hipMemcpyAsync(grad_out, c->d_g_graph, sizeof(double) * cube(c->nfin),
+                          hipMemcpyDeviceToDevice, s));
+  const double rr = std::max(st_s.relres, grad_out ? st_a.relres : 0.0);
+  return finish_stats(c, L, grad_out != nullptr, J_out, st, st_s.iters,
+                      grad_out ? st_a.iters : 0, 0, rr);
+}
+
+int run_estimate(mlsgd_ctx* c, const double* u, int L, const int64_t* M, const int64_t* first,
+                 double* grad_out, double* J_out, mlsgd_grad_stats* st) {
+  if (c->graph && !c->tm.on) return run_estimate_graph(c, u, L, M, first, grad_out, J_out, st);
+  return run_estimate_eager(c, u, L, M, first, grad_out, J_out, st);
 }
 
 // Adaptive controller (Sec. 4.1): second-order power sums v^2 per level,
@@ -1219,10 +1499,11 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     c->d_epi_out = (EpiOut*)dalloc(c.get(), sizeof(EpiOut));
     c->d_count = (int*)dalloc(c.get(), sizeof(int));
     c->d_flag = (int*)dalloc(c.get(), sizeof(int));
-    c->d_stat = (mlsgd_ctx::StatDev*)dalloc(c.get(), sizeof(mlsgd_ctx::StatDev));
+    c->d_stat = (mlsgd_ctx::StatDev*)dalloc(c.get(), 2 * sizeof(mlsgd_ctx::StatDev));
     HIPCHK(hipHostMalloc((void**)&c->h_epi_out, sizeof(EpiOut), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&c->h_count, sizeof(int), hipHostMallocDefault));
-    HIPCHK(hipHostMalloc((void**)&c->h_stat, sizeof(mlsgd_ctx::StatDev), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&c->h_stat, 2 * sizeof(mlsgd_ctx::StatDev),
+                         hipHostMallocDefault));
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
     c->cur_L = pb->n_levels;
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1252,6 +1533,22 @@ int mlsgd_kernel_timing(mlsgd_ctx* c, int enable, int n, double* ms_total, int64
       c->tm.total_bytes = 0.0;
       c->tm.launches = 0;
     }
+    return MLSGD_OK;
+  });
+}
+
+int mlsgd_set_graph(mlsgd_ctx* c, int enable) {
+  if (!c) return MLSGD_EINVAL;
+  return guard_impl(c, [&]() -> int {
+    require(enable == 0 || enable == 1, "enable must be 0 or 1");
+    if (enable && !c->cap_stream) {
+      HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+      c->d_u_graph = (double*)dalloc(c, sizeof(double) * cube(c->nfin));
+      c->d_g_graph = (double*)dalloc(c, sizeof(double) * cube(c->nfin));
+    }
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (!enable) drop_graphs(c);
+    c->graph = enable != 0;
     return MLSGD_OK;
   });
 }
@@ -1289,6 +1586,7 @@ int mlsgd_set_tuning(mlsgd_ctx* c, const mlsgd_tuning* t) {
       c->cache32 = t->cache != 0;
     else
       c->cache64 = t->cache != 0;
+    drop_graphs(c);     // captured graphs point into the plans' memory
     c->plans.clear();   // layouts depend on the tiling and the caches
     return MLSGD_OK;
   });
@@ -1302,6 +1600,9 @@ int mlsgd_destroy(mlsgd_ctx* c) {
     (void)hipEventDestroy(pr.first);
     (void)hipEventDestroy(pr.second);
   }
+  for (auto& kv : c->graphs)
+    if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void* p : c->allocs) (void)hipFree(p);
   if (c->h_epi_out) (void)hipHostFree(c->h_epi_out);
   if (c->h_count) (void)hipHostFree(c->h_count);
@@ -1368,6 +1669,81 @@ int mlsgd_solve_state_adjoint(mlsgd_ctx* c, int level, int coarse, int64_t first
       st->max_relres = std::max(r1, r2);
     }
     if (nc1 + nc2 > 0) {
+      c->err = "some solves missed rtol";
+      return MLSGD_ENOCONV;
+    }
+    return MLSGD_OK;
+  });
+}
+
+// grid halved while its cell count is even: the coarsest grid of n's hierarchy
+static int coarsest_of(int n) {
+  while (n > 3 && !((n - 1) & 1)) n = (n - 1) / 2 + 1;
+  return n;
+}
+
+int mlsgd_solve_sizes(mlsgd_ctx* c, int count, const int* n_list, int level, int64_t first,
+                      double f_value, double* y_out, mlsgd_solve_stats* st) {
+  if (!c) return MLSGD_EINVAL;
+  return guard_impl(c, [&]() -> int {
+    require(count >= 1 && n_list != nullptr, "need count >= 1 and a size list");
+    require(first >= 0 && level >= 0, "need first >= 0 and level >= 0");
+    require(std::isfinite(f_value), "f_value is not finite");
+    std::vector<long long> off(count);
+    long long tot = 0;
+    std::map<int, std::vector<int>, std::greater<int>> fam;  // grid -> problems, largest first
+    for (int j = 0; j < count; ++j) {
+      const int n = n_list[j];
+      require(n >= 5 && n <= 1025 && (n & 1), "grid sizes must be odd, 5 .. 1025");
+      require(coarsest_of(n) <= 9, "grid must coarsen to at most 9 vertices per axis");
+      off[j] = tot;
+      tot += (long long)n * n * n;
+      fam[n].push_back(j);
+    }
+    hipStream_t s = c->stream;
+    int iters = 0, nonconv = 0;
+    double relres = 0.0;
+    for (auto& kv : fam) {
+      const int n = kv.first;
+      const std::vector<int>& js = kv.second;
+      std::vector<Block> blocks;
+      for (int j : js) blocks.push_back(Block{n, level, first + j, 1});
+      Plan* P = get_plan(c, blocks);
+      double*& rhs = c->const_rhs[n];
+      if (!rhs) rhs = (double*)dalloc(c, sizeof(double) * cube(n));
+      fill_interior(n, f_value, rhs, s);
+      Group& gr = P->groups[0];
+      rows_broadcast(n, gr.count, rhs, rows_of(P->sizes[gr.sl].B, gr), s);
+      rows_broadcast(n, gr.count, rhs, gr.b0, s);
+      rows_zero((long long)gr.count * cube(n), gr.x, s);
+      HIPCHK(hipGetLastError());
+      int it = 0, nc = 0;
+      double rr = 0.0;
+      krylov(c, P, &it, &nc, &rr);
+      iters = std::max(iters, it);
+      nonconv += nc;
+      relres = std::max(relres, rr);
+      if (y_out) {
+        if (c->dst_off_len < js.size()) {
+          c->d_dst_off = (long long*)dalloc(c, sizeof(long long) * js.size());
+          c->dst_off_len = js.size();
+        }
+        std::vector<long long> h(js.size());
+        for (size_t k = 0; k < js.size(); ++k) h[k] = off[js[k]];
+        HIPCHK(hipMemcpyAsync(c->d_dst_off, h.data(), sizeof(long long) * h.size(),
+                              hipMemcpyHostToDevice, s));
+        scatter_rows(n, (int)js.size(), c->d_dst_off, gr.x, y_out, s);
+        HIPCHK(hipStreamSynchronize(s));  // h and d_dst_off are reused by the next family
+      }
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    if (st) {
+      st->iterations = iters;
+      st->nonconverged = nonconv;
+      st->max_relres = relres;
+    }
+    if (nonconv > 0) {
       c->err = "some solves missed rtol";
       return MLSGD_ENOCONV;
     }

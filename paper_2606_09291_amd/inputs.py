@@ -68,6 +68,31 @@ def random_smooth_directions(n, count, seed, kmax=3):
     return out
 
 
+ODD_SIZES = (33, 41, 49, 57, 65)
+# the batch of independent solves on grids of random size that accompanies
+# the 257^3 MLMC workload: 300 state solves, f = 1, u = 0, draws keyed by
+# level 6 (beyond the MLMC levels), seed 0
+ODD_SOLVES = {"count": 300, "level": 6, "first": 0, "f_value": 1.0, "seed": 0}
+
+
+def odd_sizes(count, seed=0, level=6, first=0):
+    """Grid sizes of the independent-solve batch: problem j takes
+    ODD_SIZES[floor(5 (w >> 11) / 2^53)], w the first word of the
+    Philox4x64-10 block with key (seed, 0) and counter (0, first + j, level, 1).
+    numpy's Philox advances its counter before each block, so it is started
+    one below the wanted counter."""
+    out = []
+    for j in range(count):
+        v = ((first + j) << 64) | (level << 128) | (1 << 192)
+        v -= 1
+        ctr = np.array([(v >> (64 * i)) & (2 ** 64 - 1) for i in range(4)], dtype=np.uint64)
+        bg = np.random.Philox(key=np.array([seed, 0], dtype=np.uint64), counter=ctr)
+        w = int(bg.random_raw(1)[0])
+        idx = ((w >> 11) * len(ODD_SIZES)) >> 53
+        out.append(ODD_SIZES[idx])
+    return out
+
+
 def grids(first_n, levels):
     """Nested vertex counts n_i = 2 (n_{i-1} - 1) + 1 starting at first_n."""
     out = [first_n]
