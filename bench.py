@@ -44,6 +44,8 @@ def parse():
     ap.add_argument("--mlsgd", action="store_true",
                     help="run the adaptive MLSGD optimisation on the 257^3 workload instead")
     ap.add_argument("--mlsgd-steps", type=int, default=50)
+    ap.add_argument("--rates", action="store_true",
+                    help="level rates (alpha, beta, gamma) of the 129^3 hierarchy per theta")
     ap.add_argument("--thetas", default="1,5,10")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=0)
@@ -213,6 +215,62 @@ def odd_size_solves(m, dev, reps=3):
             "max_relres": st["max_relres"]}
 
 
+def run_rates(args):
+    """Level rates of the 9^3..129^3 hierarchy (FP64) for each theta: per
+    level |E dX|, Var dX, |E dY| averaged over a few estimates with fresh
+    samples, the cost per sample from level-by-level batched solves (measured
+    time and the work model interior unknowns x iterations), and the fitted
+    alpha, beta, gamma and constants (rates.py)."""
+    import dataclasses
+    import torch
+    import paper_2606_09291_amd as m
+    from paper_2606_09291_amd import inputs, rates
+    dev = torch.device("cuda:0")
+    base = inputs.WORKLOADS["mlmc_129"]
+    E = max(2, args.steps)
+    out = {"mode": "rates", "workload": base.name, "estimates_per_theta": E, "runs": []}
+    for th in [float(t) for t in args.thetas.split(",")]:
+        w = dataclasses.replace(base, theta=th)
+        ctx = make_ctx(m, w, dev)
+        u = torch.as_tensor(w.u0(), device=dev).contiguous()
+        L = len(w.grid_n)
+        acc = None
+        off = [0] * L
+        for k in range(E):
+            _, st = ctx.mlmc_gradient(u, w.M, first=off)
+            off = [o + mm for o, mm in zip(off, w.M)]
+            e, V, wy = rates.level_statistics(st, w.M, th)
+            cur = [e, V, wy]
+            acc = cur if acc is None else [[a + b for a, b in zip(x, y)] for x, y in zip(acc, cur)]
+        e, V, wy = [[x / E for x in row] for row in acc]
+        t_meas, work = [], []
+        for lv in range(L):
+            cnt = int(w.M[lv])
+            tot_t, tot_w = 0.0, 0.0
+            for coarse in ((0, 1) if lv > 0 else (0,)):
+                n = w.grid_n[lv - coarse]
+                ctx.solve_state_adjoint(lv, coarse, off[lv], cnt, u, want_y=False)  # warm
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, _, _, sst = ctx.solve_state_adjoint(lv, coarse, off[lv], cnt, u, want_y=False)
+                torch.cuda.synchronize()
+                tot_t += (time.perf_counter() - t0) / cnt
+                tot_w += (n - 2) ** 3 * sst["iterations"]
+            t_meas.append(tot_t)
+            work.append(tot_w)
+        ctx.close()
+        fit_t = rates.fit_rates(w.grid_n, e, V, wy, t_meas)
+        fit_w = rates.fit_rates(w.grid_n, e, V, wy, work)
+        rec = {"theta": th, "grid": w.grid_n, "M": w.M, "norm_mean_dX": e, "var_dX": V,
+               "abs_mean_dY": wy, "seconds_per_sample": t_meas, "work_per_sample": work,
+               "fit": {k: fit_w[k] for k in ("alpha", "beta", "alpha_Y", "C_X", "C_V", "C_Y")},
+               "gamma_work": fit_w["gamma"], "gamma_measured": fit_t["gamma"]}
+        out["runs"].append(rec)
+        log(args, f"theta {th}: alpha {fit_w['alpha']:.3f} beta {fit_w['beta']:.3f} "
+                  f"gamma(work) {fit_w['gamma']:.3f} gamma(time) {fit_t['gamma']:.3f}")
+    print(json.dumps(out))
+
+
 def run_mlsgd(args):
     """Adaptive MLSGD (Algorithm 1): projected steps with step size 1/(1+j),
     batch sizes chosen by the controller after every step."""
@@ -317,6 +375,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args)
+        return
+    if args.rates:
+        run_rates(args)
         return
     if args.mlsgd:
         run_mlsgd(args)

@@ -111,7 +111,8 @@ typedef struct mlsgd_step_stats {
   mlsgd_grad_stats grad;
   int64_t M_next[MLSGD_MAX_LEVELS];  /* sample counts for the next step */
   int64_t offset[MLSGD_MAX_LEVELS];  /* running per-level sample offsets after the step */
-  double err_sam, err_num, eps;      /* adaptive-controller estimates (adapt = 1) */
+  double err_sam, err_num, eps;      /* adaptive-controller estimates (adapt != 0) */
+  double tau;                        /* step size taken */
 } mlsgd_step_stats;
 
 typedef struct mlsgd_ctx mlsgd_ctx;
@@ -200,11 +201,20 @@ int mlsgd_mlmc_objective(mlsgd_ctx* ctx, const double* u_fine, int L,
 int mlsgd_set_batch(mlsgd_ctx* ctx, int L, const int64_t* M,
                     const int64_t* offsets);
 
-/* One projected SGD step u <- Pi(u - tau grad) (Sec. 2.2, Algorithm 1, MLSGD)
- * with fresh samples: the gradient uses the current batch and running
- * offsets, which then advance by M.  adapt = 1 runs the adaptive controller
- * (Sec. 4.1: power sums, optimal batch size, bias estimate) to choose the
- * next batch.  u_inout: device, finest grid.  st: host, nullable. */
+/* One projected SGD step u <- Pi(u - tau_k grad) (Sec. 2.2, Algorithm 1,
+ * MLSGD) with fresh samples: the gradient uses the current batch and running
+ * offsets, which then advance by M.  adapt is a set of flags:
+ * MLSGD_ADAPT_BATCH runs the adaptive controller (Sec. 4.1: power sums,
+ * optimal batch size, bias estimate, level growth) to choose the next batch;
+ * MLSGD_ADAPT_STEP takes the adaptive step size of Sec. 5
+ * (eq. adaptive-step-size: tau_k = (|g_k|^2 - err_sam) / (Lhat |g_k|^2),
+ * Lhat = |g_k - g_{k-1}| / (tau_{k-1} |g_{k-1}|), clamped at 0), with tau as
+ * the step of the first step after mlsgd_set_batch and as the fallback when
+ * Lhat is undefined.  Without MLSGD_ADAPT_STEP tau is the step.  Either flag
+ * needs M >= 2 on every level.  u_inout: device, finest grid.  st: host,
+ * nullable (st->tau: the step taken). */
+#define MLSGD_ADAPT_BATCH 1
+#define MLSGD_ADAPT_STEP 2
 int mlsgd_step(mlsgd_ctx* ctx, double* u_inout, double tau, int adapt,
                mlsgd_step_stats* st);
 

@@ -88,3 +88,11 @@ def control(stats, M, grid, theta, grad_norm, n_levels_max=None):
         Lnew = L + 1
     return {"M_next": Mn, "L": Lnew, "err_sam": sampling_error(v2, M), "err_num": err_num,
             "eps": eps, "alpha_hat": ahat, "v2": v2}
+
+
+def adaptive_step(g_norm, err_sam, diff_norm, tau_prev, g_prev_norm):
+    """Adaptive step size of Sec. 5 (eq. adaptive-step-size):
+    Lhat = |g_k - g_{k-1}| / (tau_{k-1} |g_{k-1}|),
+    tau_k = (|g_k|^2 - err_sam_k) / (Lhat |g_k|^2), clamped at 0 from below."""
+    Lhat = diff_norm / (tau_prev * g_prev_norm)
+    return max(0.0, (g_norm ** 2 - err_sam) / (Lhat * g_norm ** 2))

@@ -26,6 +26,7 @@ EXPORTS = [
     "mlsgd_get_tuning", "mlsgd_set_tuning", "mlsgd_set_graph",
 ]
 SMOOTHER_RBGS, SMOOTHER_RBGS_FUSED, SMOOTHER_CHEBYSHEV = 0, 1, 2
+ADAPT_BATCH, ADAPT_STEP = 1, 2
 TUNING_FILE = os.path.join(HERE, "tuning.json")
 
 
@@ -99,7 +100,8 @@ class _Tuning(ctypes.Structure):
 class _StepStats(ctypes.Structure):
     _fields_ = [("grad", _GradStats), ("M_next", ctypes.c_int64 * MAX_LEVELS),
                 ("offset", ctypes.c_int64 * MAX_LEVELS), ("err_sam", ctypes.c_double),
-                ("err_num", ctypes.c_double), ("eps", ctypes.c_double)]
+                ("err_num", ctypes.c_double), ("eps", ctypes.c_double),
+                ("tau", ctypes.c_double)]
 
 
 _lib = None
@@ -337,18 +339,21 @@ class Context:
                                       _i64_array(offsets, L) if offsets is not None else None)
         self._check(rc)
 
-    def step(self, u, tau, adapt=False, allow_noconv=False):
-        """In-place projected SGD step on the device tensor u (float64, n^3)."""
+    def step(self, u, tau, adapt=False, adapt_step=False, allow_noconv=False):
+        """In-place projected SGD step on the device tensor u (float64, n^3).
+        adapt: adaptive batch controller; adapt_step: adaptive step size (tau is
+        then the first step and the fallback)."""
         if not (u.is_cuda and u.dtype == _torch().float64 and u.is_contiguous()):
             raise ValueError("u must be a contiguous float64 device tensor")
         st = _StepStats()
-        rc = self.lib.mlsgd_step(self._h, ctypes.c_void_p(u.data_ptr()), float(tau),
-                                 1 if adapt else 0, ctypes.byref(st))
+        flags = (ADAPT_BATCH if adapt else 0) | (ADAPT_STEP if adapt_step else 0)
+        rc = self.lib.mlsgd_step(self._h, ctypes.c_void_p(u.data_ptr()), float(tau), flags,
+                                 ctypes.byref(st))
         self._check(rc, allow_noconv)
         L = self.L
         return {"grad": st.grad.as_dict(L), "M_next": list(st.M_next)[:L],
                 "offset": list(st.offset)[:L], "err_sam": st.err_sam, "err_num": st.err_num,
-                "eps": st.eps}
+                "eps": st.eps, "tau": st.tau}
 
 
     def get_tuning(self):

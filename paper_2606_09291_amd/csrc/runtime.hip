@@ -155,6 +155,12 @@ struct mlsgd_ctx {
   int64_t cur_M[MLSGD_MAX_LEVELS] = {0};
   int64_t cur_off[MLSGD_MAX_LEVELS] = {0};
   double prev_gnorm = -1.0;
+  // adaptive step size: the previous gradient and step
+  double* d_gprev = nullptr;
+  double* d_gtmp = nullptr;
+  double* d_sc1 = nullptr;   // one device double
+  bool have_gprev = false;
+  double tau_prev = 0.0, tau_pos = 0.0, gnorm_prev = 0.0;
   hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
   // tunables of the solver (defaults from measurement; overridable for tuning)
   int nu = 2;               // smoothing sweeps before and after the coarse correction
@@ -1784,8 +1790,34 @@ int mlsgd_set_batch(mlsgd_ctx* c, int L, const int64_t* M, const int64_t* offset
       c->cur_off[i] = (offsets && i < L) ? offsets[i] : 0;
     }
     c->prev_gnorm = -1.0;
+    c->have_gprev = false;
     return MLSGD_OK;
   });
+}
+
+// Adaptive step size (Sec. 5, eq. adaptive-step-size): with g_k the
+// estimate just computed and g_{k-1}, tau_{k-1} those of the previous step,
+//   Lhat  = |g_k - g_{k-1}|_h / (tau_{k-1} |g_{k-1}|_h)
+//   tau_k = (|g_k|_h^2 - err_sam_k) / (Lhat |g_k|_h^2),
+// clamped at 0 from below.  The first step of a batch uses the given tau; a
+// step after a zero step, or an undefined Lhat, reuses the last positive one.
+double adaptive_tau(mlsgd_ctx* c, double tau0, double gnorm, double err_sam) {
+  if (!c->have_gprev) return tau0;
+  if (!(c->tau_prev > 0.0) || !(c->gnorm_prev > 0.0)) return c->tau_pos > 0.0 ? c->tau_pos : tau0;
+  hipStream_t s = c->stream;
+  const long long N = (long long)cube(c->nfin);
+  copy_rows_strided(c->nfin, 1, c->d_grad, c->d_gtmp, s);
+  axpy_full(c->nfin, -1.0, c->d_gprev, c->d_gtmp, s);
+  dot_blocks(N, c->d_gtmp, c->d_gtmp, c->d_epi_part, s);
+  finish_norm(c->nfin, c->d_epi_part, c->d_sc1, s);
+  double diff2 = 0.0;
+  HIPCHK(hipMemcpyAsync(&diff2, c->d_sc1, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double Lhat = std::sqrt(diff2) / (c->tau_prev * c->gnorm_prev);
+  const double g2 = gnorm * gnorm;
+  if (!(Lhat > 0.0) || !std::isfinite(Lhat) || !(g2 > 0.0))
+    return c->tau_pos > 0.0 ? c->tau_pos : tau0;
+  return std::max(0.0, (g2 - err_sam) / (Lhat * g2));
 }
 
 int mlsgd_step(mlsgd_ctx* c, double* u, double tau, int adapt, mlsgd_step_stats* st) {
@@ -1793,24 +1825,44 @@ int mlsgd_step(mlsgd_ctx* c, double* u, double tau, int adapt, mlsgd_step_stats*
   return guard_impl(c, [&]() -> int {
     require(u != nullptr, "u is null");
     require(std::isfinite(tau), "tau must be finite");
+    require(adapt >= 0 && adapt <= (MLSGD_ADAPT_BATCH | MLSGD_ADAPT_STEP),
+            "adapt must combine MLSGD_ADAPT_BATCH and MLSGD_ADAPT_STEP");
     require(c->cur_M[0] >= 1, "call mlsgd_set_batch first");
     if (adapt)
       for (int i = 0; i < c->cur_L; ++i) require(c->cur_M[i] >= 2, "adapt needs M >= 2");
+    if ((adapt & MLSGD_ADAPT_STEP) && !c->d_gprev) {
+      c->d_gprev = (double*)dalloc(c, sizeof(double) * cube(c->nfin));
+      c->d_gtmp = (double*)dalloc(c, sizeof(double) * cube(c->nfin));
+      c->d_sc1 = (double*)dalloc(c, sizeof(double));
+    }
     mlsgd_grad_stats g{};
     const int rc = run_estimate(c, u, c->cur_L, c->cur_M, c->cur_off, c->d_grad, nullptr, &g);
     if (rc != MLSGD_OK && rc != MLSGD_ENOCONV) return rc;
-    const bool box = c->pb.u_lo <= c->pb.u_hi;
-    box_step(c->nfin, u, c->d_grad, tau, c->pb.u_lo, c->pb.u_hi, box ? 1 : 0, c->stream);
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
     mlsgd_step_stats loc{};
-    for (int i = 0; i < c->cur_L; ++i) c->cur_off[i] += c->cur_M[i];
-    c->prev_gnorm = g.grad_norm;
+    CtrlOut o{};
     if (adapt) {
-      const CtrlOut o = controller(c, g, c->cur_L, c->cur_M);
+      o = controller(c, g, c->cur_L, c->cur_M);
       loc.err_sam = o.err_sam;
       loc.err_num = o.err_num;
       loc.eps = o.eps;
+    }
+    double tk = tau;
+    if (adapt & MLSGD_ADAPT_STEP) {
+      tk = adaptive_tau(c, tau, g.grad_norm, o.err_sam);
+      copy_rows_strided(c->nfin, 1, c->d_grad, c->d_gprev, c->stream);
+      c->have_gprev = true;
+      c->tau_prev = tk;
+      if (tk > 0.0) c->tau_pos = tk;
+      c->gnorm_prev = g.grad_norm;
+    }
+    loc.tau = tk;
+    const bool box = c->pb.u_lo <= c->pb.u_hi;
+    box_step(c->nfin, u, c->d_grad, tk, c->pb.u_lo, c->pb.u_hi, box ? 1 : 0, c->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int i = 0; i < c->cur_L; ++i) c->cur_off[i] += c->cur_M[i];
+    c->prev_gnorm = g.grad_norm;
+    if (adapt & MLSGD_ADAPT_BATCH) {
       for (int i = 0; i < o.L; ++i) c->cur_M[i] = o.M[i];
       c->cur_L = o.L;
     }

@@ -65,3 +65,35 @@ def test_sampling_error_and_level_growth():
     out2 = ctl.control(stats, [20, 10, 5], [9, 17, 33], theta=0.0, grad_norm=0.01,
                        n_levels_max=3)
     assert out2["L"] == 3
+
+
+def test_adaptive_step_is_exact_line_search_on_quadratics():
+    """J(u) = 1/2 u^T H u - b^T u with exact gradients (err_sam = 0): along an
+    eigenvector of H the estimate Lhat is the eigenvalue, so the step is 1/lam
+    and lands on the minimiser in that direction; scaling J by c scales the
+    step by 1/c; a gradient below the sampling error gives no step."""
+    rng = np.random.default_rng(3)
+    lam = rng.uniform(0.5, 20.0, size=6)
+    H = np.diag(lam)
+    b = rng.standard_normal(6)
+    ustar = b / lam
+    for j in range(6):
+        e = np.zeros(6)
+        e[j] = 1.0
+        u0 = ustar + 3.0 * e
+        g0 = H @ u0 - b
+        tau0 = 0.05
+        u1 = u0 - tau0 * g0
+        g1 = H @ u1 - b
+        tau1 = ctl.adaptive_step(np.linalg.norm(g1), 0.0, np.linalg.norm(g1 - g0), tau0,
+                                 np.linalg.norm(g0))
+        assert tau1 == pytest.approx(1.0 / lam[j], rel=1e-12)
+        u2 = u1 - tau1 * g1
+        assert np.linalg.norm(H @ u2 - b) <= 1e-12 * np.linalg.norm(g0)
+        for c in (0.1, 7.0):
+            gc0 = c * g0
+            gc1 = c * (H @ (u0 - tau0 * gc0) - b)
+            t = ctl.adaptive_step(np.linalg.norm(gc1), 0.0, np.linalg.norm(gc1 - gc0), tau0,
+                                  np.linalg.norm(gc0))
+            assert t == pytest.approx(1.0 / (c * lam[j]), rel=1e-12)
+    assert ctl.adaptive_step(1.0, 2.0, 0.5, 0.1, 1.0) == 0.0
