@@ -78,7 +78,7 @@ def make_ctx(m, w, dev):
     solver = m.SOLVER_CG if w.solver == "cg" else m.SOLVER_MGPCG
     pb = m.Problem(grid_n=w.grid_n, y_d=w.y_d(), f=w.f() if w.f_value else None, seed=w.seed,
                    K=w.K, sigma2=w.sigma2, theta=w.theta, alpha=w.alpha, precision=prec,
-                   solver=solver, rtol=w.rtol, max_iters=200)
+                   solver=solver, rtol=w.rtol, max_iters=200, law=w.law, rho=w.rho)
     return m.Context(pb, device=dev)
 
 
@@ -495,6 +495,16 @@ def main():
             "value": vg, "ms_per_step": 1e3 / vg, "solves_per_s": s257 * vg}
         log(args, "odd-size solve batch")
         out["odd_size_solves"] = odd_size_solves(m, dev)
+        wp = inputs.WORKLOADS["paper_law_65"]
+        log(args, "Sec. 5 law workload")
+        kp = max(2, args.steps)
+        rp = run(args, m, wp, dev, kp, 1)
+        sp, up = problem_counts(wp.grid_n, wp.M)
+        vp = kp / rp["dt"]
+        out["paper_law"] = {"workload": wp.name, "value": vp, "unit": "gradient estimates/s",
+                            "ms_per_step": 1e3 / vp, "solves_per_s": sp * vp,
+                            "iters_state": max(x["iters_state"] for x in rp["stats"]),
+                            "iters_adjoint": max(x["iters_adjoint"] for x in rp["stats"])}
     if not args.no_per_sample:
         log(args, "per-sample FP64 comparator")
         ps = per_sample_fp64(m, inputs.WORKLOADS[args.mixed_workload], dev)

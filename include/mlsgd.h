@@ -78,7 +78,20 @@ typedef struct mlsgd_problem {
   double u_lo, u_hi;                   /* box of U_ad; u_lo > u_hi means no box */
   const double* f;                     /* device, finest grid, nullable (= 0) */
   const double* y_d;                   /* device, finest grid target */
+  int32_t kl_law;                      /* MLSGD_LAW_*: law of the KL draws */
+  double kl_rho;                       /* correlation length of MLSGD_LAW_EXPONENTIAL, > 0 */
 } mlsgd_problem;
+
+/* Laws of the KL expansion log a = sum c_k phi_k with c = sqrt(sigma2 lam) xi.
+ * ALGEBRAIC: xi ~ N(0, 1), lam_k = (1 + |k|^2)^(-5/2),
+ *   phi_k = cos(k1 pi x) cos(k2 pi y) cos(k3 pi z), draw t = ((k1-1)K + (k2-1))K + (k3-1).
+ * EXPONENTIAL (Sec. 5): xi ~ U(-4, 4), lam_jkl = exp(-pi (j + k + l) rho),
+ *   phi_jkl = cos(j pi y) cos(k pi z) cos(l pi x), draw t = ((j-1)K + (k-1))K + (l-1).
+ * Both draw from Philox4x64-10 (key (seed, 0), counter (block, sample,
+ * level, 0)), four 53-bit uniforms u = ((w >> 11) + 1/2) 2^-53 per block:
+ * normals by Box-Muller on the pairs (u0, u1), (u2, u3); uniforms -4 + 8 u. */
+#define MLSGD_LAW_ALGEBRAIC 0
+#define MLSGD_LAW_EXPONENTIAL 1
 
 typedef struct mlsgd_solve_stats {
   int32_t iterations;      /* outer iterations of the slowest solve */
@@ -132,8 +145,9 @@ int mlsgd_destroy(mlsgd_ctx* ctx);
 const char* mlsgd_last_error(const mlsgd_ctx* ctx);
 
 /* Draw xi for samples first .. first+count-1 of `level` (the random input of
- * one sample, Sec. 2.2 "draw xi^(m,l)"): xi_out is device memory of
- * count * K^3 doubles, sample-major.  Errors: MLSGD_EINVAL for level out of
+ * one sample, Sec. 2.2 "draw xi^(m,l)"), in draw order under the context's
+ * law (MLSGD_LAW_*): xi_out is device memory of count * K^3 doubles,
+ * sample-major.  Errors: MLSGD_EINVAL for level out of
  * range, count < 0, first < 0 or a null xi_out with count > 0. */
 int mlsgd_sample_fields(mlsgd_ctx* ctx, int level, int64_t first, int64_t count,
                         double* xi_out);

@@ -31,6 +31,8 @@ class OrProblem(ctypes.Structure):
         ("maxit", ctypes.c_int),
         ("nthreads", ctypes.c_int),
         ("common_xi", ctypes.c_int),
+        ("law", ctypes.c_int),
+        ("rho", ctypes.c_double),
     ]
 
 
@@ -79,6 +81,9 @@ def lib():
         L.or_philox_words.argtypes = [u64, ctypes.c_int, i64, ctypes.c_int, ctypes.c_int, P(u64)]
         L.or_normals.argtypes = [u64, ctypes.c_int, i64, ctypes.c_int, ctypes.c_int, P(d)]
         L.or_kl_coeffs.argtypes = [u64, ctypes.c_int, i64, ctypes.c_int, d, P(d)]
+        L.or_draws.argtypes = [u64, ctypes.c_int, i64, ctypes.c_int, ctypes.c_int, P(d)]
+        L.or_kl_coeffs_law.argtypes = [u64, ctypes.c_int, i64, ctypes.c_int, d, ctypes.c_int, d,
+                                       P(d)]
         L.or_log_coeff.argtypes = [ctypes.c_int, ctypes.c_int, P(d), P(d)]
         L.or_apply.argtypes = [ctypes.c_int, ctypes.c_int, P(d), P(d), P(d)]
         L.or_assemble_dense.argtypes = [ctypes.c_int, ctypes.c_int, P(d), P(d)]
@@ -128,9 +133,19 @@ def normals(seed, level, sample, tag, count):
     return out
 
 
-def kl_coeffs(seed, level, sample, K, sigma2=1.0):
+LAW_ALGEBRAIC, LAW_EXPONENTIAL = 0, 1
+
+
+def kl_coeffs(seed, level, sample, K, sigma2=1.0, law=LAW_ALGEBRAIC, rho=0.15):
     out = np.zeros(K ** 3)
-    lib().or_kl_coeffs(seed, level, sample, K, sigma2, _dp(out))
+    lib().or_kl_coeffs_law(seed, level, sample, K, sigma2, law, rho, _dp(out))
+    return out
+
+
+def draws(seed, level, sample, K, law=LAW_ALGEBRAIC):
+    """The K^3 draws xi of one sample in draw order under the given law."""
+    out = np.zeros(K ** 3)
+    lib().or_draws(seed, level, sample, K, law, _dp(out))
     return out
 
 
@@ -190,7 +205,7 @@ def misfit(n, y, yd):
 
 def make_problem(grid_n, seed=0, K=4, sigma2=1.0, theta=1.0, alpha=1e-3,
                  method=SOLVE_AUTO, rtol=1e-13, maxit=2000, nthreads=None,
-                 common_xi=False):
+                 common_xi=False, law=LAW_ALGEBRAIC, rho=0.15):
     pb = OrProblem()
     pb.L = len(grid_n)
     for i, n in enumerate(grid_n):
@@ -205,6 +220,8 @@ def make_problem(grid_n, seed=0, K=4, sigma2=1.0, theta=1.0, alpha=1e-3,
     pb.maxit = maxit
     pb.nthreads = nthreads if nthreads else min(16, os.cpu_count() or 1)
     pb.common_xi = 1 if common_xi else 0
+    pb.law = law
+    pb.rho = rho
     return pb
 
 

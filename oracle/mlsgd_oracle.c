@@ -93,6 +93,52 @@ void or_normals(uint64_t seed, int level, int64_t sample, int tag, int count,
   }
 }
 
+/* The K^3 draws of one sample in draw order: normals for the algebraic law,
+ * xi = -4 + 8 u on the 53-bit uniforms u of the same Philox words for the
+ * exponential law (Sec. 5: xi_jkl ~ U(-4, 4)). */
+void or_draws(uint64_t seed, int level, int64_t sample, int K, int law, double* xi) {
+  int nt = K * K * K;
+  if (law == OR_LAW_ALGEBRAIC) {
+    or_normals(seed, level, sample, 0, nt, xi);
+    return;
+  }
+  int nblocks = (nt + 3) / 4;
+  for (int b = 0; b < nblocks; ++b) {
+    uint64_t key[2] = {seed, 0};
+    uint64_t ctr[4] = {(uint64_t)b, (uint64_t)sample, (uint64_t)level, 0};
+    uint64_t w[4];
+    or_philox4x64_10(ctr, key, w);
+    for (int q = 0; q < 4; ++q) {
+      double u = ((double)(w[q] >> 11) + 0.5) * 0x1.0p-53;
+      if (4 * b + q < nt) xi[4 * b + q] = -4.0 + 8.0 * u;
+    }
+  }
+}
+
+/* KL coefficients under either law (Sec. 5 for the exponential one: the
+ * term (j, k, l) multiplies cos(j pi x_2) cos(k pi x_3) cos(l pi x_1), so in
+ * the x-major product index it sits at (k1, k2, k3) = (l, j, k)). */
+void or_kl_coeffs_law(uint64_t seed, int level, int64_t sample, int K, double sigma2,
+                      int law, double rho, double* c) {
+  if (law == OR_LAW_ALGEBRAIC) {
+    or_kl_coeffs(seed, level, sample, K, sigma2, c);
+    return;
+  }
+  int nt = K * K * K;
+  double* xi = (double*)malloc(sizeof(double) * (size_t)nt);
+  or_draws(seed, level, sample, K, law, xi);
+  double sigma = sqrt(sigma2);
+  for (int j = 1; j <= K; ++j)
+    for (int k = 1; k <= K; ++k)
+      for (int l = 1; l <= K; ++l) {
+        int t = ((j - 1) * K + (k - 1)) * K + (l - 1);
+        int e = ((l - 1) * K + (j - 1)) * K + (k - 1);
+        double lam = exp(-OR_PI * (double)(j + k + l) * rho);
+        c[e] = sigma * sqrt(lam) * xi[t];
+      }
+  free(xi);
+}
+
 /* KL coefficients c_j = sigma sqrt(lam_k) xi_j, lam_k = (1 + |k|^2)^(-5/2),
  * for the coefficient law of the experiments (Sec. 5, with the decay and
  * normal law of the synthetic workloads). */
@@ -694,7 +740,8 @@ static int run_pairs(const or_problem* pb, const double* f, const double* u,
     int nf = pb->n[i];
     int K = pb->K;
     double* c = (double*)malloc(sizeof(double) * (size_t)(K * K * K));
-    or_kl_coeffs(pb->seed, pb->common_xi ? 0 : i, pr->m, K, pb->sigma2, c);
+    or_kl_coeffs_law(pb->seed, pb->common_xi ? 0 : i, pr->m, K, pb->sigma2, pb->law, pb->rho,
+                     c);
     size_t Nf = (size_t)nf * nf * nf;
     int itf = 0, itc = 0;
     double rf = 0.0, rc = 0.0;

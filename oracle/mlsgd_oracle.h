@@ -53,7 +53,17 @@ typedef struct or_problem {
   int maxit;
   int nthreads;             /* OpenMP threads for the (level, sample) loop */
   int common_xi;            /* test switch: key every level's draws as level 0 */
+  int law;                  /* OR_LAW_*: law of the KL draws */
+  double rho;               /* correlation length of OR_LAW_EXPONENTIAL */
 } or_problem;
+
+/* KL laws.  ALGEBRAIC: xi ~ N(0,1), lam = (1 + |k|^2)^(-5/2), phi_k =
+ * cos(k1 pi x) cos(k2 pi y) cos(k3 pi z).  EXPONENTIAL (Sec. 5): xi ~
+ * U(-4,4), lam_jkl = exp(-pi (j+k+l) rho), phi_jkl = cos(j pi y) cos(k pi z)
+ * cos(l pi x).  Coefficients are returned at the index of the product
+ * cos(k1 pi x) cos(k2 pi y) cos(k3 pi z), ((k1-1) K + (k2-1)) K + (k3-1). */
+#define OR_LAW_ALGEBRAIC 0
+#define OR_LAW_EXPONENTIAL 1
 
 typedef struct or_stats {
   double s;                          /* max Phi over the estimate (shift) */
@@ -78,6 +88,9 @@ void or_normals(uint64_t seed, int level, int64_t sample, int tag, int count,
                 double* out);
 void or_kl_coeffs(uint64_t seed, int level, int64_t sample, int K,
                   double sigma2, double* c);
+void or_draws(uint64_t seed, int level, int64_t sample, int K, int law, double* xi);
+void or_kl_coeffs_law(uint64_t seed, int level, int64_t sample, int K, double sigma2,
+                      int law, double rho, double* c);
 void or_log_coeff(int n, int K, const double* c, double* loga);
 void or_apply(int n, int K, const double* c, const double* y, double* out);
 void or_assemble_dense(int n, int K, const double* c, double* Adense);

@@ -27,6 +27,7 @@ EXPORTS = [
 ]
 SMOOTHER_RBGS, SMOOTHER_RBGS_FUSED, SMOOTHER_CHEBYSHEV = 0, 1, 2
 ADAPT_BATCH, ADAPT_STEP = 1, 2
+LAW_ALGEBRAIC, LAW_EXPONENTIAL = 0, 1
 TUNING_FILE = os.path.join(HERE, "tuning.json")
 
 
@@ -57,6 +58,8 @@ class _Problem(ctypes.Structure):
         ("u_hi", ctypes.c_double),
         ("f", ctypes.c_void_p),
         ("y_d", ctypes.c_void_p),
+        ("kl_law", ctypes.c_int32),
+        ("kl_rho", ctypes.c_double),
     ]
 
 
@@ -179,6 +182,8 @@ class Problem:
     max_iters: int = 500
     u_lo: float = 1.0
     u_hi: float = -1.0               # u_lo > u_hi: no box constraint
+    law: int = 0                     # LAW_ALGEBRAIC or LAW_EXPONENTIAL (Sec. 5)
+    rho: float = 0.15                # correlation length of LAW_EXPONENTIAL
     extra: dict = field(default_factory=dict)
 
 
@@ -211,6 +216,8 @@ class Context:
         pb.max_iters = int(problem.max_iters)
         pb.u_lo = float(problem.u_lo)
         pb.u_hi = float(problem.u_hi)
+        pb.kl_law = int(problem.law)
+        pb.kl_rho = float(problem.rho)
         pb.f = self._f.data_ptr() if self._f is not None else None
         pb.y_d = self._yd.data_ptr()
         h = ctypes.c_void_p()

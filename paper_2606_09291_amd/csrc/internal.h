@@ -94,9 +94,10 @@ void fill_interior(int n, double v, double* out, hipStream_t s);
 
 // ---- random field ----
 void kl_coeffs(const int* prob_level, const int64_t* prob_sample, int nprob,
-               uint64_t seed, int K, double sigma2, double* coef, hipStream_t s);
-void kl_normals(uint64_t seed, int level, int64_t first, int64_t count, int K3,
-                double* xi, hipStream_t s);
+               uint64_t seed, int K, double sigma2, int law, double rho, double* coef,
+               hipStream_t s);
+void kl_draws(uint64_t seed, int level, int64_t first, int64_t count, int K3, int law,
+              double* xi, hipStream_t s);
 void philox_words(uint64_t seed, int level, int64_t sample, int tag, int nblocks,
                   uint64_t* out, hipStream_t s);
 void cos_table(int n, int K, double* out, hipStream_t s);

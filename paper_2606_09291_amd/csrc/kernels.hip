@@ -1221,9 +1221,41 @@ __device__ __forceinline__ void normals4(uint64_t seed, int level, int64_t sampl
   }
 }
 
+// Four draws of block blk in draw order: law 0 standard normals (Box-Muller),
+// law 1 uniforms on (-4, 4) (xi = -4 + 8 u of the same 53-bit uniforms).
+__device__ __forceinline__ void draws4(uint64_t seed, int level, int64_t sample, int blk,
+                                       int law, double z[4]) {
+  if (law == 0) {
+    normals4(seed, level, sample, 0, blk, z);
+    return;
+  }
+  uint64_t w[4];
+  philox_block((uint64_t)blk, (uint64_t)sample, (uint64_t)level, 0ULL, seed, 0ULL, w);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) z[q] = -4.0 + 8.0 * (((double)(w[q] >> 11) + 0.5) * 0x1.0p-53);
+}
+
+// KL coefficient of draw t, stored at its evaluation index (k1, k2, k3) <->
+// cos(k1 pi x) cos(k2 pi y) cos(k3 pi z), e = ((k1-1) K + (k2-1)) K + (k3-1).
+// law 0: t = e, lam = (1 + |k|^2)^(-5/2).
+// law 1 (Sec. 5): draw t = ((j-1) K + (k-1)) K + (l-1) multiplies
+// cos(j pi y) cos(k pi z) cos(l pi x), so it lands at (k1, k2, k3) = (l, j, k);
+// lam = exp(-pi (j + k + l) rho).
+__device__ __forceinline__ void kl_term(int t, int K, int law, double rho, int* e, double* lam) {
+  const int a = t / (K * K) + 1, b = (t / K) % K + 1, c = t % K + 1;
+  if (law == 0) {
+    *e = t;
+    *lam = pow(1.0 + (double)(a * a + b * b + c * c), -2.5);
+  } else {
+    *e = ((c - 1) * K + (a - 1)) * K + (b - 1);
+    *lam = exp(-3.14159265358979323846 * (double)(a + b + c) * rho);
+  }
+}
+
 __global__ void k_kl_coeffs(const int* __restrict__ prob_level,
                             const int64_t* __restrict__ prob_sample, int nprob, uint64_t seed,
-                            int K, double sigma2, double* __restrict__ coef) {
+                            int K, double sigma2, int law, double rho,
+                            double* __restrict__ coef) {
   const int K3 = K * K * K;
   const int nblk = (K3 + 3) / 4;
   const long long total = (long long)nprob * nblk;
@@ -1231,19 +1263,19 @@ __global__ void k_kl_coeffs(const int* __restrict__ prob_level,
        i += (long long)gridDim.x * blockDim.x) {
     const int p = (int)(i / nblk), b = (int)(i % nblk);
     double z[4];
-    normals4(seed, prob_level[p], prob_sample[p], 0, b, z);
+    draws4(seed, prob_level[p], prob_sample[p], b, law, z);
     for (int q = 0; q < 4; ++q) {
-      const int j = 4 * b + q;
-      if (j >= K3) break;
-      const int k1 = j / (K * K) + 1, k2 = (j / K) % K + 1, k3 = j % K + 1;
-      const double lam = pow(1.0 + (double)(k1 * k1 + k2 * k2 + k3 * k3), -2.5);
-      coef[(size_t)p * K3 + j] = sqrt(sigma2) * sqrt(lam) * z[q];
+      const int t = 4 * b + q;
+      if (t >= K3) break;
+      int e;
+      double lam;
+      kl_term(t, K, law, rho, &e, &lam);
+      coef[(size_t)p * K3 + e] = sqrt(sigma2) * sqrt(lam) * z[q];
     }
   }
 }
-
-__global__ void k_kl_normals(uint64_t seed, int level, int64_t first, int64_t count, int K3,
-                             double* __restrict__ xi) {
+__global__ void k_kl_draws(uint64_t seed, int level, int64_t first, int64_t count, int K3,
+                           int law, double* __restrict__ xi) {
   const int nblk = (K3 + 3) / 4;
   const long long total = count * nblk;
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
@@ -1251,7 +1283,7 @@ __global__ void k_kl_normals(uint64_t seed, int level, int64_t first, int64_t co
     const long long m = i / nblk;
     const int b = (int)(i % nblk);
     double z[4];
-    normals4(seed, level, first + m, 0, b, z);
+    draws4(seed, level, first + m, b, law, z);
     for (int q = 0; q < 4; ++q) {
       const int j = 4 * b + q;
       if (j < K3) xi[m * K3 + j] = z[q];
@@ -1277,18 +1309,18 @@ __global__ void k_cos_table(int n, int K, double* out) {
 }
 
 void kl_coeffs(const int* prob_level, const int64_t* prob_sample, int nprob, uint64_t seed,
-               int K, double sigma2, double* coef, hipStream_t s) {
+               int K, double sigma2, int law, double rho, double* coef, hipStream_t s) {
   if (nprob <= 0) return;
   const long long total = (long long)nprob * ((K * K * K + 3) / 4);
   hipLaunchKernelGGL(k_kl_coeffs, dim3(grid_for(total, 256)), dim3(256), 0, s, prob_level,
-                     prob_sample, nprob, seed, K, sigma2, coef);
+                     prob_sample, nprob, seed, K, sigma2, law, rho, coef);
 }
-void kl_normals(uint64_t seed, int level, int64_t first, int64_t count, int K3, double* xi,
-                hipStream_t s) {
+void kl_draws(uint64_t seed, int level, int64_t first, int64_t count, int K3, int law,
+              double* xi, hipStream_t s) {
   if (count <= 0) return;
   const long long total = count * ((K3 + 3) / 4);
-  hipLaunchKernelGGL(k_kl_normals, dim3(grid_for(total, 256)), dim3(256), 0, s, seed, level,
-                     first, count, K3, xi);
+  hipLaunchKernelGGL(k_kl_draws, dim3(grid_for(total, 256)), dim3(256), 0, s, seed, level,
+                     first, count, K3, law, xi);
 }
 void philox_words(uint64_t seed, int level, int64_t sample, int tag, int nblocks, uint64_t* out,
                   hipStream_t s) {

@@ -369,8 +369,8 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks, bool fields = tru
 // the dense coarsest inverses.
 void plan_fields(mlsgd_ctx* c, Plan* P) {
   const int K = c->pb.kl_K;
-  kl_coeffs(P->d_level, P->d_sample, P->nprob, c->pb.seed, K, c->pb.kl_sigma2, P->d_coef,
-            c->stream);
+  kl_coeffs(P->d_level, P->d_sample, P->nprob, c->pb.seed, K, c->pb.kl_sigma2, c->pb.kl_law,
+            c->pb.kl_rho, P->d_coef, c->stream);
   // the coefficient is regenerated from the draws once per call for the
   // cached sweeps (the Krylov matvec and residual always run in FP64)
   for (auto& sl : P->sizes)
@@ -1449,6 +1449,10 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     require(pb->kl_K >= 1 && pb->kl_K <= MLSGD_MAX_K, "kl_K out of range");
     require(pb->kl_sigma2 >= 0.0 && std::isfinite(pb->kl_sigma2), "kl_sigma2 must be >= 0");
     require(pb->theta >= 0.0 && std::isfinite(pb->theta), "theta must be >= 0");
+    require(pb->kl_law == MLSGD_LAW_ALGEBRAIC || pb->kl_law == MLSGD_LAW_EXPONENTIAL,
+            "kl_law must be MLSGD_LAW_ALGEBRAIC or MLSGD_LAW_EXPONENTIAL");
+    require(pb->kl_law != MLSGD_LAW_EXPONENTIAL || (pb->kl_rho > 0.0 && std::isfinite(pb->kl_rho)),
+            "kl_rho must be > 0 for MLSGD_LAW_EXPONENTIAL");
     require(pb->alpha >= 0.0 && std::isfinite(pb->alpha), "alpha must be >= 0");
     require(pb->precision == MLSGD_FP64 || pb->precision == MLSGD_MIXED_FP32 ||
                 pb->precision == MLSGD_MIXED_BF16,
@@ -1628,7 +1632,7 @@ int mlsgd_sample_fields(mlsgd_ctx* c, int level, int64_t first, int64_t count, d
     require(first >= 0 && count >= 0, "first and count must be >= 0");
     require(count == 0 || xi_out != nullptr, "xi_out is null");
     const int K3 = c->pb.kl_K * c->pb.kl_K * c->pb.kl_K;
-    kl_normals(c->pb.seed, level, first, count, K3, xi_out, c->stream);
+    kl_draws(c->pb.seed, level, first, count, K3, c->pb.kl_law, xi_out, c->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
     return MLSGD_OK;

@@ -119,6 +119,9 @@ class Workload:
     u_kind: str = "xyz"            # "zero" | "xyz"
     steps: int = 1
     tau: Optional[float] = None
+    law: int = 0                   # 0 algebraic (N(0,1), (1+|k|^2)^-5/2); 1 exponential (Sec. 5)
+    rho: float = 0.15              # correlation length of the exponential law
+    target_freq: int = 1           # y_d = prod sin(freq pi x_d)
     extra: dict = field(default_factory=dict)
 
     def u0(self):
@@ -129,7 +132,7 @@ class Workload:
         return constant(self.grid_n[-1], self.f_value)
 
     def y_d(self):
-        return target_sin(self.grid_n[-1])
+        return target_sin(self.grid_n[-1], freq=self.target_freq)
 
 
 # The five synthetic workloads (sizes of the paper's 3-D experiments: nested
@@ -153,6 +156,14 @@ WORKLOADS = {
     "mlmc_257_batched": Workload(
         name="MLMC gradient, levels 9^3..257^3, M=8192/2048/512/128/32/8",
         grid_n=grids(9, 6), M=[8192, 2048, 512, 128, 32, 8], precision="mixed", rtol=1e-10),
+    # the paper's own law (Sec. 5): xi ~ U(-4, 4), lam = exp(-pi (j+k+l) 0.15),
+    # permuted axes, 125 terms, target prod sin(2 pi x_d), strong risk
+    # aversion theta = 72, initial batch 128/16/2 on 17^3/33^3/65^3, u_0 = 0
+    "paper_law_65": Workload(
+        name="MLMC gradient, Sec. 5 law (U(-4,4), exp(-pi(j+k+l)0.15), K=5), levels "
+             "17^3..65^3, M=128/16/2, theta=72",
+        grid_n=grids(17, 3), M=[128, 16, 2], K=5, theta=72.0, law=1, rho=0.15,
+        target_freq=2, u_kind="zero"),
     "adaptive_257": Workload(
         name="adaptive MLSGD, levels 9^3..257^3, K=5, alpha=1e-4, f=1",
         grid_n=grids(9, 6), M=[8192, 2048, 512, 128, 32, 8], K=5, alpha=1e-4,

@@ -472,3 +472,45 @@ def test_truncation_flag(orc):
     g, st = orc.mlmc_gradient(pb, None, u, yd, M)
     EY = st["EY_shifted"] * math.exp(5.0 * st["s"])
     assert (EY < 1.0) == bool(st["truncated"])
+
+
+# ----------------------------------------------------------------------------
+# Exponential KL law of Sec. 5 (xi ~ U(-4, 4), lam_jkl = exp(-pi (j+k+l) rho),
+# phi_jkl = cos(j pi x2) cos(k pi x3) cos(l pi x1))
+# ----------------------------------------------------------------------------
+def test_exponential_law_draws_are_uniforms(orc):
+    """xi = -4 + 8 u from the same 53-bit uniforms as the normals, against
+    numpy's independent Philox; moments and KS against U(-4, 4)."""
+    import scipy.stats as sst
+    K = 5
+    for (seed, level, sample) in [(0, 0, 0), (7, 3, 12345)]:
+        xi = orc.draws(seed, level, sample, K, law=orc.LAW_EXPONENTIAL)
+        words = np.concatenate([_numpy_block(seed, [b, sample, level, 0]) for b in range(32)])
+        u = ((words[:K ** 3] >> np.uint64(11)).astype(np.float64) + 0.5) * 2.0 ** -53
+        assert np.array_equal(xi, -4.0 + 8.0 * u)
+    allx = np.concatenate([orc.draws(0, 2, m, K, law=orc.LAW_EXPONENTIAL) for m in range(200)])
+    assert abs(allx.mean()) < 0.1 and abs(allx.var() - 16.0 / 3.0) < 0.2
+    assert sst.kstest(allx, "uniform", args=(-4.0, 8.0)).pvalue > 1e-3
+
+
+@pytest.mark.parametrize("rho,sigma2", [(0.15, 1.0), (0.4, 2.0)])
+def test_exponential_law_field_is_the_sec5_sum(orc, rho, sigma2):
+    """log a at every vertex equals sum_{j,k,l} sqrt(sigma2 lam_jkl) xi_jkl
+    cos(j pi y) cos(k pi z) cos(l pi x), written out with the draws taken in
+    the order j, k, l (l fastest)."""
+    K, n = 5, 9
+    xi = orc.draws(3, 1, 4, K, law=orc.LAW_EXPONENTIAL)
+    c = orc.kl_coeffs(3, 1, 4, K, sigma2, law=orc.LAW_EXPONENTIAL, rho=rho)
+    field = orc.log_coeff(n, c)
+    x = np.linspace(0.0, 1.0, n)
+    X, Y, Z = np.meshgrid(x, x, x, indexing="ij")
+    ref = np.zeros((n, n, n))
+    t = 0
+    for j in range(1, K + 1):
+        for k in range(1, K + 1):
+            for l in range(1, K + 1):
+                lam = math.exp(-math.pi * (j + k + l) * rho)
+                ref += (math.sqrt(sigma2 * lam) * xi[t] * np.cos(j * math.pi * Y)
+                        * np.cos(k * math.pi * Z) * np.cos(l * math.pi * X))
+                t += 1
+    assert np.max(np.abs(field - ref)) <= 1e-13 * max(1.0, np.max(np.abs(ref)))
