@@ -1871,9 +1871,12 @@ void level_dx_mean(int nf, int M, const double* part, double* mean, hipStream_t 
                      level_sample_blocks(M), M, part, mean);
 }
 
+// points per workgroup of the M2 reduction (two per thread: enough
+// workgroups to fill the chip on the finest level, whose sample count is small)
+constexpr int M2_CHUNK = 256 * 2;
 int level_m2_chunks(int nf) {
   const long long N = (long long)nf * nf * nf;
-  return cdiv(N, 256 * 16);
+  return cdiv(N, M2_CHUNK);
 }
 __global__ void __launch_bounds__(256)
     k_level_dx_m2(int nf, int M, const double* __restrict__ pf, const double* __restrict__ wf,
@@ -1882,7 +1885,7 @@ __global__ void __launch_bounds__(256)
   __shared__ double sred[4];
   const long long N = (long long)nf * nf * nf;
   const int chunk = blockIdx.x, sb = blockIdx.y;
-  const long long lo = (long long)chunk * 256 * 16, hi = min(N, lo + 256 * 16);
+  const long long lo = (long long)chunk * M2_CHUNK, hi = min(N, lo + M2_CHUNK);
   const int m1 = min(M, (sb + 1) * SB);
   double acc = 0.0;
   for (long long v = lo + threadIdx.x; v < hi; v += 256) {
