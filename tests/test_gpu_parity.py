@@ -315,3 +315,43 @@ def test_full_size_estimate_matches_oracle(mm, orc, workload, bar):
     assert err <= bar
     assert st["J"] == pytest.approx(so["J"], rel=1e-10)
     assert st["EY_shifted"] == pytest.approx(so["EY_shifted"], rel=1e-10)
+
+
+def test_full_size_257_sampled(mm, orc):
+    """The 9^3..257^3 workload (M = 8192/.../8, mixed, rtol 1e-10) at full
+    size in the benchmark's launch configuration: every solve converges, the
+    gradient is finite, the objective stays below the entropic upper bound
+    s + alpha/2 |u|^2 (s the largest misfit of the estimate), and one 257^3
+    state and adjoint solve of the same draw equals the oracle's to 1e-8 (the
+    rtol 1e-10 of this workload; the oracle solves to 1e-11)."""
+    import torch
+    import bench
+    w = inputs.WORKLOADS["mlmc_257_batched"]
+    print("full size 257", flush=True)
+    dev = torch.device("cuda:0")
+    ctx = bench.make_ctx(mm, w, dev)
+    u = w.u0()
+    g, st = ctx.mlmc_gradient(u, w.M)
+    assert st["nonconverged"] == 0 and st["max_relres"] <= w.rtol
+    assert np.all(np.isfinite(g.cpu().numpy()))
+    h = 1.0 / (w.grid_n[-1] - 1)
+    unorm2 = h ** 3 * float(np.sum(u[1:-1, 1:-1, 1:-1] ** 2))
+    assert st["J"] <= st["s"] + 0.5 * w.alpha * unorm2 + 1e-12
+    y, p, phi, sst = ctx.solve_state_adjoint(5, 0, 3, 1, u)
+    ctx.close()
+    n = w.grid_n[-1]
+    c = orc.kl_coeffs(w.seed, 5, 3, w.K, w.sigma2)
+    b = u.copy()
+    b[0] = b[-1] = 0
+    b[:, 0] = b[:, -1] = 0
+    b[:, :, 0] = b[:, :, -1] = 0
+    yo, _, rr = orc.solve(n, c, b, method=orc.SOLVE_MGPCG, rtol=1e-11)
+    assert _rel(y[0].cpu().numpy(), yo) <= 1e-8
+    yd = w.y_d()
+    r = yo - yd
+    r[0] = r[-1] = 0
+    r[:, 0] = r[:, -1] = 0
+    r[:, :, 0] = r[:, :, -1] = 0
+    po, _, _ = orc.solve(n, c, r, method=orc.SOLVE_MGPCG, rtol=1e-11)
+    assert _rel(p[0].cpu().numpy(), po) <= 1e-8
+    assert float(phi[0]) == pytest.approx(orc.misfit(n, yo, yd), rel=1e-7)
