@@ -49,6 +49,7 @@ struct GridArgs {
   double ih2;           // 1/h^2
   const void* cache;    // [problem][n^3] cached 1/a of the compute type, or null
   int cache_bf16;       // FP32 sweeps: the cache holds bfloat16 values
+  double omega1;        // first step of the fused two-step Jacobi sweep
 };
 
 // ---- stencil kernels (marching LDS tiles, coefficient regenerated) ----
@@ -73,6 +74,14 @@ void rb_sweep(const GridArgs& g, const T* xin, const T* xc, const T* b, T* xout,
               double omega, hipStream_t s);
 void coef_cache(int n, int rows, const double* coef, int K, const double* cosT, double* out64,
                 float* out32, uint16_t* out16, hipStream_t s);
+// reciprocal diagonal 1 / (h^-2 sum_f a_f) of every row from the cached 1/a
+template <typename T>
+void dinv_rows(int n, int rows, const void* cache, int cache_bf16, T* dinv, hipStream_t s);
+// two Jacobi steps from x = 0 in one pass: x2 = J(omega2) J(omega1) 0 (the
+// first step x1 = omega1 b / D is formed on the fly from b and 1/D)
+template <typename T>
+void march_jac2z(const GridArgs& g, const T* dinv, const T* b, T* xout, double omega1,
+                 double omega2, hipStream_t s);
 
 // ---- batched grid transfers (rows of one grid size) ----
 template <typename T>

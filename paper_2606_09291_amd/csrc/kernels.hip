@@ -122,6 +122,9 @@ Tiling make_tiling(int n, int tile_y, int xchunk) {
 //            (the steps of the Chebyshev smoother; x_zero: x = 0; partial:
 //            <b, x'>); OP_JACP also adds the trilinear prolongation of the
 //            coarse rows in2 to every loaded x (coarse-grid correction)
+// OP_JAC2Z : the first two steps from x = 0 in one pass: every loaded x is the
+//            first step's value omega1 b / D, formed from b (rhs) and the
+//            stored reciprocal diagonal (in), then one Jacobi step follows
 // ---------------------------------------------------------------------------
 template <typename T>
 __device__ __forceinline__ T prolong_val(int nc, const T* __restrict__ c, int ix, int iy, int iz) {
@@ -192,7 +195,7 @@ struct Ld {
   T c;
 };
 
-enum MarchOp { OP_RESID = 0, OP_MATVEC = 1, OP_GS = 2, OP_JAC = 3, OP_JACP = 4 };
+enum MarchOp { OP_RESID = 0, OP_MATVEC = 1, OP_GS = 2, OP_JAC = 3, OP_JACP = 4, OP_JAC2Z = 5 };
 
 template <typename T, typename TI, int TY, int TZ, int OP, int CK>
 __global__ void __launch_bounds__(TY* TZ)
@@ -258,6 +261,7 @@ __global__ void __launch_bounds__(TY* TZ)
 
   T beta = T(0);
   if (OP == OP_MATVEC) beta = (T)g.scal[prob].beta;
+  const T omega1 = (T)g.omega1;
 
   const int x0 = 1 + xc * g.t.xchunk;
   const int x1 = min(x0 + g.t.xchunk, n - 1);
@@ -271,11 +275,13 @@ __global__ void __launch_bounds__(TY* TZ)
     const size_t idx = base + ((size_t)ix * n + jy) * n + jz;
     v.r = in[idx];
     if (OP == OP_MATVEC) v.c = in2[idx];
+    if (OP == OP_JAC2Z) v.c = rhs[idx];
     return v;
   };
   auto full = [&](const LdT& v) -> T {
     if (OP == OP_MATVEC) return (T)v.r + beta * v.c;
     if (OP == OP_JACP) return (T)v.r + v.c;
+    if (OP == OP_JAC2Z) return (omega1 * v.c) * (T)v.r;
     return (T)v.r;
   };
 
@@ -422,7 +428,8 @@ __global__ void __launch_bounds__(TY* TZ)
   }
   T xm = full(xmr), xcur = full(xcr), hcur = full(hcr);
   T fxm = face(bm, bc);
-  constexpr bool USES_B = (OP == OP_RESID || OP == OP_GS || OP == OP_JAC || OP == OP_JACP);
+  constexpr bool USES_B =
+      (OP == OP_RESID || OP == OP_GS || OP == OP_JAC || OP == OP_JACP || OP == OP_JAC2Z);
   T bv = T(0);
   if (USES_B && own) bv = rhs[base + ((size_t)x0 * n + iy) * n + iz];
   double dot = 0.0;
@@ -480,7 +487,7 @@ __global__ void __launch_bounds__(TY* TZ)
         __builtin_nontemporal_store(q, &out[idx]);
         __builtin_nontemporal_store(xcur, &out2[idx]);
         dot += (double)xcur * (double)q;
-      } else if (OP == OP_JAC || OP == OP_JACP) {
+      } else if (OP == OP_JAC || OP == OP_JACP || OP == OP_JAC2Z) {
         const T val = xcur + omega * (bv - ih2 * (diag * xcur - off)) * drcp(ih2 * diag);
         __builtin_nontemporal_store(val, &out[idx]);
         if (partial) dot += (double)bv * (double)val;
@@ -604,6 +611,69 @@ template void march_jac<double>(const GridArgs&, const double*, const double*, c
                                 double*, int, double, const int*, double*, int, hipStream_t);
 template void march_jac<float>(const GridArgs&, const float*, const float*, const float*, float*,
                                int, double, const int*, double*, int, hipStream_t);
+
+static int grid_for(long long total, int bs);
+
+template <typename T>
+void march_jac2z(const GridArgs& g, const T* dinv, const T* b, T* xout, double omega1,
+                 double omega2, hipStream_t s) {
+  GridArgs g2 = g;
+  g2.omega1 = omega1;
+  launch_march<T, T, OP_JAC2Z>(g2, dinv, nullptr, b, xout, nullptr, nullptr, nullptr, 0, 0, 0,
+                               (T)omega2, s);
+}
+template void march_jac2z<double>(const GridArgs&, const double*, const double*, double*, double,
+                                  double, hipStream_t);
+template void march_jac2z<float>(const GridArgs&, const float*, const float*, float*, double,
+                                 double, hipStream_t);
+
+// Reciprocal diagonal drcp(h^-2 ((fxm + fxp) + (fym + fyp)) + (fzm + fzp)) of
+// every interior vertex, with the faces and the summation order of k_march,
+// so the first smoothing step formed from it equals the one k_march forms.
+template <typename T, int CK>
+__global__ void k_dinv(int n, long long total, const void* __restrict__ cache, T ih2,
+                       T* __restrict__ dinv) {
+  const long long per = (long long)n * n * n;
+  const T* c = (const T*)cache;
+  const uint16_t* c16 = (const uint16_t*)cache;
+  auto bval = [&](long long e) -> T {
+    if constexpr (CK == 2)
+      return (T)from_bf16(c16[e]);
+    else
+      return c[e];
+  };
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long v = e % per;
+    const int ix = (int)(v / ((long long)n * n)), iy = (int)((v / n) % n), iz = (int)(v % n);
+    if (ix < 1 || iy < 1 || iz < 1 || ix > n - 2 || iy > n - 2 || iz > n - 2) {
+      dinv[e] = T(0);
+      continue;
+    }
+    const long long sx = (long long)n * n, sy = n;
+    const T bc = bval(e);
+    const T fxm = face(bval(e - sx), bc), fxp = face(bc, bval(e + sx));
+    const T fym = face(bc, bval(e - sy)), fyp = face(bc, bval(e + sy));
+    const T fzm = face(bc, bval(e - 1)), fzp = face(bc, bval(e + 1));
+    const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
+    dinv[e] = drcp(ih2 * diag);
+  }
+}
+
+template <typename T>
+void dinv_rows(int n, int rows, const void* cache, int cache_bf16, T* dinv, hipStream_t s) {
+  const long long total = (long long)rows * n * n * n;
+  if (total <= 0 || !cache || !dinv) return;
+  const T ih2 = (T)((double)(n - 1) * (double)(n - 1));
+  if (cache_bf16)
+    hipLaunchKernelGGL((k_dinv<T, 2>), dim3(grid_for(total, 256)), dim3(256), 0, s, n, total,
+                       cache, ih2, dinv);
+  else
+    hipLaunchKernelGGL((k_dinv<T, 1>), dim3(grid_for(total, 256)), dim3(256), 0, s, n, total,
+                       cache, ih2, dinv);
+}
+template void dinv_rows<double>(int, int, const void*, int, double*, hipStream_t);
+template void dinv_rows<float>(int, int, const void*, int, float*, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Fused red-black Gauss-Seidel sweep (both colours in one pass, out of place).

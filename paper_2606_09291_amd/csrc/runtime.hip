@@ -63,6 +63,8 @@ struct SizeLvl {
   float *Xf = nullptr, *Bf = nullptr, *Rf = nullptr;  // FP32 multigrid rows (mixed precision)
   float* Cf = nullptr;                              // FP32 cache of 1/a (null: regenerate)
   uint16_t* Cb = nullptr;                           // bfloat16 cache of 1/a (BF16 smoothing)
+  double* Di = nullptr;                             // FP64 reciprocal diagonal (with C)
+  float* Dif = nullptr;                             // FP32 reciprocal diagonal (with Cf / Cb)
   const double* cosT = nullptr;
   int cur = 0;   // fused sweeps: which of X/R (Xf/Rf) holds the current iterate
 };
@@ -316,8 +318,10 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks, bool fields = tru
           s.Rf = cv.take<float>(e);
           if (c->cache32 && c->bf16) s.Cb = cv.take<uint16_t>(e);
           else if (c->cache32) s.Cf = cv.take<float>(e);
+          if (c->cache32) s.Dif = cv.take<float>(e);
         }
         if (c->cache64) s.C = cv.take<double>(e);
+        if (c->cache64 && !c->mixed) s.Di = cv.take<double>(e);
       }
       for (auto& g : P->groups) {
         const size_t e = (size_t)g.count * cube(g.n);
@@ -373,8 +377,13 @@ void plan_fields(mlsgd_ctx* c, Plan* P) {
             c->pb.kl_rho, P->d_coef, c->stream);
   // the coefficient is regenerated from the draws once per call for the
   // cached sweeps (the Krylov matvec and residual always run in FP64)
-  for (auto& sl : P->sizes)
+  for (auto& sl : P->sizes) {
     coef_cache(sl.n, sl.rows, P->d_coef, K, sl.cosT, sl.C, sl.Cf, sl.Cb, c->stream);
+    if (sl.Di) dinv_rows<double>(sl.n, sl.rows, sl.C, 0, sl.Di, c->stream);
+    if (sl.Dif)
+      dinv_rows<float>(sl.n, sl.rows, sl.Cb ? (const void*)sl.Cb : (const void*)sl.Cf,
+                       sl.Cb ? 1 : 0, sl.Dif, c->stream);
+  }
   if (P->dense_N) {
     const SizeLvl& co = P->sizes.back();
     dense_coarse_inv(co.n, co.rows, P->d_coef, K, co.cosT, P->ainv, c->stream);
@@ -396,6 +405,7 @@ GridArgs args_size(mlsgd_ctx* c, Plan* P, const SizeLvl& s) {
   g.ih2 = (double)(s.n - 1) * (double)(s.n - 1);
   g.cache = s.C;
   g.cache_bf16 = 0;
+  g.omega1 = 0.0;
   return g;
 }
 
@@ -575,6 +585,15 @@ double jac_bytes(int n, int rows, bool x_zero, bool prolong, const GridArgs& g) 
 // post-smoothing whose first step folds in the prolonged coarse correction
 // and whose last step forms <r, z> for the problems whose top grid it is.
 // The single unknown of the 3^3 grid is solved exactly by one Jacobi step.
+// reciprocal diagonal of a grid size in the V-cycle's precision (null when
+// the coefficient is regenerated in the sweeps)
+template <typename T>
+const T* dinv_of(const SizeLvl& L);
+template <>
+const double* dinv_of<double>(const SizeLvl& L) { return L.Di; }
+template <>
+const float* dinv_of<float>(const SizeLvl& L) { return L.Dif; }
+
 template <typename T>
 void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
   const int S = (int)P->sizes.size();
@@ -601,10 +620,19 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
       break;
     }
     int cur = 0;
-    timed_launch(c, g, jac_bytes<T>(L.n, L.rows, true, false, g), [&] {
-      march_jac<T>(g, nullptr, nullptr, v.B, A[0], 1, om[0], nullptr, nullptr, 0, c->stream);
-    });
-    for (int j = 1; j < deg; ++j) {
+    int j0 = 1;
+    const T* dinv = dinv_of<T>(L);
+    if (deg >= 2 && dinv) {
+      // steps 0 and 1 in one pass from the stored reciprocal diagonal
+      march_jac2z<T>(g, dinv, v.B, A[1], om[0], om[1], c->stream);
+      cur = 1;
+      j0 = 2;
+    } else {
+      timed_launch(c, g, jac_bytes<T>(L.n, L.rows, true, false, g), [&] {
+        march_jac<T>(g, nullptr, nullptr, v.B, A[0], 1, om[0], nullptr, nullptr, 0, c->stream);
+      });
+    }
+    for (int j = j0; j < deg; ++j) {
       timed_launch(c, g, jac_bytes<T>(L.n, L.rows, false, false, g), [&] {
         march_jac<T>(g, A[cur], nullptr, v.B, A[cur ^ 1], 0, om[j], nullptr, nullptr, 0,
                      c->stream);
