@@ -1,4 +1,4 @@
-"""MLSGD driver (Algorithm 1, function MLSGD): projected SGD steps through
+"""MLSGD outer loop (Algorithm 1, function MLSGD): projected SGD steps through
 mlsgd_step with the adaptive batch controller (Sec. 4.1) and the adaptive step
 size (Sec. 5), until the norm of the latest gradient estimate is at most
 eps_tilde, the step limit is reached, or the wall-clock budget is spent (the

@@ -1,4 +1,4 @@
-"""Adaptive step size (mlsgd_step with ADAPT_STEP) and the MLSGD driver.
+"""Adaptive step size (mlsgd_step with ADAPT_STEP) and the MLSGD outer loop.
 
 sigma = 0 pins the step exactly: every sample then gives the same field
 (a = 1), the MLMC estimate is the exact finest-grid gradient, and along
@@ -92,7 +92,7 @@ def test_adaptive_step_matches_oracle_formula(mm, orc):
     ctx.close()
 
 
-def test_driver_stops(mm):
+def test_mlsgd_loop_stops(mm):
     import torch
     from paper_2606_09291_amd import mlsgd
     grid, M = [9, 17], [8, 4]
