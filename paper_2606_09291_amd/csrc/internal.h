@@ -12,6 +12,21 @@ namespace mlsgd {
 constexpr int KMAX = 5;
 constexpr int RED_BLOCKS = 256;   // fixed block count of the deterministic dot kernels
 
+// Row layout of the batched solver fields (right-hand sides, iterates,
+// coefficient caches, reciprocal diagonals) on a grid with n vertices per
+// axis: vertex (x, y, z) of a row sits at (x n + y) lay_pitch(n) + lay_off(n)
+// + z, and a row holds lay_row(n) elements.  From 129 vertices on, every z
+// line is padded so that its first interior vertex starts a 128-byte line and
+// the pitch is a whole number of 128-byte lines in FP64; the padding holds
+// zeros.  Smaller grids are stored densely.  Fields that callers and the
+// epilogue see (controls, targets, level sums, gradients) are always dense
+// [n][n][n].
+__host__ __device__ __forceinline__ int lay_off(int n) { return n >= 129 ? 15 : 0; }
+__host__ __device__ __forceinline__ int lay_pitch(int n) { return n >= 129 ? (n + 30) & ~15 : n; }
+__host__ __device__ __forceinline__ long long lay_row(int n) {
+  return (long long)n * n * lay_pitch(n);
+}
+
 // Tiling of one grid size for the marching stencil kernels: a workgroup owns
 // a TY x TZ patch of the (y, z) plane and marches along x over xchunk planes.
 struct Tiling {
@@ -40,7 +55,7 @@ struct GridArgs {
   int n;                // vertices per axis
   int rows;             // rows (problems) in the launch, rows [0, rows)
   int row0;             // problem index of row 0
-  long long stride;     // elements per row (n^3)
+  long long stride;     // elements per row, lay_row(n)
   Tiling t;
   const double* coef;   // [problem][K^3] KL coefficients sqrt(sigma2 lam) xi
   int K;
@@ -97,6 +112,7 @@ void dense_coarse_inv(int n, int rows, const double* coef, int K, const double* 
 template <typename T>
 void dense_apply(int n, int rows, const CgScal* scal, const double* ainv, const T* b, T* x,
                  hipStream_t s);
+// solver rows [count] to dense rows at per-row destination offsets
 void scatter_rows(int n, int count, const long long* dst_off, const double* src, double* dst,
                   hipStream_t s);
 void fill_interior(int n, double v, double* out, hipStream_t s);
@@ -111,8 +127,12 @@ void philox_words(uint64_t seed, int level, int64_t sample, int tag, int nblocks
                   uint64_t* out, hipStream_t s);
 void cos_table(int n, int K, double* out, hipStream_t s);
 
-// ---- elementwise over the rows of one group (full n^3 per row) ----
+// ---- elementwise over the rows of one group (lay_row(n) per row) ----
+// one dense field copied into every solver row
 void rows_broadcast(int n, int rows, const double* src, double* dst, hipStream_t s);
+// solver rows copied (copy_rows) or converted to dense rows (unpack_rows)
+void copy_rows(int n, int rows, const double* src, double* dst, hipStream_t s);
+void unpack_rows(int n, int rows, const double* src, double* dst, hipStream_t s);
 void rows_zero(long long count, double* x, hipStream_t s);
 void to_f32(long long count, const double* x, float* y, hipStream_t s);
 void group_dot(const GridArgs& g, const double* a, const double* b, const int* poff,
@@ -120,6 +140,7 @@ void group_dot(const GridArgs& g, const double* a, const double* b, const int* p
 void group_update(const GridArgs& g, double* x, const double* p, double* r,
                   const double* q, const int* poff, double* partial, float* r32,
                   hipStream_t s);
+// b = y - y_d on the interior (y_d dense), y reset to 0, partials of |b|^2
 void group_misfit(const GridArgs& g, double* y, const double* yd, double* b_rows,
                   const int* poff, double* partial, hipStream_t s);
 
@@ -153,12 +174,13 @@ void dot_blocks(long long N, const double* a, const double* b, double* part,
 void box_step(int n, double* u, const double* g, double tau, double lo, double hi,
               int use_box, hipStream_t s);
 void nonfinite_flag(long long count, const double* x, int* flag, hipStream_t s);
-void copy_rows_strided(int n, int rows, const double* src, double* dst, hipStream_t s);
+void copy_elems(long long count, const double* src, double* dst, hipStream_t s);
 
 // ---- entropic epilogue ----
 void shift_weights(int nprob, const double* phi, double theta, double* w, double* s_out,
                    hipStream_t s);
 int level_sample_blocks(int M);
+// pf, pc: solver rows of the level's fine and coarse solves; part, mean dense
 void level_dx_partial(int nf, int M, const double* pf, const double* wf, const double* pc,
                       const double* wc, double* part, hipStream_t s);
 void level_dx_mean(int nf, int M, const double* part, double* mean, hipStream_t s);

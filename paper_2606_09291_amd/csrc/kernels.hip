@@ -131,7 +131,8 @@ __device__ __forceinline__ T prolong_val(int nc, const T* __restrict__ c, int ix
   const int ax = ix >> 1, bx = (ix + 1) >> 1;
   const int ay = iy >> 1, by = (iy + 1) >> 1;
   const int az = iz >> 1, bz = (iz + 1) >> 1;
-  auto cv = [&](int a, int b, int d) { return c[((size_t)a * nc + b) * nc + d]; };
+  const int cp = lay_pitch(nc), co = lay_off(nc);
+  auto cv = [&](int a, int b, int d) { return c[((size_t)a * nc + b) * cp + d + co]; };
   T v = cv(ax, ay, az);
   if (iz & 1) v += cv(ax, ay, bz);
   if (iy & 1) {
@@ -212,6 +213,7 @@ __global__ void __launch_bounds__(TY* TZ)
   __shared__ double sred[NT / 64];
 
   const int n = g.n;
+  const int LP = lay_pitch(n), LO = lay_off(n);
   const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
   const int tpr = g.t.tiles_per_row;
   const int row = bid / tpr;
@@ -272,7 +274,7 @@ __global__ void __launch_bounds__(TY* TZ)
   auto ldr = [&](int ix, int jy, int jz) -> LdT {
     LdT v{TI(0), T(0)};
     if (x_zero || !interior(ix, jy, jz)) return v;
-    const size_t idx = base + ((size_t)ix * n + jy) * n + jz;
+    const size_t idx = base + ((size_t)ix * n + jy) * LP + jz + LO;
     v.r = in[idx];
     if (OP == OP_MATVEC) v.c = in2[idx];
     if (OP == OP_JAC2Z) v.c = rhs[idx];
@@ -294,17 +296,18 @@ __global__ void __launch_bounds__(TY* TZ)
   static_assert(CSLAB <= NT, "coarse slab larger than the workgroup");
   __shared__ T scs[OP == OP_JACP ? 4 * CSLAB : 1];
   const int nc = (n - 1) / 2 + 1;
-  const T* crow = in2 + (size_t)row * ((size_t)nc * nc * nc);
+  const int cLP = lay_pitch(nc), cLO = lay_off(nc);
+  const T* crow = in2 + (size_t)row * (size_t)lay_row(nc);
   const int cy0 = (y0 - 1) >> 1, cz0 = (z0 - 1) >> 1;
   bool cld = false;
   size_t coff = 0;
   if (OP == OP_JACP && tid < CSLAB) {
     const int gy = cy0 + tid / CZN, gz = cz0 + tid % CZN;
     cld = gy <= nc - 1 && gz <= nc - 1;
-    coff = (size_t)gy * nc + gz;
+    coff = (size_t)gy * cLP + gz + cLO;
   }
   auto cload = [&](int J) -> T {
-    return (cld && J <= nc - 1) ? crow[(size_t)J * nc * nc + coff] : T(0);
+    return (cld && J <= nc - 1) ? crow[(size_t)J * nc * cLP + coff] : T(0);
   };
   auto cstore = [&](int J, T v) {
     if (tid < CSLAB) scs[(J & 3) * CSLAB + tid] = v;
@@ -344,9 +347,9 @@ __global__ void __launch_bounds__(TY* TZ)
   const CR one = CK == 2 ? CR(0x3F80) : CR(1);
   auto coefr = [&](int ix, int jy, int jz, const T* S) -> CR {
     if constexpr (CK == 1) {
-      return cache[((size_t)ix * n + jy) * n + jz];
+      return cache[((size_t)ix * n + jy) * LP + jz + LO];
     } else if constexpr (CK == 2) {
-      return cache16[((size_t)ix * n + jy) * n + jz];
+      return cache16[((size_t)ix * n + jy) * LP + jz + LO];
     } else {
       T l = T(0);
 #pragma unroll
@@ -431,7 +434,7 @@ __global__ void __launch_bounds__(TY* TZ)
   constexpr bool USES_B =
       (OP == OP_RESID || OP == OP_GS || OP == OP_JAC || OP == OP_JACP || OP == OP_JAC2Z);
   T bv = T(0);
-  if (USES_B && own) bv = rhs[base + ((size_t)x0 * n + iy) * n + iz];
+  if (USES_B && own) bv = rhs[base + ((size_t)x0 * n + iy) * LP + iz + LO];
   double dot = 0.0;
   const int cidx = (ly + 1) * PZ + (lz + 1);
   const int hidx = hly * PZ + hlz;
@@ -452,7 +455,7 @@ __global__ void __launch_bounds__(TY* TZ)
       hnn = ldr(ix + 2, hy, hz);
       hbnn = coefr(ix + 2, hy, hz, Sh);
     }
-    if (USES_B && own && ix + 1 < x1) bvn = __builtin_nontemporal_load(&rhs[base + ((size_t)(ix + 1) * n + iy) * n + iz]);
+    if (USES_B && own && ix + 1 < x1) bvn = __builtin_nontemporal_load(&rhs[base + ((size_t)(ix + 1) * n + iy) * LP + iz + LO]);
     if (OP == OP_JACP && ((ix + 3) >> 1) > chi) {
       ++chi;
       cstore(chi, cnext);
@@ -479,7 +482,7 @@ __global__ void __launch_bounds__(TY* TZ)
       const T fzm = face(bc, sb[buf][cidx - 1]), fzp = face(bc, sb[buf][cidx + 1]);
       const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
       const T off = ((fxm * xm + fxp * xp) + (fym * xym + fyp * xyp)) + (fzm * xzm + fzp * xzp);
-      const size_t idx = base + ((size_t)ix * n + iy) * n + iz;
+      const size_t idx = base + ((size_t)ix * n + iy) * LP + iz + LO;
       if (OP == OP_RESID) {
         __builtin_nontemporal_store(bv - ih2 * (diag * xcur - off), &out[idx]);
       } else if (OP == OP_MATVEC) {
@@ -633,7 +636,8 @@ template void march_jac2z<float>(const GridArgs&, const float*, const float*, fl
 template <typename T, int CK>
 __global__ void k_dinv(int n, long long total, const void* __restrict__ cache, T ih2,
                        T* __restrict__ dinv) {
-  const long long per = (long long)n * n * n;
+  const long long per = lay_row(n);
+  const int LP = lay_pitch(n), LO = lay_off(n);
   const T* c = (const T*)cache;
   const uint16_t* c16 = (const uint16_t*)cache;
   auto bval = [&](long long e) -> T {
@@ -645,12 +649,13 @@ __global__ void k_dinv(int n, long long total, const void* __restrict__ cache, T
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
     const long long v = e % per;
-    const int ix = (int)(v / ((long long)n * n)), iy = (int)((v / n) % n), iz = (int)(v % n);
+    const int ix = (int)(v / ((long long)n * LP)), iy = (int)((v / LP) % n),
+              iz = (int)(v % LP) - LO;
     if (ix < 1 || iy < 1 || iz < 1 || ix > n - 2 || iy > n - 2 || iz > n - 2) {
       dinv[e] = T(0);
       continue;
     }
-    const long long sx = (long long)n * n, sy = n;
+    const long long sx = (long long)n * LP, sy = LP;
     const T bc = bval(e);
     const T fxm = face(bval(e - sx), bc), fxp = face(bc, bval(e + sx));
     const T fym = face(bc, bval(e - sy)), fyp = face(bc, bval(e + sy));
@@ -662,7 +667,7 @@ __global__ void k_dinv(int n, long long total, const void* __restrict__ cache, T
 
 template <typename T>
 void dinv_rows(int n, int rows, const void* cache, int cache_bf16, T* dinv, hipStream_t s) {
-  const long long total = (long long)rows * n * n * n;
+  const long long total = (long long)rows * lay_row(n);
   if (total <= 0 || !cache || !dinv) return;
   const T ih2 = (T)((double)(n - 1) * (double)(n - 1));
   if (cache_bf16)
@@ -707,7 +712,8 @@ __global__ void __launch_bounds__(TY* TZ)
   __shared__ double sred[NT / 64];
 
   const int n = g.n;
-  const int nn = n * n;
+  const int LP = lay_pitch(n), LO = lay_off(n);
+  const int nn = n * LP;
   const int nc = (n - 1) / 2 + 1;
   const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
   const int tpr = g.t.tiles_per_row;
@@ -726,7 +732,7 @@ __global__ void __launch_bounds__(TY* TZ)
   const T* __restrict__ br = rhs + (size_t)row * stride;
   T* __restrict__ outr = xout + (size_t)row * stride;
   const T* __restrict__ cache = (const T*)g.cache + (size_t)prob * stride;
-  const T* __restrict__ xcr = PROLONG ? xc + (size_t)row * ((size_t)nc * nc * nc) : nullptr;
+  const T* __restrict__ xcr = PROLONG ? xc + (size_t)row * (size_t)lay_row(nc) : nullptr;
   const int tid = threadIdx.x;
   const int y0 = 1 + ty * TY, z0 = 1 + tz * TZ;
   const int c1 = first_color ^ 1;
@@ -774,7 +780,7 @@ __global__ void __launch_bounds__(TY* TZ)
   const bool ring_upd = ring_on && !ring_corner && ry >= 1 && rz >= 1 && ry <= n - 2 && rz <= n - 2;
   const bool r2_on = tid < NR2 && qy >= 0 && qz >= 0 && qy <= n - 1 && qz <= n - 1;
   const bool r2_int = r2_on && qy >= 1 && qz >= 1 && qy <= n - 2 && qz <= n - 2;
-  const int ocol = oy * n + oz, rcol = ry * n + rz, qcol = qy * n + qz;
+  const int ocol = oy * LP + oz + LO, rcol = ry * LP + rz + LO, qcol = qy * LP + qz + LO;
   const int opar = (oy + oz) & 1, rpar = (ry + rz) & 1;
 
   // previous iterate (+ prolonged coarse correction) on plane ix of a column
@@ -969,14 +975,15 @@ __global__ void __launch_bounds__(256)
     }
     S[k1] = acc;
   }
-  const size_t base = (size_t)row * ((size_t)n * n * n) + col;
+  const int LP = lay_pitch(n);
+  const size_t base = (size_t)row * (size_t)lay_row(n) + (size_t)iy * LP + iz + lay_off(n);
   for (int ix = 0; ix < n; ++ix) {
     double l = 0.0;
 #pragma unroll
     for (int k = 0; k < KMAX; ++k)
       if (k < K) l += cosT[k * n + ix] * S[k];
     const double b = exp(-l);
-    const size_t i = base + (size_t)ix * cols;
+    const size_t i = base + (size_t)ix * n * LP;
     if (out64) out64[i] = b;
     if (out32) out32[i] = (float)b;
     if (out16) out16[i] = to_bf16((float)b);
@@ -994,7 +1001,8 @@ __global__ void k_restrict_rows(int nf, int rows, int row0, const CgScal* scal,
   const int nc = (nf - 1) / 2 + 1, mc = nc - 2;
   const long long per = (long long)mc * mc * mc;
   const long long total = per * rows;
-  const size_t sf = (size_t)nf * nf * nf, scs = (size_t)nc * nc * nc;
+  const size_t sf = (size_t)lay_row(nf), scs = (size_t)lay_row(nc);
+  const int fp = lay_pitch(nf), fo = lay_off(nf), cp = lay_pitch(nc), co = lay_off(nc);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     const int row = (int)(i / per);
@@ -1010,12 +1018,12 @@ __global__ void k_restrict_rows(int nf, int rows, int row0, const CgScal* scal,
 #pragma unroll
       for (int dy = -1; dy <= 1; ++dy) {
         const T wy = dy == 0 ? T(0.5) : T(0.25);
-        const T* p = f + ((size_t)(2 * jx + dx) * nf + (2 * jy + dy)) * nf + 2 * jz;
+        const T* p = f + ((size_t)(2 * jx + dx) * nf + (2 * jy + dy)) * fp + 2 * jz + fo;
         ay += wy * (T(0.25) * p[-1] + T(0.5) * p[0] + T(0.25) * p[1]);
       }
       acc += wx * ay;
     }
-    coarse[(size_t)row * scs + ((size_t)jx * nc + jy) * nc + jz] = acc;
+    coarse[(size_t)row * scs + ((size_t)jx * nc + jy) * cp + jz + co] = acc;
   }
 }
 
@@ -1025,7 +1033,8 @@ __global__ void k_prolong_add_rows(int nc, int rows, int row0, const CgScal* sca
   const int nf = 2 * (nc - 1) + 1, mf = nf - 2;
   const long long per = (long long)mf * mf * mf;
   const long long total = per * rows;
-  const size_t sf = (size_t)nf * nf * nf, scs = (size_t)nc * nc * nc;
+  const size_t sf = (size_t)lay_row(nf), scs = (size_t)lay_row(nc);
+  const int fp = lay_pitch(nf), fo = lay_off(nf), cp = lay_pitch(nc), co = lay_off(nc);
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     const int row = (int)(i / per);
@@ -1038,7 +1047,7 @@ __global__ void k_prolong_add_rows(int nc, int rows, int row0, const CgScal* sca
     const int az = iz >> 1, bz = (iz + 1) >> 1;
     const T wx = (ix & 1) ? T(0.5) : T(1), wy = (iy & 1) ? T(0.5) : T(1),
             wz = (iz & 1) ? T(0.5) : T(1);
-    auto cv = [&](int a, int b, int d) { return c[((size_t)a * nc + b) * nc + d]; };
+    auto cv = [&](int a, int b, int d) { return c[((size_t)a * nc + b) * cp + d + co]; };
     T v = cv(ax, ay, az);
     if (iz & 1) v += cv(ax, ay, bz);
     if (iy & 1) {
@@ -1053,7 +1062,7 @@ __global__ void k_prolong_add_rows(int nc, int rows, int row0, const CgScal* sca
         if (iz & 1) v += cv(bx, by, bz);
       }
     }
-    fine[(size_t)row * sf + ((size_t)ix * nf + iy) * nf + iz] += wx * wy * wz * v;
+    fine[(size_t)row * sf + ((size_t)ix * nf + iy) * fp + iz + fo] += wx * wy * wz * v;
   }
 }
 
@@ -1192,8 +1201,11 @@ __global__ void __launch_bounds__(256)
   const int prob = blockIdx.x, tid = threadIdx.x;
   if (scal && !scal[prob].active) return;  // uniform per workgroup
   const int m = n - 2, N = m * m * m;
-  const size_t base = (size_t)prob * n * n * n;
-  auto vtx = [&](int i) { return ((1 + i / (m * m)) * n + 1 + (i / m) % m) * n + 1 + i % m; };
+  const size_t base = (size_t)prob * (size_t)lay_row(n);
+  const int lp = lay_pitch(n), lo = lay_off(n);
+  auto vtx = [&](int i) {
+    return ((1 + i / (m * m)) * n + 1 + (i / m) % m) * lp + 1 + i % m + lo;
+  };
   for (int i = tid; i < N; i += 256) sbv[i] = (double)b[base + vtx(i)];
   __syncthreads();
   const double* A = ainv + (size_t)prob * N * N;
@@ -1215,23 +1227,30 @@ template void dense_apply<double>(int, int, const CgScal*, const double*, const 
 template void dense_apply<float>(int, int, const CgScal*, const double*, const float*, float*,
                                  hipStream_t);
 
-// Rows [count][n^3] scattered to per-row destination offsets (packed output
-// of problems of different sizes).
-__global__ void k_scatter_rows(long long per, int count, const long long* __restrict__ dst_off,
-                               const double* __restrict__ src, double* __restrict__ dst) {
-  const long long total = per * count;
+// Solver rows [count] written as dense [n][n][n] rows, row r at dst + dst_off[r]
+// (dst_off null: row r at r n^3).
+__global__ void k_unpack_rows(int n, int count, const long long* __restrict__ dst_off,
+                              const double* __restrict__ src, double* __restrict__ dst) {
+  const long long per = (long long)n * n * n, total = per * count;
+  const long long srow = lay_row(n);
+  const int lp = lay_pitch(n), lo = lay_off(n);
   for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
        e += (long long)gridDim.x * blockDim.x) {
-    const long long r = e / per;
-    dst[dst_off[r] + (e - r * per)] = src[e];
+    const long long r = e / per, v = e - r * per;
+    const long long xy = v / n;
+    const int iz = (int)(v - xy * n);
+    dst[(dst_off ? dst_off[r] : r * per) + v] = src[r * srow + xy * lp + iz + lo];
   }
 }
 void scatter_rows(int n, int count, const long long* dst_off, const double* src, double* dst,
                   hipStream_t s) {
-  const long long per = (long long)n * n * n, total = per * count;
+  const long long total = (long long)n * n * n * count;
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_scatter_rows, dim3(grid_for(total, 256)), dim3(256), 0, s, per, count,
+  hipLaunchKernelGGL(k_unpack_rows, dim3(grid_for(total, 256)), dim3(256), 0, s, n, count,
                      dst_off, src, dst);
+}
+void unpack_rows(int n, int rows, const double* src, double* dst, hipStream_t s) {
+  scatter_rows(n, rows, nullptr, src, dst, s);
 }
 
 // Constant on the interior, zero on the boundary.
@@ -1407,16 +1426,23 @@ void cos_table(int n, int K, double* out, hipStream_t s) {
 // tiles_per_row contiguous chunks, one workgroup each, so partial sums land
 // in fixed slots and every reduction is deterministic.
 // ---------------------------------------------------------------------------
-__global__ void k_rows_broadcast(long long per, long long total, const double* __restrict__ src,
+// dense field src copied into every solver row of dst (padding untouched)
+__global__ void k_rows_broadcast(int n, long long total, const double* __restrict__ src,
                                  double* __restrict__ dst) {
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x)
-    dst[i] = src[i % per];
+  const long long per = (long long)n * n * n, drow = lay_row(n);
+  const int lp = lay_pitch(n), lo = lay_off(n);
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long r = e / per, v = e - r * per;
+    const long long xy = v / n;
+    const int iz = (int)(v - xy * n);
+    dst[r * drow + xy * lp + iz + lo] = src[v];
+  }
 }
 void rows_broadcast(int n, int rows, const double* src, double* dst, hipStream_t s) {
-  const long long per = (long long)n * n * n, total = per * rows;
+  const long long total = (long long)n * n * n * rows;
   if (total <= 0) return;
-  hipLaunchKernelGGL(k_rows_broadcast, dim3(grid_for(total, 256)), dim3(256), 0, s, per, total,
+  hipLaunchKernelGGL(k_rows_broadcast, dim3(grid_for(total, 256)), dim3(256), 0, s, n, total,
                      src, dst);
 }
 __global__ void k_to_f32(long long count, const double* __restrict__ x, float* __restrict__ y) {
@@ -1495,10 +1521,12 @@ __global__ void __launch_bounds__(256)
       acc += r * r;
     }
   } else {  // G_MISFIT: a = y (reset to 0 afterwards), b = y_d (shared), c = adjoint rhs rows
+    const int lp = lay_pitch(n), lo_ = lay_off(n);
     for (long long i = lo + threadIdx.x; i < hi; i += 256) {
-      const int ix = (int)(i / ((long long)n * n)), iy = (int)((i / n) % n), iz = (int)(i % n);
+      const int ix = (int)(i / ((long long)n * lp)), iy = (int)((i / lp) % n),
+                iz = (int)(i % lp) - lo_;
       const bool in = ix > 0 && iy > 0 && iz > 0 && ix < n - 1 && iy < n - 1 && iz < n - 1;
-      const double r = in ? a[base + i] - b[i] : 0.0;
+      const double r = in ? a[base + i] - b[((size_t)ix * n + iy) * n + iz] : 0.0;
       c[base + i] = r;
       a[base + i] = 0.0;
       acc += r * r;
@@ -1725,12 +1753,14 @@ void restrict_full(int nf, const double* fine, double* coarse, hipStream_t s) {
                      s, nf, fine, coarse);
 }
 
-__device__ __forceinline__ double prolong_at(int nc, const double* __restrict__ c, int ix, int iy,
-                                             int iz) {
+// trilinear prolongation at fine vertex (ix, iy, iz) of the coarse field c
+// stored with z pitch cp and offset co
+__device__ __forceinline__ double prolong_at(int nc, int cp, int co, const double* __restrict__ c,
+                                             int ix, int iy, int iz) {
   const int ax = ix >> 1, bx = (ix + 1) >> 1;
   const int ay = iy >> 1, by = (iy + 1) >> 1;
   const int az = iz >> 1, bz = (iz + 1) >> 1;
-  auto cv = [&](int a, int b, int d) { return c[((size_t)a * nc + b) * nc + d]; };
+  auto cv = [&](int a, int b, int d) { return c[((size_t)a * nc + b) * cp + d + co]; };
   double v = cv(ax, ay, az);
   if (iz & 1) v += cv(ax, ay, bz);
   if (iy & 1) {
@@ -1755,7 +1785,7 @@ __global__ void k_prolong_full(int nc, const double* __restrict__ c, double* __r
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < N;
        i += (long long)gridDim.x * blockDim.x) {
     const int ix = (int)(i / ((long long)nf * nf)), iy = (int)((i / nf) % nf), iz = (int)(i % nf);
-    f[i] = interior(nf, ix, iy, iz) ? prolong_at(nc, c, ix, iy, iz) : 0.0;
+    f[i] = interior(nf, ix, iy, iz) ? prolong_at(nc, nc, 0, c, ix, iy, iz) : 0.0;
   }
 }
 void prolong_full(int nc, const double* coarse, double* fine, hipStream_t s) {
@@ -1854,10 +1884,12 @@ __global__ void k_copy_rows(long long total, const double* __restrict__ src,
        i += (long long)gridDim.x * blockDim.x)
     dst[i] = src[i];
 }
-void copy_rows_strided(int n, int rows, const double* src, double* dst, hipStream_t s) {
-  const long long total = (long long)n * n * n * rows;
-  if (total <= 0) return;
-  hipLaunchKernelGGL(k_copy_rows, dim3(grid_for(total, 256)), dim3(256), 0, s, total, src, dst);
+void copy_elems(long long count, const double* src, double* dst, hipStream_t s) {
+  if (count <= 0) return;
+  hipLaunchKernelGGL(k_copy_rows, dim3(grid_for(count, 256)), dim3(256), 0, s, count, src, dst);
+}
+void copy_rows(int n, int rows, const double* src, double* dst, hipStream_t s) {
+  copy_elems(lay_row(n) * rows, src, dst, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -1888,18 +1920,18 @@ void shift_weights(int nprob, const double* phi, double theta, double* w, double
 constexpr int SB = 32;  // samples per block of the level reductions
 int level_sample_blocks(int M) { return (M + SB - 1) / SB; }
 
-// dX_m(v) = w_f[m] p_f[m](v) - w_c[m] (P p_c[m])(v) at interior v of the fine grid
+// dX_m(v) = w_f[m] p_f[m](v) - w_c[m] (P p_c[m])(v) at interior v = (ix, iy, iz)
+// of the fine grid; p_f and p_c are solver rows
 __device__ __forceinline__ double dx_at(int nf, int m, const double* __restrict__ pf,
                                         const double* __restrict__ wf,
                                         const double* __restrict__ pc,
-                                        const double* __restrict__ wc, long long v, int ix,
-                                        int iy, int iz) {
-  const size_t sf = (size_t)nf * nf * nf;
-  double d = wf[m] * pf[(size_t)m * sf + v];
+                                        const double* __restrict__ wc, int ix, int iy, int iz) {
+  const size_t sf = (size_t)lay_row(nf);
+  double d = wf[m] * pf[(size_t)m * sf + ((size_t)ix * nf + iy) * lay_pitch(nf) + iz + lay_off(nf)];
   if (pc) {
     const int nc = (nf - 1) / 2 + 1;
-    const size_t scs = (size_t)nc * nc * nc;
-    d -= wc[m] * prolong_at(nc, pc + (size_t)m * scs, ix, iy, iz);
+    const size_t scs = (size_t)lay_row(nc);
+    d -= wc[m] * prolong_at(nc, lay_pitch(nc), lay_off(nc), pc + (size_t)m * scs, ix, iy, iz);
   }
   return d;
 }
@@ -1915,7 +1947,7 @@ __global__ void k_level_dx_partial(int nf, int M, const double* __restrict__ pf,
   double acc = 0.0;
   if (interior(nf, ix, iy, iz)) {
     const int m1 = min(M, (sb + 1) * SB);
-    for (int m = sb * SB; m < m1; ++m) acc += dx_at(nf, m, pf, wf, pc, wc, v, ix, iy, iz);
+    for (int m = sb * SB; m < m1; ++m) acc += dx_at(nf, m, pf, wf, pc, wc, ix, iy, iz);
   }
   part[(size_t)sb * N + v] = acc;
 }
@@ -1963,7 +1995,7 @@ __global__ void __launch_bounds__(256)
     if (!interior(nf, ix, iy, iz)) continue;
     const double mv = mean[v];
     for (int m = sb * SB; m < m1; ++m) {
-      const double d = dx_at(nf, m, pf, wf, pc, wc, v, ix, iy, iz) - mv;
+      const double d = dx_at(nf, m, pf, wf, pc, wc, ix, iy, iz) - mv;
       acc += d * d;
     }
   }

@@ -52,6 +52,8 @@ static bool is_dyadic(int n) {
 }
 
 static inline size_t cube(int n) { return (size_t)n * n * n; }
+// elements of one solver row (padded z lines from 129 vertices on)
+static inline size_t srow(int n) { return (size_t)lay_row(n); }
 
 // One grid size of the hierarchy: rows [0, rows) are the problems whose top
 // grid is at least this size; rows [top_begin, rows) have exactly this top.
@@ -307,7 +309,7 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks, bool fields = tru
     for (int pass = 0; pass < 2; ++pass) {
       Carver cv{pass == 0 ? nullptr : (char*)P->arena};
       for (auto& s : P->sizes) {
-        const size_t e = (size_t)s.rows * cube(s.n);
+        const size_t e = (size_t)s.rows * srow(s.n);
         s.B = cv.take<double>(e);
         if (!c->mixed) {
           s.X = cv.take<double>(e);
@@ -324,7 +326,7 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks, bool fields = tru
         if (c->cache64 && !c->mixed) s.Di = cv.take<double>(e);
       }
       for (auto& g : P->groups) {
-        const size_t e = (size_t)g.count * cube(g.n);
+        const size_t e = (size_t)g.count * srow(g.n);
         g.x = cv.take<double>(e);
         g.q = cv.take<double>(e);
         g.b0 = cv.take<double>(e);
@@ -396,7 +398,7 @@ GridArgs args_size(mlsgd_ctx* c, Plan* P, const SizeLvl& s) {
   g.n = s.n;
   g.rows = s.rows;
   g.row0 = 0;
-  g.stride = (long long)cube(s.n);
+  g.stride = (long long)srow(s.n);
   g.t = s.t;
   g.coef = P->d_coef;
   g.K = c->pb.kl_K;
@@ -425,7 +427,7 @@ GridArgs args_group(mlsgd_ctx* c, Plan* P, const Group& gr, bool skip_inactive) 
   return g;
 }
 
-inline double* rows_of(double* base, const Group& gr) { return base + (size_t)gr.p0 * cube(gr.n); }
+inline double* rows_of(double* base, const Group& gr) { return base + (size_t)gr.p0 * srow(gr.n); }
 
 // Symmetric V(nu,nu) cycle for every active problem: z = V(r) with r in the
 // B rows of each problem's top grid and z left in its X rows.  Pre-smoothing
@@ -807,12 +809,12 @@ bool out_of_place(const mlsgd_ctx* c) {
 const double* z64(mlsgd_ctx* c, Plan* P, const Group& gr) {
   SizeLvl& L = P->sizes[gr.sl];
   const double* A = (out_of_place(c) && L.cur) ? L.R : L.X;
-  return A + (size_t)gr.p0 * cube(gr.n);
+  return A + (size_t)gr.p0 * srow(gr.n);
 }
 const float* z32(mlsgd_ctx* c, Plan* P, const Group& gr) {
   SizeLvl& L = P->sizes[gr.sl];
   const float* A = (out_of_place(c) && L.cur) ? L.Rf : L.Xf;
-  return A + (size_t)gr.p0 * cube(gr.n);
+  return A + (size_t)gr.p0 * srow(gr.n);
 }
 
 int read_count(mlsgd_ctx* c) {
@@ -840,8 +842,8 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
     if (mg && c->mixed) {
       for (auto& gr : P->groups) {
         SizeLvl& L = P->sizes[gr.sl];
-        to_f32((long long)gr.count * cube(gr.n), rows_of(L.B, gr),
-               L.Bf + (size_t)gr.p0 * cube(gr.n), s);
+        to_f32((long long)gr.count * srow(gr.n), rows_of(L.B, gr),
+               L.Bf + (size_t)gr.p0 * srow(gr.n), s);
       }
     }
     if (mg) {
@@ -870,7 +872,7 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
                 c->d_count, s);
       for (auto& gr : P->groups) {
         GridArgs g = args_group(c, P, gr, true);
-        float* r32 = (mg && c->mixed) ? P->sizes[gr.sl].Bf + (size_t)gr.p0 * cube(gr.n) : nullptr;
+        float* r32 = (mg && c->mixed) ? P->sizes[gr.sl].Bf + (size_t)gr.p0 * srow(gr.n) : nullptr;
         group_update(g, gr.x, gr.p[gr.pcur ^ 1], rows_of(P->sizes[gr.sl].B, gr), gr.q,
                      P->d_poff, P->d_partial, r32, s);
         gr.pcur ^= 1;
@@ -899,7 +901,7 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
     HIPCHK(hipGetLastError());
     if (read_count(c) == 0) break;
     for (auto& gr : P->groups)
-      copy_rows_strided(gr.n, gr.count, gr.q, rows_of(P->sizes[gr.sl].B, gr), s);
+      copy_rows(gr.n, gr.count, gr.q, rows_of(P->sizes[gr.sl].B, gr), s);
   }
   scal_to_stats(P->d_scal, P->nprob, rtol, &c->d_stat->iters, &c->d_stat->nonconv,
                 &c->d_stat->relres, s);
@@ -932,8 +934,8 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
     if (mg && c->mixed) {
       for (auto& gr : P->groups) {
         SizeLvl& L = P->sizes[gr.sl];
-        to_f32((long long)gr.count * cube(gr.n), rows_of(L.B, gr),
-               L.Bf + (size_t)gr.p0 * cube(gr.n), s);
+        to_f32((long long)gr.count * srow(gr.n), rows_of(L.B, gr),
+               L.Bf + (size_t)gr.p0 * srow(gr.n), s);
       }
     }
     if (mg) {
@@ -960,7 +962,7 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
       cg(PH_ALPHA, P->d_partial);
       for (auto& gr : P->groups) {
         GridArgs g = args_group(c, P, gr, true);
-        float* r32 = (mg && c->mixed) ? P->sizes[gr.sl].Bf + (size_t)gr.p0 * cube(gr.n) : nullptr;
+        float* r32 = (mg && c->mixed) ? P->sizes[gr.sl].Bf + (size_t)gr.p0 * srow(gr.n) : nullptr;
         group_update(g, gr.x, gr.p[gr.pcur ^ 1], rows_of(P->sizes[gr.sl].B, gr), gr.q,
                      P->d_poff, P->d_partial, r32, s);
         gr.pcur ^= 1;
@@ -992,7 +994,7 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
   iterate(iters);
   true_residual();
   for (auto& gr : P->groups)
-    copy_rows_strided(gr.n, gr.count, gr.q, rows_of(P->sizes[gr.sl].B, gr), s);
+    copy_rows(gr.n, gr.count, gr.q, rows_of(P->sizes[gr.sl].B, gr), s);
   start();
   iterate(kRestartIters);
   true_residual();
@@ -1022,7 +1024,7 @@ void state_phase(mlsgd_ctx* c, Plan* P, int* it, int* nc, double* rr, double* y_
     double* b = rows_of(P->sizes[gr.sl].B, gr);
     rows_broadcast(gr.n, gr.count, c->rhs_lvl[gr.n], b, s);
     rows_broadcast(gr.n, gr.count, c->rhs_lvl[gr.n], gr.b0, s);
-    rows_zero((long long)gr.count * cube(gr.n), gr.x, s);
+    rows_zero((long long)gr.count * srow(gr.n), gr.x, s);
   }
   HIPCHK(hipGetLastError());
   if (fixed > 0)
@@ -1030,11 +1032,11 @@ void state_phase(mlsgd_ctx* c, Plan* P, int* it, int* nc, double* rr, double* y_
   else
     krylov(c, P, it, nc, rr);
   for (auto& gr : P->groups) {
-    if (y_out) copy_rows_strided(gr.n, gr.count, gr.x, y_out, s);
+    if (y_out) unpack_rows(gr.n, gr.count, gr.x, y_out, s);
     GridArgs g = args_group(c, P, gr, false);
     double* b = rows_of(P->sizes[gr.sl].B, gr);
     group_misfit(g, gr.x, c->yd_lvl[gr.n], b, P->d_poff, P->d_partial, s);
-    copy_rows_strided(gr.n, gr.count, b, gr.b0, s);
+    copy_rows(gr.n, gr.count, b, gr.b0, s);
     const double h = 1.0 / (double)(gr.n - 1);
     sum_partials(gr.count, P->d_poff + gr.p0, P->d_pcnt + gr.p0, P->d_partial, 0.5 * h * h * h,
                  P->d_phi + gr.p0, s);
@@ -1176,12 +1178,12 @@ void estimate_enqueue(mlsgd_ctx* c, const EstPrep& e, int L, const int64_t* M, c
   if (grad_out) {
     for (int i = 0; i < L; ++i) {
       const int nf = c->pb.grid_n[i];
-      const double* pf = e.lr[i].gf->x + (size_t)e.lr[i].fine_row * cube(nf);
+      const double* pf = e.lr[i].gf->x + (size_t)e.lr[i].fine_row * srow(nf);
       const double* wf = P->d_w + e.lr[i].fine_prob;
       const double* pc = nullptr;
       const double* wc = nullptr;
       if (i > 0) {
-        pc = e.lr[i].gc->x + (size_t)e.lr[i].coarse_row * cube(c->pb.grid_n[i - 1]);
+        pc = e.lr[i].gc->x + (size_t)e.lr[i].coarse_row * srow(c->pb.grid_n[i - 1]);
         wc = P->d_w + e.lr[i].coarse_prob;
       }
       double* mean = c->mean_lvl[nf];
@@ -1697,7 +1699,7 @@ int mlsgd_solve_state_adjoint(mlsgd_ctx* c, int level, int coarse, int64_t first
                             c->stream));
     if (p_out) {
       krylov(c, P, &it2, &nc2, &r2);
-      copy_rows_strided(n, (int)count, P->groups[0].x, p_out, c->stream);
+      unpack_rows(n, (int)count, P->groups[0].x, p_out, c->stream);
     }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(c->stream));
@@ -1753,7 +1755,7 @@ int mlsgd_solve_sizes(mlsgd_ctx* c, int count, const int* n_list, int level, int
       Group& gr = P->groups[0];
       rows_broadcast(n, gr.count, rhs, rows_of(P->sizes[gr.sl].B, gr), s);
       rows_broadcast(n, gr.count, rhs, gr.b0, s);
-      rows_zero((long long)gr.count * cube(n), gr.x, s);
+      rows_zero((long long)gr.count * srow(n), gr.x, s);
       HIPCHK(hipGetLastError());
       int it = 0, nc = 0;
       double rr = 0.0;
@@ -1838,7 +1840,7 @@ double adaptive_tau(mlsgd_ctx* c, double tau0, double gnorm, double err_sam) {
   if (!(c->tau_prev > 0.0) || !(c->gnorm_prev > 0.0)) return c->tau_pos > 0.0 ? c->tau_pos : tau0;
   hipStream_t s = c->stream;
   const long long N = (long long)cube(c->nfin);
-  copy_rows_strided(c->nfin, 1, c->d_grad, c->d_gtmp, s);
+  copy_elems((long long)cube(c->nfin), c->d_grad, c->d_gtmp, s);
   axpy_full(c->nfin, -1.0, c->d_gprev, c->d_gtmp, s);
   dot_blocks(N, c->d_gtmp, c->d_gtmp, c->d_epi_part, s);
   finish_norm(c->nfin, c->d_epi_part, c->d_sc1, s);
@@ -1881,7 +1883,7 @@ int mlsgd_step(mlsgd_ctx* c, double* u, double tau, int adapt, mlsgd_step_stats*
     double tk = tau;
     if (adapt & MLSGD_ADAPT_STEP) {
       tk = adaptive_tau(c, tau, g.grad_norm, o.err_sam);
-      copy_rows_strided(c->nfin, 1, c->d_grad, c->d_gprev, c->stream);
+      copy_elems((long long)cube(c->nfin), c->d_grad, c->d_gprev, c->stream);
       c->have_gprev = true;
       c->tau_prev = tk;
       if (tk > 0.0) c->tau_pos = tk;

@@ -1,0 +1,143 @@
+"""Solver rows of grids with 129 or more vertices per axis are stored with
+padded z lines (the first interior vertex of every line on a 128-byte
+boundary).  These tests take every path through such rows against the FP64
+oracle on identical draws:
+- each smoother, coefficient mode and precision on a 17^3..129^3 hierarchy;
+- tile heights and ragged x chunks on the 129^3 grid;
+- independent solves of mixed sizes (129 padded, 65 and 33 dense) through the
+  packed output of mlsgd_solve_sizes;
+- the unpacked state and adjoint outputs of mlsgd_solve_state_adjoint.
+Bars as elsewhere: 1e-9 relative L2 (FP64), 1e-8 (FP32 V-cycles)."""
+import numpy as np
+import pytest
+
+from paper_2606_09291_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+GRID = [17, 33, 65, 129]
+M = [4, 2, 2, 1]
+KW = dict(theta=1.0, alpha=1e-3, sigma2=2.0)
+
+
+def _rel(a, b):
+    a = np.asarray(a, dtype=np.float64)
+    b = np.asarray(b, dtype=np.float64)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+@pytest.fixture(scope="module")
+def mm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2606_09291_amd as m
+    m.lib()
+    return m
+
+
+def _u_yd():
+    n = GRID[-1]
+    yd = inputs.target_sin(n)
+    return inputs.control_xyz(n) + 15.0 * yd, yd
+
+
+@pytest.fixture(scope="module")
+def oracle_grad(orc):
+    u, yd = _u_yd()
+    pb = orc.make_problem(GRID, rtol=1e-13, **KW)
+    go, so = orc.mlmc_gradient(pb, None, u, yd, M, first=[1, 1, 1, 1])
+    return go, so
+
+
+def _ctx(mm, precision="fp64", **extra):
+    prec = {"fp64": mm.FP64, "mixed": mm.MIXED_FP32, "bf16": mm.MIXED_BF16}[precision]
+    _, yd = _u_yd()
+    return mm.Context(mm.Problem(grid_n=GRID, y_d=yd, rtol=1e-12, precision=prec, **KW, **extra),
+                      use_tuned=False)
+
+
+@pytest.mark.parametrize("env,precision", [
+    ({}, "fp64"),                                                    # Chebyshev, fused first pass
+    ({"MLSGD_SMOOTHER": "rbgs"}, "fp64"),                            # in-place red-black GS
+    ({"MLSGD_SMOOTHER": "rbfused"}, "fp64"),                         # fused red-black sweeps
+    ({"MLSGD_SMOOTHER": "cheb", "MLSGD_CACHE64": "0"}, "fp64"),      # coefficient regenerated
+    ({}, "mixed"),
+    ({"MLSGD_SMOOTHER": "rbfused"}, "mixed"),
+    ({}, "bf16"),
+])
+def test_padded_hierarchy_matches_oracle(mm, oracle_grad, monkeypatch, env, precision):
+    print("padded hierarchy", env, precision, flush=True)
+    for k, v in env.items():
+        monkeypatch.setenv(k, v)
+    u, _ = _u_yd()
+    ctx = _ctx(mm, precision)
+    g, st = ctx.mlmc_gradient(u, M, first=[1, 1, 1, 1])
+    ctx.close()
+    go, so = oracle_grad
+    assert st["nonconverged"] == 0
+    assert _rel(g.cpu().numpy(), go) <= (1e-9 if precision == "fp64" else 1e-8)
+    assert st["J"] == pytest.approx(so["J"], rel=1e-10)
+
+
+@pytest.mark.parametrize("tuning", [{"tile_y": 4, "xchunk": 40}, {"tile_y": 16, "xchunk": 48},
+                                    {"tile_y": 8, "xchunk": 128}])
+def test_padded_tiles_match_oracle(mm, oracle_grad, tuning):
+    print("padded tiles", tuning, flush=True)
+    u, _ = _u_yd()
+    ctx = _ctx(mm)
+    ctx.set_tuning(**tuning)
+    g, st = ctx.mlmc_gradient(u, M, first=[1, 1, 1, 1])
+    ctx.close()
+    assert st["nonconverged"] == 0
+    assert _rel(g.cpu().numpy(), oracle_grad[0]) <= 1e-9
+
+
+def _oracle_solve(orc, n, sample, level, f_value, K=4, sigma2=1.0):
+    c = orc.kl_coeffs(0, level, sample, K, sigma2)
+    b = inputs.constant(n, f_value)
+    b[0] = b[-1] = 0
+    b[:, 0] = b[:, -1] = 0
+    b[:, :, 0] = b[:, :, -1] = 0
+    # the FP64 residual floor of a 129^3 solve sits just above 1e-13
+    x, _, rr = orc.solve(n, c, b, method=orc.SOLVE_MGPCG, rtol=2e-13)
+    assert rr <= 2e-13
+    return x
+
+
+def test_padded_solve_sizes(mm, orc):
+    sizes = [129, 33, 65, 129]
+    print("solve_sizes", sizes, flush=True)
+    ctx = mm.Context(mm.Problem(grid_n=[9, 17, 33, 65], y_d=inputs.target_sin(65), rtol=1e-12),
+                     use_tuned=False)
+    ys, st = ctx.solve_sizes(sizes, level=6, first=2, f_value=1.0)
+    ctx.close()
+    assert st["nonconverged"] == 0
+    for j, n in enumerate(sizes):
+        y = ys[j].cpu().numpy()
+        assert y[0].max() == 0 and y[:, :, -1].max() == 0
+        assert _rel(y, _oracle_solve(orc, n, 2 + j, 6, 1.0)) <= 1e-10
+
+
+def test_padded_state_adjoint_outputs(mm, orc):
+    print("state/adjoint 129", flush=True)
+    u, yd = _u_yd()
+    ctx = _ctx(mm)
+    y, p, phi, st = ctx.solve_state_adjoint(3, 0, 5, 2, u)
+    ctx.close()
+    n = GRID[-1]
+    for k in range(2):
+        c = orc.kl_coeffs(0, 3, 5 + k, 4, KW["sigma2"])
+        b = u.copy()
+        b[0] = b[-1] = 0
+        b[:, 0] = b[:, -1] = 0
+        b[:, :, 0] = b[:, :, -1] = 0
+        yo, _, _ = orc.solve(n, c, b, method=orc.SOLVE_MGPCG, rtol=1e-13)
+        assert _rel(y[k].cpu().numpy(), yo) <= 1e-10
+        r = yo - yd
+        r[0] = r[-1] = 0
+        r[:, 0] = r[:, -1] = 0
+        r[:, :, 0] = r[:, :, -1] = 0
+        po, _, _ = orc.solve(n, c, r, method=orc.SOLVE_MGPCG, rtol=1e-13)
+        assert _rel(p[k].cpu().numpy(), po) <= 1e-10
+        assert float(phi[k]) == pytest.approx(orc.misfit(n, yo, yd), rel=1e-9)
