@@ -243,6 +243,10 @@ __global__ void __launch_bounds__(TY* TZ)
   const int iy = y0 + ly, iz = z0 + lz;
   const bool inside = (iy <= n - 1) && (iz <= n - 1);
   const bool own = (iy <= n - 2) && (iz <= n - 2);
+  // the out-of-place ops also store the boundary zero at z = n - 1 on padded
+  // grids, so their stores cover whole 128-byte lines
+  constexpr bool OUT_OF_PLACE = OP != OP_GS;
+  const bool zedge = OUT_OF_PLACE && LO > 0 && iy <= n - 2 && iz == n - 1;
 
   // halo slot (no corners are needed by a 7-point stencil)
   constexpr int NH = 2 * (TY + TZ);
@@ -475,7 +479,7 @@ __global__ void __launch_bounds__(TY* TZ)
     const T xp = full(xn);
     const T bp = cvt(bn);
     const T fxp = face(bc, bp);
-    if (own) {
+    if (own || zedge) {
       const T xym = sx[buf][cidx - PZ], xyp = sx[buf][cidx + PZ];
       const T xzm = sx[buf][cidx - 1], xzp = sx[buf][cidx + 1];
       const T fym = face(bc, sb[buf][cidx - PZ]), fyp = face(bc, sb[buf][cidx + PZ]);
@@ -483,15 +487,19 @@ __global__ void __launch_bounds__(TY* TZ)
       const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
       const T off = ((fxm * xm + fxp * xp) + (fym * xym + fyp * xyp)) + (fzm * xzm + fzp * xzp);
       const size_t idx = base + ((size_t)ix * n + iy) * LP + iz + LO;
+      // the z = n - 1 lane computes from in-bounds (zero-start) values and
+      // stores a zero in the same vector store as its line's vertices
       if (OP == OP_RESID) {
-        __builtin_nontemporal_store(bv - ih2 * (diag * xcur - off), &out[idx]);
+        const T r = bv - ih2 * (diag * xcur - off);
+        __builtin_nontemporal_store(own ? r : T(0), &out[idx]);
       } else if (OP == OP_MATVEC) {
-        const T q = ih2 * (diag * xcur - off);
+        const T q = own ? ih2 * (diag * xcur - off) : T(0);
         __builtin_nontemporal_store(q, &out[idx]);
         __builtin_nontemporal_store(xcur, &out2[idx]);
         dot += (double)xcur * (double)q;
       } else if (OP == OP_JAC || OP == OP_JACP || OP == OP_JAC2Z) {
-        const T val = xcur + omega * (bv - ih2 * (diag * xcur - off)) * drcp(ih2 * diag);
+        const T v = xcur + omega * (bv - ih2 * (diag * xcur - off)) * drcp(ih2 * diag);
+        const T val = own ? v : T(0);
         __builtin_nontemporal_store(val, &out[idx]);
         if (partial) dot += (double)bv * (double)val;
       } else {  // OP_GS
@@ -1466,7 +1474,47 @@ void rows_zero(long long count, double* x, hipStream_t s) {
 
 enum GroupOp { G_DOT = 0, G_UPDATE = 1, G_MISFIT = 2 };
 
+// Elementwise step of one group op at solver-row element k (interior vertex
+// (ix, iy, iz)); returns the term of the workgroup's partial sum.
 template <int OP>
+__device__ __forceinline__ double group_elem(size_t k, int n, int ix, int iy, int iz, double al,
+                                             double* __restrict__ a, const double* __restrict__ b,
+                                             double* __restrict__ c,
+                                             const double* __restrict__ d,
+                                             float* __restrict__ cf) {
+  if (OP == G_DOT) return a[k] * b[k];
+  if (OP == G_UPDATE) {
+    a[k] = a[k] + al * b[k];
+    const double r = c[k] - al * d[k];
+    c[k] = r;
+    if (cf) cf[k] = (float)r;
+    return r * r;
+  }
+  // G_MISFIT
+  const double r = a[k] - b[((size_t)ix * n + iy) * n + iz];
+  c[k] = r;
+  a[k] = 0.0;
+  return r * r;
+}
+
+// Group ops over the rows of one group; each row is cut into tiles_per_row
+// workgroups whose partial sums land in fixed slots (deterministic sums).
+//   G_DOT    : <a, b>
+//   G_UPDATE : a += alpha b (x += alpha p), c -= alpha d (r -= alpha q),
+//              <c, c>; cf (nullable) receives c in FP32
+//   G_MISFIT : c = a - y_d (b: dense y_d, shared), a = 0, <c, c>
+// Only interior vertices are visited: boundary vertices and padding of these
+// rows hold zeros that every op leaves unchanged.  On grids of 65 and more
+// vertices a wave walks whole interior z lines (z = 1 .. n-2, 64 lanes
+// abreast), skipping the boundary planes, lines and padding in memory.  NZ > 0
+// is the number of 64-point chunks of a line (n - 1 <= 64 NZ): a lane then
+// handles LU = max(1, 4 / NZ) lines per step and issues the loads of all its
+// LU x NZ points before any store.  These lines also take the boundary
+// vertex z = n - 1 (a zero in every operand, so unchanged): with the padded
+// layout the stores then cover whole 128-byte lines.  NZ = 0 walks lines of any length one
+// chunk at a time; NZ = -1 (grids below 65) strides over the dense row and
+// tests each vertex.
+template <int OP, int NZ>
 __global__ void __launch_bounds__(256)
     k_group(GridArgs g, double* __restrict__ a, const double* __restrict__ b,
             double* __restrict__ c, const double* __restrict__ d, const int* __restrict__ poff,
@@ -1477,82 +1525,112 @@ __global__ void __launch_bounds__(256)
   const int tile = blockIdx.x - row * tpr;
   const int prob = g.row0 + row;
   if (g.scal && !g.scal[prob].active) return;
-  const long long N = g.stride;
-  const long long chunk = (N + tpr - 1) / tpr;
-  const long long lo = (long long)tile * chunk;
-  const long long hi = min(N, lo + chunk);
-  const size_t base = (size_t)row * (size_t)N;
-  const int n = g.n;
+  const int n = g.n, m = n - 2;
+  const size_t base = (size_t)row * (size_t)g.stride;
+  const double al = OP == G_UPDATE ? g.scal[prob].alpha : 0.0;
   double acc = 0.0;
-  if (OP == G_DOT) {
-    for (long long i = lo + threadIdx.x; i < hi; i += 256) acc += a[base + i] * b[base + i];
-  } else if (OP == G_UPDATE) {
-    // x += alpha p, r -= alpha q; four elements per thread in flight (the
-    // per-thread summation order of <r, r> is the plain ascending one)
-    const double al = g.scal[prob].alpha;
-    constexpr int U = 4;
-    long long i = lo + threadIdx.x;
-    for (; i + (U - 1) * 256 < hi; i += U * 256) {
-      double xa[U], pb[U], rc[U], qd[U];
+  if constexpr (NZ >= 0) {
+    const int lp = lay_pitch(n), lo = lay_off(n);
+    const long long lines = (long long)m * m;
+    const long long per = (lines + tpr - 1) / tpr;
+    const long long l0 = (long long)tile * per, l1 = min(lines, l0 + per);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if constexpr (NZ > 0 && OP != G_MISFIT) {
+      constexpr int LU = NZ >= 4 ? 1 : 4 / NZ;
+      for (long long l = l0 + wave; l < l1; l += 4 * LU) {
+        size_t k[LU][NZ];
+        bool ok[LU][NZ];
+        double va[LU][NZ], vb[LU][NZ], vc[LU][NZ], vd[LU][NZ];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const size_t k = base + i + u * 256;
-        xa[u] = a[k];
-        pb[u] = b[k];
-        rc[u] = c[k];
-        qd[u] = d[k];
+        for (int u = 0; u < LU; ++u) {
+          const long long ll = l + 4 * u;
+          const int ix = 1 + (int)(ll / m), iy = 1 + (int)(ll % m);
+          const size_t lb = base + ((size_t)ix * n + iy) * lp + lo;
+#pragma unroll
+          for (int j = 0; j < NZ; ++j) {
+            const int iz = 1 + lane + 64 * j;
+            ok[u][j] = ll < l1 && iz <= m + 1;
+            k[u][j] = lb + iz;
+            if (ok[u][j]) {
+              va[u][j] = a[k[u][j]];
+              vb[u][j] = b[k[u][j]];
+              if (OP == G_UPDATE) {
+                vc[u][j] = c[k[u][j]];
+                vd[u][j] = d[k[u][j]];
+              }
+            }
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < LU; ++u) {
+#pragma unroll
+          for (int j = 0; j < NZ; ++j) {
+            if (!ok[u][j]) continue;
+            if (OP == G_DOT) {
+              acc += va[u][j] * vb[u][j];
+            } else {
+              a[k[u][j]] = va[u][j] + al * vb[u][j];
+              const double r = vc[u][j] - al * vd[u][j];
+              c[k[u][j]] = r;
+              if (cf) cf[k[u][j]] = (float)r;
+              acc += r * r;
+            }
+          }
+        }
       }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const size_t k = base + i + u * 256;
-        a[k] = xa[u] + al * pb[u];
-        const double r = rc[u] - al * qd[u];
-        c[k] = r;
-        if (cf) cf[k] = (float)r;
-        acc += r * r;
+    } else {
+      for (long long l = l0 + wave; l < l1; l += 4) {
+        const int ix = 1 + (int)(l / m), iy = 1 + (int)(l % m);
+        const size_t lb = base + ((size_t)ix * n + iy) * lp + lo;
+        for (int iz = 1 + lane; iz <= m; iz += 64)
+          acc += group_elem<OP>(lb + iz, n, ix, iy, iz, al, a, b, c, d, cf);
       }
     }
-    for (; i < hi; i += 256) {
-      const size_t k = base + i;
-      a[k] = a[k] + al * b[k];
-      const double r = c[k] - al * d[k];
-      c[k] = r;
-      if (cf) cf[k] = (float)r;
-      acc += r * r;
-    }
-  } else {  // G_MISFIT: a = y (reset to 0 afterwards), b = y_d (shared), c = adjoint rhs rows
-    const int lp = lay_pitch(n), lo_ = lay_off(n);
+  } else {
+    const long long N = g.stride;
+    const long long chunk = (N + tpr - 1) / tpr;
+    const long long lo = (long long)tile * chunk;
+    const long long hi = min(N, lo + chunk);
     for (long long i = lo + threadIdx.x; i < hi; i += 256) {
-      const int ix = (int)(i / ((long long)n * lp)), iy = (int)((i / lp) % n),
-                iz = (int)(i % lp) - lo_;
-      const bool in = ix > 0 && iy > 0 && iz > 0 && ix < n - 1 && iy < n - 1 && iz < n - 1;
-      const double r = in ? a[base + i] - b[((size_t)ix * n + iy) * n + iz] : 0.0;
-      c[base + i] = r;
-      a[base + i] = 0.0;
-      acc += r * r;
+      const int ix = (int)(i / ((long long)n * n)), iy = (int)((i / n) % n), iz = (int)(i % n);
+      if (ix > 0 && iy > 0 && iz > 0 && ix < n - 1 && iy < n - 1 && iz < n - 1)
+        acc += group_elem<OP>(base + i, n, ix, iy, iz, al, a, b, c, d, cf);
     }
   }
   const double sum = block_sum<256>(acc, sred);
   if (threadIdx.x == 0) partial[poff[prob] + tile] = sum;
 }
 
+template <int OP>
+static void launch_group(const GridArgs& g, double* a, const double* b, double* c,
+                         const double* d, const int* poff, double* partial, float* cf,
+                         hipStream_t s) {
+  if (g.rows <= 0) return;
+  const dim3 grid(g.rows * g.t.tiles_per_row), block(256);
+  const int m = g.n - 2;
+  if (m < 63)
+    hipLaunchKernelGGL((k_group<OP, -1>), grid, block, 0, s, g, a, b, c, d, poff, partial, cf);
+  else if (m <= 64)
+    hipLaunchKernelGGL((k_group<OP, 1>), grid, block, 0, s, g, a, b, c, d, poff, partial, cf);
+  else if (m <= 128)
+    hipLaunchKernelGGL((k_group<OP, 2>), grid, block, 0, s, g, a, b, c, d, poff, partial, cf);
+  else if (m <= 256)
+    hipLaunchKernelGGL((k_group<OP, 4>), grid, block, 0, s, g, a, b, c, d, poff, partial, cf);
+  else
+    hipLaunchKernelGGL((k_group<OP, 0>), grid, block, 0, s, g, a, b, c, d, poff, partial, cf);
+}
+
 void group_dot(const GridArgs& g, const double* a, const double* b, const int* poff,
                double* partial, hipStream_t s) {
-  if (g.rows <= 0) return;
-  hipLaunchKernelGGL(k_group<G_DOT>, dim3(g.rows * g.t.tiles_per_row), dim3(256), 0, s, g,
-                     (double*)a, b, nullptr, nullptr, poff, partial, nullptr);
+  launch_group<G_DOT>(g, (double*)a, b, nullptr, nullptr, poff, partial, nullptr, s);
 }
 void group_update(const GridArgs& g, double* x, const double* p, double* r, const double* q,
                   const int* poff, double* partial, float* r32, hipStream_t s) {
-  if (g.rows <= 0) return;
-  hipLaunchKernelGGL(k_group<G_UPDATE>, dim3(g.rows * g.t.tiles_per_row), dim3(256), 0, s, g,
-                     x, p, r, q, poff, partial, r32);
+  launch_group<G_UPDATE>(g, x, p, r, q, poff, partial, r32, s);
 }
 void group_misfit(const GridArgs& g, double* y, const double* yd, double* b_rows,
                   const int* poff, double* partial, hipStream_t s) {
-  if (g.rows <= 0) return;
-  hipLaunchKernelGGL(k_group<G_MISFIT>, dim3(g.rows * g.t.tiles_per_row), dim3(256), 0, s, g,
-                     y, yd, b_rows, nullptr, poff, partial, nullptr);
+  launch_group<G_MISFIT>(g, y, yd, b_rows, nullptr, poff, partial, nullptr, s);
 }
 
 // ---------------------------------------------------------------------------
