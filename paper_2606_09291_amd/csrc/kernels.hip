@@ -1512,8 +1512,9 @@ __device__ __forceinline__ double group_elem(size_t k, int n, int ix, int iy, in
 // LU x NZ points before any store.  These lines also take the boundary
 // vertex z = n - 1 (a zero in every operand, so unchanged): with the padded
 // layout the stores then cover whole 128-byte lines.  NZ = 0 walks lines of any length one
-// chunk at a time; NZ = -1 (grids below 65) strides over the dense row and
-// tests each vertex.
+// chunk at a time; NZ = -1 (grids below 65) strides over the dense row: the
+// misfit tests each vertex, the dot and the update stream every element
+// (boundary zeros pass through unchanged), four per thread in flight.
 template <int OP, int NZ>
 __global__ void __launch_bounds__(256)
     k_group(GridArgs g, double* __restrict__ a, const double* __restrict__ b,
@@ -1591,10 +1592,42 @@ __global__ void __launch_bounds__(256)
     const long long chunk = (N + tpr - 1) / tpr;
     const long long lo = (long long)tile * chunk;
     const long long hi = min(N, lo + chunk);
-    for (long long i = lo + threadIdx.x; i < hi; i += 256) {
-      const int ix = (int)(i / ((long long)n * n)), iy = (int)((i / n) % n), iz = (int)(i % n);
-      if (ix > 0 && iy > 0 && iz > 0 && ix < n - 1 && iy < n - 1 && iz < n - 1)
-        acc += group_elem<OP>(base + i, n, ix, iy, iz, al, a, b, c, d, cf);
+    long long i = lo + threadIdx.x;
+    if (OP == G_MISFIT) {
+      for (; i < hi; i += 256) {
+        const int ix = (int)(i / ((long long)n * n)), iy = (int)((i / n) % n), iz = (int)(i % n);
+        if (ix > 0 && iy > 0 && iz > 0 && ix < n - 1 && iy < n - 1 && iz < n - 1)
+          acc += group_elem<OP>(base + i, n, ix, iy, iz, al, a, b, c, d, cf);
+      }
+    } else {
+      constexpr int U = 4;
+      for (; i + (U - 1) * 256 < hi; i += U * 256) {
+        double va[U], vb[U], vc[U], vd[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const size_t k = base + i + u * 256;
+          va[u] = a[k];
+          vb[u] = b[k];
+          if (OP == G_UPDATE) {
+            vc[u] = c[k];
+            vd[u] = d[k];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const size_t k = base + i + u * 256;
+          if (OP == G_DOT) {
+            acc += va[u] * vb[u];
+          } else {
+            a[k] = va[u] + al * vb[u];
+            const double r = vc[u] - al * vd[u];
+            c[k] = r;
+            if (cf) cf[k] = (float)r;
+            acc += r * r;
+          }
+        }
+      }
+      for (; i < hi; i += 256) acc += group_elem<OP>(base + i, n, 0, 0, 0, al, a, b, c, d, cf);
     }
   }
   const double sum = block_sum<256>(acc, sred);
