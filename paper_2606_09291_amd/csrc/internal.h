@@ -97,6 +97,13 @@ void dinv_rows(int n, int rows, const void* cache, int cache_bf16, T* dinv, hipS
 template <typename T>
 void march_jac2z(const GridArgs& g, const T* dinv, const T* b, T* xout, double omega1,
                  double omega2, hipStream_t s);
+// the same two steps and the residual of their result in one pass:
+// xout = J(omega2) J(omega1) 0, rout = b - A xout (64-wide tiles of height 8
+// or 16 and a cached coefficient only; returns false, launching nothing,
+// otherwise)
+template <typename T>
+bool march_pre2r(const GridArgs& g, const T* dinv, const T* b, T* xout, T* rout, double omega1,
+                 double omega2, hipStream_t s);
 
 // ---- batched grid transfers (rows of one grid size) ----
 template <typename T>

@@ -638,6 +638,250 @@ template void march_jac2z<double>(const GridArgs&, const double*, const double*,
 template void march_jac2z<float>(const GridArgs&, const float*, const float*, float*, double,
                                  double, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// Fused pre-smoothing and residual.  From x = 0, the first two Chebyshev
+// steps and the residual of their result in one pass:
+//   x1 = omega1 b / D                   (pointwise, from b and the stored 1/D)
+//   x2 = x1 + omega2 D^-1 (b - A x1)
+//   r  = b - A x2
+// x2 and r are written; b, 1/D and 1/a are read once: 40 B per point instead
+// of 32 + 32 for the two-step pass and a residual pass.  Both outputs equal
+// those two passes' bitwise (same faces, neighbours and summation order).
+//
+// The march lags the residual one plane behind the second step.  At plane q
+// the workgroup puts x1 and 1/a of its patch and a two-point ring in LDS,
+// forms x2 on the patch and its one-point ring (LDS, double-buffered), and
+// then r on plane q - 1.  Besides its patch column, thread t owns one ring
+// slot: t < NR a column of the one-point ring (x2 is formed there, so it
+// keeps x1 and 1/a of three planes like the patch columns), NR <= t < 2 NR a
+// slot of the two-point ring, and the next four threads the corners of the
+// one-point ring (NR = 2 (TY + TZ); the corners of the two-point ring are not
+// needed).  1/a sits in a ring of three LDS planes, as plane q - 1 is still
+// read after the next plane is stored.  Each patch column keeps the faces it
+// formed for x2 on plane q and reuses them for r on that plane one step
+// later.  The loads of plane q + 2 are issued at the start of step q and
+// combined at its end.
+// ---------------------------------------------------------------------------
+template <typename T, int TY, int TZ, int CK>
+__global__ void __launch_bounds__(TY* TZ)
+    k_pre2r(GridArgs g, const T* __restrict__ dinv, const T* __restrict__ rhs,
+            T* __restrict__ xout, T* __restrict__ rout, T omega1, T omega2) {
+  constexpr int NT = TY * TZ;
+  constexpr int PZ = TZ + 4;
+  constexpr int PLANE = (TY + 4) * PZ;
+  constexpr int NR = 2 * (TY + TZ);
+  static_assert(2 * NR + 4 <= NT, "tile too small for its rings");
+  using CR = typename std::conditional<CK == 2, uint16_t, T>::type;
+  __shared__ T s1[PLANE];      // x1, plane q
+  __shared__ T sb[3][PLANE];   // 1/a, plane q in slot q % 3
+  __shared__ T s2[2][PLANE];   // x2, plane q in slot q & 1
+
+  const int n = g.n;
+  const int LP = lay_pitch(n), LO = lay_off(n);
+  const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int tpr = g.t.tiles_per_row;
+  const int row = bid / tpr;
+  const int tile = bid - row * tpr;
+  int tt = tile;
+  const int ty = tt % g.t.nty;
+  tt /= g.t.nty;
+  const int tz = tt % g.t.ntz;
+  const int xc = tt / g.t.ntz;
+  const int prob = g.row0 + row;
+  if (g.scal && !g.scal[prob].active) return;  // uniform per workgroup
+
+  const size_t base = (size_t)row * (size_t)g.stride;
+  const CR* __restrict__ cache = (const CR*)g.cache + (size_t)prob * (size_t)g.stride;
+  const int tid = threadIdx.x;
+  const int y0 = 1 + ty * TY, z0 = 1 + tz * TZ;
+  const T ih2 = (T)g.ih2;
+
+  // LDS coordinates: the patch is [2, TY+2) x [2, TZ+2); grid vertex (jy, jz)
+  // sits at (jy - y0 + 2, jz - z0 + 2)
+  auto ring_slot = [&](int t, int d) {  // slot t < NR of the d-point ring
+    int a, b;
+    if (t < TZ) {
+      a = 2 - d; b = 2 + t;
+    } else if (t < 2 * TZ) {
+      a = TY + 1 + d; b = 2 + t - TZ;
+    } else if (t < 2 * TZ + TY) {
+      a = 2 + t - 2 * TZ; b = 2 - d;
+    } else {
+      a = 2 + t - 2 * TZ - TY; b = TZ + 1 + d;
+    }
+    return a * PZ + b;
+  };
+  const int ly = tid / TZ, lz = tid - (tid / TZ) * TZ;
+  const int oidx = (ly + 2) * PZ + (lz + 2);
+  int sidx = 0;
+  const bool ring1 = tid < NR;                       // x2 is formed at this slot
+  const bool s_on = tid < 2 * NR + 4;
+  if (tid < NR) {
+    sidx = ring_slot(tid, 1);
+  } else if (tid < 2 * NR) {
+    sidx = ring_slot(tid - NR, 2);
+  } else if (s_on) {
+    const int k = tid - 2 * NR;
+    sidx = ((k >> 1) ? TY + 2 : 1) * PZ + ((k & 1) ? TZ + 2 : 1);
+  }
+  const int oy = y0 - 2 + oidx / PZ, oz = z0 - 2 + oidx % PZ;
+  const int sy = y0 - 2 + sidx / PZ, sz = z0 - 2 + sidx % PZ;
+  auto in_grid = [&](int jy, int jz) { return jy >= 0 && jz >= 0 && jy <= n - 1 && jz <= n - 1; };
+  auto in_int = [&](int jy, int jz) { return jy >= 1 && jz >= 1 && jy <= n - 2 && jz <= n - 2; };
+  const bool o_grid = in_grid(oy, oz), o_int = in_int(oy, oz);
+  const bool s_grid = s_on && in_grid(sy, sz), s_int = s_on && in_int(sy, sz);
+
+  // one plane of one column as loaded: b, 1/D (interior only) and 1/a
+  struct Raw {
+    T b, d;
+    CR a;
+  };
+  const CR one = CK == 2 ? CR(0x3F80) : CR(1);
+  auto load = [&](int ix, int jy, int jz, bool grid, bool inter) -> Raw {
+    Raw v{T(0), T(0), one};
+    if (ix < 0 || ix > n - 1 || !grid) return v;
+    const size_t e = ((size_t)ix * n + jy) * LP + jz + LO;
+    v.a = cache[e];
+    if (inter && ix >= 1 && ix <= n - 2) {
+      v.b = rhs[base + e];
+      v.d = dinv[base + e];
+    }
+    return v;
+  };
+  auto cvt = [&](CR v) -> T {
+    if constexpr (CK == 2)
+      return (T)from_bf16(v);
+    else
+      return v;
+  };
+  auto x1of = [&](const Raw& v) -> T { return (omega1 * v.b) * v.d; };
+
+  const int x0 = 1 + xc * g.t.xchunk;
+  const int x1 = min(x0 + g.t.xchunk, n - 1);
+
+  // On entry to step q: x1 and 1/a at q-1, q, q+1 and b at q, q+1 for the
+  // patch column (o*) and the slot (s*; two-point ring slots and corners use
+  // plane q only)
+  T oxm, oxc, oxp, obm, obc, obp, orc, orp;
+  T sxm = T(0), sxc = T(0), sxp = T(0), sbm = T(1), sbc = T(1), sbp = T(1), src = T(0), srp = T(0);
+  {
+    const int q = x0 - 1;
+    const Raw m = load(q - 1, oy, oz, o_grid, o_int), c = load(q, oy, oz, o_grid, o_int),
+              p = load(q + 1, oy, oz, o_grid, o_int);
+    oxm = x1of(m); oxc = x1of(c); oxp = x1of(p);
+    obm = cvt(m.a); obc = cvt(c.a); obp = cvt(p.a);
+    orc = c.b; orp = p.b;
+    if (s_on) {
+      const Raw sm = load(q - 1, sy, sz, s_grid, s_int), sc = load(q, sy, sz, s_grid, s_int),
+                sp = load(q + 1, sy, sz, s_grid, s_int);
+      sxm = x1of(sm); sxc = x1of(sc); sxp = x1of(sp);
+      sbm = cvt(sm.a); sbc = cvt(sc.a); sbp = cvt(sp.a);
+      src = sc.b; srp = sp.b;
+    }
+  }
+
+  // patch column: x2 at q-2, q-1, the faces of plane q-1 and b at q-1
+  T x2a = T(0), x2b = T(0), rm_ = T(0);
+  T gfxm = T(0), gfxp = T(0), gfym = T(0), gfyp = T(0), gfzm = T(0), gfzp = T(0), gdiag = T(1);
+
+  for (int q = x0 - 1; q <= x1; ++q) {
+    const Raw on = load(q + 2, oy, oz, o_grid, o_int);
+    Raw sn{T(0), T(0), one};
+    if (s_on) sn = load(q + 2, sy, sz, s_grid, s_int);
+
+    T* __restrict__ b3 = sb[q % 3];
+    s1[oidx] = oxc;
+    b3[oidx] = obc;
+    if (s_on) {
+      s1[sidx] = sxc;
+      b3[sidx] = sbc;
+    }
+    __syncthreads();
+
+    // x2 on plane q: patch and one-point ring
+    const bool qin = q >= 1 && q <= n - 2;
+    T x2c = T(0);
+    T fxm = T(0), fxp = T(0), fym = T(0), fyp = T(0), fzm = T(0), fzp = T(0), diag = T(1);
+    if (qin && o_int) {
+      fxm = face(obc, obm);
+      fxp = face(obc, obp);
+      fym = face(obc, b3[oidx - PZ]);
+      fyp = face(obc, b3[oidx + PZ]);
+      fzm = face(obc, b3[oidx - 1]);
+      fzp = face(obc, b3[oidx + 1]);
+      diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
+      const T off = ((fxm * oxm + fxp * oxp) + (fym * s1[oidx - PZ] + fyp * s1[oidx + PZ])) +
+                    (fzm * s1[oidx - 1] + fzp * s1[oidx + 1]);
+      x2c = oxc + omega2 * (orc - ih2 * (diag * oxc - off)) * drcp(ih2 * diag);
+    }
+    T* __restrict__ x2s = s2[q & 1];
+    x2s[oidx] = x2c;
+    if (ring1) {
+      T v = T(0);
+      if (qin && s_int) {
+        const T hxm = face(sbc, sbm), hxp = face(sbc, sbp);
+        const T hym = face(sbc, b3[sidx - PZ]), hyp = face(sbc, b3[sidx + PZ]);
+        const T hzm = face(sbc, b3[sidx - 1]), hzp = face(sbc, b3[sidx + 1]);
+        const T hd = ((hxm + hxp) + (hym + hyp)) + (hzm + hzp);
+        const T hoff = ((hxm * sxm + hxp * sxp) + (hym * s1[sidx - PZ] + hyp * s1[sidx + PZ])) +
+                       (hzm * s1[sidx - 1] + hzp * s1[sidx + 1]);
+        v = sxc + omega2 * (src - ih2 * (hd * sxc - hoff)) * drcp(ih2 * hd);
+      }
+      x2s[sidx] = v;
+    }
+    __syncthreads();
+
+    // r on plane q-1 from x2 of planes q-2, q-1 (LDS with ring), q
+    const int qr = q - 1;
+    if (qr >= x0 && o_int) {
+      const T* __restrict__ x2p = s2[qr & 1];
+      const T off = ((gfxm * x2a + gfxp * x2c) + (gfym * x2p[oidx - PZ] + gfyp * x2p[oidx + PZ])) +
+                    (gfzm * x2p[oidx - 1] + gfzp * x2p[oidx + 1]);
+      const T r = rm_ - ih2 * (gdiag * x2b - off);
+      const size_t e = base + ((size_t)qr * n + oy) * LP + oz + LO;
+      __builtin_nontemporal_store(x2b, &xout[e]);
+      __builtin_nontemporal_store(r, &rout[e]);
+    }
+
+    // advance one plane
+    x2a = x2b;
+    x2b = x2c;
+    rm_ = orc;
+    gfxm = fxm; gfxp = fxp; gfym = fym; gfyp = fyp; gfzm = fzm; gfzp = fzp; gdiag = diag;
+    oxm = oxc; oxc = oxp; oxp = x1of(on);
+    obm = obc; obc = obp; obp = cvt(on.a);
+    orc = orp; orp = on.b;
+    if (s_on) {
+      sxm = sxc; sxc = sxp; sxp = x1of(sn);
+      sbm = sbc; sbc = sbp; sbp = cvt(sn.a);
+      src = srp; srp = sn.b;
+    }
+  }
+}
+
+template <typename T>
+bool march_pre2r(const GridArgs& g, const T* dinv, const T* b, T* xout, T* rout, double omega1,
+                 double omega2, hipStream_t s) {
+  if (g.t.TZ != 64 || g.t.TY < 8 || !g.cache) return false;
+  if (g.rows <= 0) return true;
+  const int nblk = g.rows * g.t.tiles_per_row;
+#define MLSGD_LAUNCH(TY_, CK_)                                                                  \
+  hipLaunchKernelGGL((k_pre2r<T, TY_, 64, CK_>), dim3(nblk), dim3(TY_ * 64), 0, s, g, dinv, b, \
+                     xout, rout, (T)omega1, (T)omega2)
+  const bool b16 = sizeof(T) == 4 && g.cache_bf16;
+  if (g.t.TY == 8) {
+    if (b16) MLSGD_LAUNCH(8, 2); else MLSGD_LAUNCH(8, 1);
+  } else {
+    if (b16) MLSGD_LAUNCH(16, 2); else MLSGD_LAUNCH(16, 1);
+  }
+#undef MLSGD_LAUNCH
+  return true;
+}
+template bool march_pre2r<double>(const GridArgs&, const double*, const double*, double*,
+                                  double*, double, double, hipStream_t);
+template bool march_pre2r<float>(const GridArgs&, const float*, const float*, float*, float*,
+                                 double, double, hipStream_t);
+
 // Reciprocal diagonal drcp(h^-2 ((fxm + fxp) + (fym + fyp)) + (fzm + fzp)) of
 // every interior vertex, with the faces and the summation order of k_march,
 // so the first smoothing step formed from it equals the one k_march forms.

@@ -177,6 +177,7 @@ struct mlsgd_ctx {
   double cheb_lo = 1.0 / 6.0;  // Chebyshev interval [cheb_lo * 2, 2] for D^-1 A
   int tile_y = 8;           // y extent of the stencil tiles on large grids
   int xchunk = 32;          // x planes per workgroup
+  bool pre2r = true;        // fused pre-smoothing and residual pass where it applies
   // event timing of the smoothing passes on one grid size (roofline figures)
   struct Timing {
     bool on = false;
@@ -624,6 +625,14 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
     int cur = 0;
     int j0 = 1;
     const T* dinv = dinv_of<T>(L);
+    if (deg == 2 && dinv && c->pre2r &&
+        march_pre2r<T>(g, dinv, v.B, A[1], A[0], om[0], om[1], c->stream)) {
+      // both pre-smoothing steps and the residual in one pass: x2 in A[1], r in A[0]
+      restrict_rows<T>(L.n, L.rows, 0, P->d_scal, A[0], mg_view<T>(P->sizes[k + 1]).B,
+                       c->stream);
+      L.cur = 1;
+      continue;
+    }
     if (deg >= 2 && dinv) {
       // steps 0 and 1 in one pass from the stored reciprocal diagonal
       march_jac2z<T>(g, dinv, v.B, A[1], om[0], om[1], c->stream);
@@ -1511,6 +1520,7 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     if (const char* e = getenv("MLSGD_CHEB_LO")) c->cheb_lo = atof(e);
     if (const char* e = getenv("MLSGD_TY64")) c->tile_y = atoi(e);
     if (const char* e = getenv("MLSGD_XCHUNK")) c->xchunk = atoi(e);
+    if (const char* e = getenv("MLSGD_PRE2R")) c->pre2r = atoi(e) != 0;
     c->nfin = pb->grid_n[pb->n_levels - 1];
     const size_t NF = cube(c->nfin);
     c->d_f = (double*)dalloc(c.get(), sizeof(double) * NF);

@@ -141,3 +141,49 @@ def test_padded_state_adjoint_outputs(mm, orc):
         po, _, _ = orc.solve(n, c, r, method=orc.SOLVE_MGPCG, rtol=1e-13)
         assert _rel(p[k].cpu().numpy(), po) <= 1e-10
         assert float(phi[k]) == pytest.approx(orc.misfit(n, yo, yd), rel=1e-9)
+
+
+@pytest.mark.parametrize("grid,M,precision,tuning", [
+    ([17, 33, 65], [8, 4, 3], "fp64", {}),
+    ([17, 33, 65], [8, 4, 3], "mixed", {}),
+    ([17, 33, 65], [8, 4, 3], "bf16", {}),
+    (GRID, M, "fp64", {}),
+    (GRID, M, "fp64", {"tile_y": 16, "xchunk": 40}),
+    (GRID, M, "mixed", {"tile_y": 8, "xchunk": 24}),
+])
+def test_fused_presmoothing_equals_separate_passes(mm, orc, monkeypatch, grid, M, precision, tuning):
+    """The one-pass pre-smoothing with its residual (64-wide tiles) computes
+    what the two-step pass followed by the residual pass computes, with the
+    same faces, neighbours and summation order; only the compiler's fused
+    multiply-adds may differ.  Whole estimates then agree to rounding (a wrong
+    neighbour or plane would change the preconditioner and move the Krylov
+    iterates, and the result, by about the solver tolerance) with identical
+    iteration counts, and both match the oracle."""
+    print("fused presmoothing", grid, precision, tuning, flush=True)
+    nL = grid[-1]
+    yd = inputs.target_sin(nL)
+    u = inputs.control_xyz(nL) + 15.0 * yd
+    prec = {"fp64": mm.FP64, "mixed": mm.MIXED_FP32, "bf16": mm.MIXED_BF16}[precision]
+    out = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("MLSGD_PRE2R", flag)
+        ctx = mm.Context(mm.Problem(grid_n=grid, y_d=yd, rtol=1e-12, precision=prec, **KW),
+                         use_tuned=False)
+        if tuning:
+            ctx.set_tuning(**tuning)
+        g, st = ctx.mlmc_gradient(u, M, first=[2] * len(M))
+        ctx.close()
+        assert st["nonconverged"] == 0
+        out.append((g.cpu().numpy(), st))
+    d = _rel(out[1][0], out[0][0])
+    print("fused vs separate: relative L2", d, "iterations", out[0][1]["iters_state"],
+          out[1][1]["iters_state"], out[0][1]["iters_adjoint"], out[1][1]["iters_adjoint"],
+          flush=True)
+    assert d <= 1e-13
+    assert out[0][1]["J"] == pytest.approx(out[1][1]["J"], rel=1e-14)
+    assert out[0][1]["iters_state"] == out[1][1]["iters_state"]
+    assert out[0][1]["iters_adjoint"] == out[1][1]["iters_adjoint"]
+    if grid != GRID:
+        pb = orc.make_problem(grid, rtol=1e-13, **KW)
+        go, _ = orc.mlmc_gradient(pb, None, u, yd, M, first=[2] * len(M))
+        assert _rel(out[1][0], go) <= (1e-9 if precision == "fp64" else 1e-8)
