@@ -97,13 +97,26 @@ void dinv_rows(int n, int rows, const void* cache, int cache_bf16, T* dinv, hipS
 template <typename T>
 void march_jac2z(const GridArgs& g, const T* dinv, const T* b, T* xout, double omega1,
                  double omega2, hipStream_t s);
+// the fused smoothing passes below serve the 8x64, 16x64, 8x32 and 16x16
+// tiles (grids of 17 and more vertices, tile height 4 excepted) with a cached
+// coefficient
+inline bool fused_tiles(const GridArgs& g) {
+  return g.cache != nullptr && ((g.t.TZ == 64 && g.t.TY >= 8) || g.t.TZ == 32 || g.t.TZ == 16);
+}
 // the same two steps and the residual of their result in one pass:
-// xout = J(omega2) J(omega1) 0, rout = b - A xout (64-wide tiles of height 8
-// or 16 and a cached coefficient only; returns false, launching nothing,
-// otherwise)
+// xout = J(omega2) J(omega1) 0, rout = b - A xout (tiles and coefficient as
+// fused_tiles; returns false, launching nothing, otherwise)
 template <typename T>
 bool march_pre2r(const GridArgs& g, const T* dinv, const T* b, T* xout, T* rout, double omega1,
                  double omega2, hipStream_t s);
+// two Jacobi steps after the coarse-grid correction in one pass:
+// xout = J(omega_b) J(omega_a) (xin + P xc), partials of <b, xout> for the
+// problems >= top_begin (partial nullable); same tile and coefficient
+// conditions (and xc non-null), false otherwise
+template <typename T>
+bool march_post2(const GridArgs& g, const T* xin, const T* xc, const T* b, T* xout,
+                 double omega_a, double omega_b, const int* poff, double* partial, int top_begin,
+                 hipStream_t s);
 
 // ---- batched grid transfers (rows of one grid size) ----
 template <typename T>

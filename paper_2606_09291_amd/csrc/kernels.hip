@@ -862,18 +862,28 @@ __global__ void __launch_bounds__(TY* TZ)
 template <typename T>
 bool march_pre2r(const GridArgs& g, const T* dinv, const T* b, T* xout, T* rout, double omega1,
                  double omega2, hipStream_t s) {
-  if (g.t.TZ != 64 || g.t.TY < 8 || !g.cache) return false;
+  if (!fused_tiles(g)) return false;
   if (g.rows <= 0) return true;
   const int nblk = g.rows * g.t.tiles_per_row;
-#define MLSGD_LAUNCH(TY_, CK_)                                                                  \
-  hipLaunchKernelGGL((k_pre2r<T, TY_, 64, CK_>), dim3(nblk), dim3(TY_ * 64), 0, s, g, dinv, b, \
-                     xout, rout, (T)omega1, (T)omega2)
+#define MLSGD_LAUNCH(TY_, TZ_, CK_)                                                     \
+  hipLaunchKernelGGL((k_pre2r<T, TY_, TZ_, CK_>), dim3(nblk), dim3(TY_ * TZ_), 0, s, g, \
+                     dinv, b, xout, rout, (T)omega1, (T)omega2)
+#define MLSGD_LAUNCH2(TY_, TZ_)  \
+  if (b16)                       \
+    MLSGD_LAUNCH(TY_, TZ_, 2);   \
+  else                           \
+    MLSGD_LAUNCH(TY_, TZ_, 1)
   const bool b16 = sizeof(T) == 4 && g.cache_bf16;
-  if (g.t.TY == 8) {
-    if (b16) MLSGD_LAUNCH(8, 2); else MLSGD_LAUNCH(8, 1);
+  if (g.t.TZ == 16) {
+    MLSGD_LAUNCH2(16, 16);
+  } else if (g.t.TZ == 32) {
+    MLSGD_LAUNCH2(8, 32);
+  } else if (g.t.TY == 8) {
+    MLSGD_LAUNCH2(8, 64);
   } else {
-    if (b16) MLSGD_LAUNCH(16, 2); else MLSGD_LAUNCH(16, 1);
+    MLSGD_LAUNCH2(16, 64);
   }
+#undef MLSGD_LAUNCH2
 #undef MLSGD_LAUNCH
   return true;
 }
@@ -881,6 +891,305 @@ template bool march_pre2r<double>(const GridArgs&, const double*, const double*,
                                   double*, double, double, hipStream_t);
 template bool march_pre2r<float>(const GridArgs&, const float*, const float*, float*, float*,
                                  double, double, hipStream_t);
+
+// ---------------------------------------------------------------------------
+// Fused post-smoothing: two Chebyshev steps after the coarse-grid correction
+// in one pass,
+//   y  = x + P e                        (trilinear prolongation of the coarse e)
+//   x3 = y  + omega_a D^-1 (b - A y)
+//   x4 = x3 + omega_b D^-1 (b - A x3)
+// with the partial sums of <b, x4> for the problems whose top grid this is.
+// x, e / 8, b and 1/a are read and x4 written once: 33 B per point instead of
+// 33 + 32 for the step with the folded correction and a plain step.  Both
+// steps use k_march's faces, neighbours and summation order.
+//
+// The plane pipeline is that of k_pre2r (y in place of x1): y and 1/a of the
+// patch and a two-point ring on plane q in LDS, x3 on the patch and its
+// one-point ring, x4 on plane q - 1.  The coarse planes covering the
+// two-point ring's footprint sit in a four-plane LDS ring (TY/2 + 3 by
+// TZ/2 + 3 coarse points); every column forms its prolonged correction with
+// ProlongLds, two planes ahead of its use.
+// ---------------------------------------------------------------------------
+template <typename T, int TY, int TZ, int CK>
+__global__ void __launch_bounds__(TY* TZ)
+    k_post2(GridArgs g, const T* __restrict__ xin, const T* __restrict__ xc,
+            const T* __restrict__ rhs, T* __restrict__ xout, const int* __restrict__ poff,
+            double* __restrict__ partial, int top_begin, T omega_a, T omega_b) {
+  constexpr int NT = TY * TZ;
+  constexpr int PZ = TZ + 4;
+  constexpr int PLANE = (TY + 4) * PZ;
+  constexpr int NR = 2 * (TY + TZ);
+  static_assert(2 * NR + 4 <= NT, "tile too small for its rings");
+  constexpr int CYN = TY / 2 + 3, CZN = TZ / 2 + 3;
+  constexpr int CSLAB = CYN * CZN;
+  static_assert(CSLAB <= NT, "coarse slab larger than the workgroup");
+  using CR = typename std::conditional<CK == 2, uint16_t, T>::type;
+  __shared__ T s1[PLANE];      // y, plane q
+  __shared__ T sb[3][PLANE];   // 1/a, plane q in slot q % 3
+  __shared__ T s3[2][PLANE];   // x3, plane q in slot q & 1
+  __shared__ T scs[4 * CSLAB]; // coarse plane J in slot J & 3
+  __shared__ double sred[NT / 64];
+
+  const int n = g.n;
+  const int LP = lay_pitch(n), LO = lay_off(n);
+  const int bid = xcd_swizzle(blockIdx.x, gridDim.x);
+  const int tpr = g.t.tiles_per_row;
+  const int row = bid / tpr;
+  const int tile = bid - row * tpr;
+  int tt = tile;
+  const int ty = tt % g.t.nty;
+  tt /= g.t.nty;
+  const int tz = tt % g.t.ntz;
+  const int xcix = tt / g.t.ntz;
+  const int prob = g.row0 + row;
+  if (g.scal && !g.scal[prob].active) return;  // uniform per workgroup
+
+  const size_t base = (size_t)row * (size_t)g.stride;
+  const CR* __restrict__ cache = (const CR*)g.cache + (size_t)prob * (size_t)g.stride;
+  const int tid = threadIdx.x;
+  const int y0 = 1 + ty * TY, z0 = 1 + tz * TZ;
+  const T ih2 = (T)g.ih2;
+
+  auto ring_slot = [&](int t, int d) {  // slot t < NR of the d-point ring
+    int a, b;
+    if (t < TZ) {
+      a = 2 - d; b = 2 + t;
+    } else if (t < 2 * TZ) {
+      a = TY + 1 + d; b = 2 + t - TZ;
+    } else if (t < 2 * TZ + TY) {
+      a = 2 + t - 2 * TZ; b = 2 - d;
+    } else {
+      a = 2 + t - 2 * TZ - TY; b = TZ + 1 + d;
+    }
+    return a * PZ + b;
+  };
+  const int ly = tid / TZ, lz = tid - (tid / TZ) * TZ;
+  const int oidx = (ly + 2) * PZ + (lz + 2);
+  int sidx = 0;
+  const bool ring1 = tid < NR;
+  const bool s_on = tid < 2 * NR + 4;
+  if (tid < NR) {
+    sidx = ring_slot(tid, 1);
+  } else if (tid < 2 * NR) {
+    sidx = ring_slot(tid - NR, 2);
+  } else if (s_on) {
+    const int k = tid - 2 * NR;
+    sidx = ((k >> 1) ? TY + 2 : 1) * PZ + ((k & 1) ? TZ + 2 : 1);
+  }
+  const int oy = y0 - 2 + oidx / PZ, oz = z0 - 2 + oidx % PZ;
+  const int sy = y0 - 2 + sidx / PZ, sz = z0 - 2 + sidx % PZ;
+  auto in_grid = [&](int jy, int jz) { return jy >= 0 && jz >= 0 && jy <= n - 1 && jz <= n - 1; };
+  auto in_int = [&](int jy, int jz) { return jy >= 1 && jz >= 1 && jy <= n - 2 && jz <= n - 2; };
+  const bool o_grid = in_grid(oy, oz), o_int = in_int(oy, oz);
+  const bool s_grid = s_on && in_grid(sy, sz), s_int = s_on && in_int(sy, sz);
+
+  struct Raw {  // one plane of one column as loaded: x, b (interior only), 1/a
+    T x, b;
+    CR a;
+  };
+  const CR one = CK == 2 ? CR(0x3F80) : CR(1);
+  auto load = [&](int ix, int jy, int jz, bool grid, bool inter) -> Raw {
+    Raw v{T(0), T(0), one};
+    if (ix < 0 || ix > n - 1 || !grid) return v;
+    const size_t e = ((size_t)ix * n + jy) * LP + jz + LO;
+    v.a = cache[e];
+    if (inter && ix >= 1 && ix <= n - 2) {
+      v.x = xin[base + e];
+      v.b = rhs[base + e];
+    }
+    return v;
+  };
+  auto cvt = [&](CR v) -> T {
+    if constexpr (CK == 2)
+      return (T)from_bf16(v);
+    else
+      return v;
+  };
+
+  // coarse ring: lane l < CSLAB owns slab point (cy0 + l / CZN, cz0 + l % CZN)
+  const int nc = (n - 1) / 2 + 1;
+  const int cLP = lay_pitch(nc), cLO = lay_off(nc);
+  const T* __restrict__ crow = xc + (size_t)row * (size_t)lay_row(nc);
+  const int cy0 = (y0 - 3) >> 1, cz0 = (z0 - 3) >> 1;
+  bool cld = false;
+  size_t coff = 0;
+  if (tid < CSLAB) {
+    const int gy = cy0 + tid / CZN, gz = cz0 + tid % CZN;
+    cld = gy >= 0 && gz >= 0 && gy <= nc - 1 && gz <= nc - 1;
+    if (cld) coff = (size_t)gy * cLP + gz + cLO;
+  }
+  auto cload = [&](int J) -> T {
+    return (cld && J >= 0 && J <= nc - 1) ? crow[(size_t)J * nc * cLP + coff] : T(0);
+  };
+  auto cstore = [&](int J, T v) {
+    if (tid < CSLAB) scs[(J & 3) * CSLAB + tid] = v;
+  };
+  ProlongLds<T> pco, pcs;
+  // prolonged correction of plane ix of a column (zero where x is)
+  auto corr = [&](ProlongLds<T>& pc, int ix, bool inter) -> T {
+    const T v = pc.at(scs, CSLAB, ix);
+    return (inter && ix >= 1 && ix <= n - 2) ? v : T(0);
+  };
+
+  const int x0 = 1 + xcix * g.t.xchunk;
+  const int x1 = min(x0 + g.t.xchunk, n - 1);
+  const int ixs = x0 - 2;  // first plane whose y a column forms
+  int chi = (x0 + 1) >> 1; // highest coarse plane stored
+  for (int J = ixs >> 1; J <= chi; ++J) cstore(J, cload(J));
+  T cnext = cload(chi + 1);
+  __syncthreads();
+  pco.init(scs, CSLAB, CZN, cy0, cz0, oy, oz, ixs);
+  if (s_on) pcs.init(scs, CSLAB, CZN, cy0, cz0, sy, sz, ixs);
+
+  // On entry to step q: y and 1/a at q-1, q, q+1 and b at q, q+1 for the
+  // patch column (o*) and the slot (s*; two-point ring slots and corners use
+  // plane q only)
+  T oym, oyc, oyp, obm, obc, obp, orc, orp;
+  T sym = T(0), syc = T(0), syp = T(0), sbm = T(1), sbc = T(1), sbp = T(1), src = T(0), srp = T(0);
+  {
+    const Raw m = load(ixs, oy, oz, o_grid, o_int), c = load(ixs + 1, oy, oz, o_grid, o_int),
+              p = load(ixs + 2, oy, oz, o_grid, o_int);
+    oym = m.x + corr(pco, ixs, o_int);
+    oyc = c.x + corr(pco, ixs + 1, o_int);
+    oyp = p.x + corr(pco, ixs + 2, o_int);
+    obm = cvt(m.a); obc = cvt(c.a); obp = cvt(p.a);
+    orc = c.b; orp = p.b;
+    if (s_on) {
+      const Raw sm = load(ixs, sy, sz, s_grid, s_int), sc = load(ixs + 1, sy, sz, s_grid, s_int),
+                sp = load(ixs + 2, sy, sz, s_grid, s_int);
+      sym = sm.x + corr(pcs, ixs, s_int);
+      syc = sc.x + corr(pcs, ixs + 1, s_int);
+      syp = sp.x + corr(pcs, ixs + 2, s_int);
+      sbm = cvt(sm.a); sbc = cvt(sc.a); sbp = cvt(sp.a);
+      src = sc.b; srp = sp.b;
+    }
+  }
+
+  // patch column: x3 at q-2, q-1, b at q-1 and 1/a at q-2
+  T x3a = T(0), x3b = T(0), rm_ = T(0), obmm = T(1);
+  double dot = 0.0;
+
+  for (int q = x0 - 1; q <= x1; ++q) {
+    const Raw on = load(q + 2, oy, oz, o_grid, o_int);
+    Raw sn{T(0), T(0), one};
+    if (s_on) sn = load(q + 2, sy, sz, s_grid, s_int);
+    if (((q + 3) >> 1) > chi) {
+      ++chi;
+      cstore(chi, cnext);
+      cnext = cload(chi + 1);
+    }
+
+    T* __restrict__ b3 = sb[q % 3];
+    s1[oidx] = oyc;
+    b3[oidx] = obc;
+    if (s_on) {
+      s1[sidx] = syc;
+      b3[sidx] = sbc;
+    }
+    __syncthreads();
+    const T ocn = corr(pco, q + 2, o_int);
+    const T scn = s_on ? corr(pcs, q + 2, s_int) : T(0);
+
+    // x3 on plane q: patch and one-point ring
+    const bool qin = q >= 1 && q <= n - 2;
+    T x3c = T(0);
+    if (qin && o_int) {
+      const T fxm = face(obc, obm), fxp = face(obc, obp);
+      const T fym = face(obc, b3[oidx - PZ]), fyp = face(obc, b3[oidx + PZ]);
+      const T fzm = face(obc, b3[oidx - 1]), fzp = face(obc, b3[oidx + 1]);
+      const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
+      const T off = ((fxm * oym + fxp * oyp) + (fym * s1[oidx - PZ] + fyp * s1[oidx + PZ])) +
+                    (fzm * s1[oidx - 1] + fzp * s1[oidx + 1]);
+      x3c = oyc + omega_a * (orc - ih2 * (diag * oyc - off)) * drcp(ih2 * diag);
+    }
+    T* __restrict__ x3s = s3[q & 1];
+    x3s[oidx] = x3c;
+    if (ring1) {
+      T v = T(0);
+      if (qin && s_int) {
+        const T hxm = face(sbc, sbm), hxp = face(sbc, sbp);
+        const T hym = face(sbc, b3[sidx - PZ]), hyp = face(sbc, b3[sidx + PZ]);
+        const T hzm = face(sbc, b3[sidx - 1]), hzp = face(sbc, b3[sidx + 1]);
+        const T hd = ((hxm + hxp) + (hym + hyp)) + (hzm + hzp);
+        const T hoff = ((hxm * sym + hxp * syp) + (hym * s1[sidx - PZ] + hyp * s1[sidx + PZ])) +
+                       (hzm * s1[sidx - 1] + hzp * s1[sidx + 1]);
+        v = syc + omega_a * (src - ih2 * (hd * syc - hoff)) * drcp(ih2 * hd);
+      }
+      x3s[sidx] = v;
+    }
+    __syncthreads();
+
+    // x4 on plane q-1 from x3 of planes q-2, q-1 (LDS with ring), q; the
+    // faces of plane q-1 are formed again from 1/a (registers and LDS)
+    const int qr = q - 1;
+    if (qr >= x0 && o_int) {
+      const T* __restrict__ x3p = s3[qr & 1];
+      const T* __restrict__ bq = sb[qr % 3];
+      const T fxm = face(obm, obmm), fxp = face(obm, obc);
+      const T fym = face(obm, bq[oidx - PZ]), fyp = face(obm, bq[oidx + PZ]);
+      const T fzm = face(obm, bq[oidx - 1]), fzp = face(obm, bq[oidx + 1]);
+      const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
+      const T off = ((fxm * x3a + fxp * x3c) + (fym * x3p[oidx - PZ] + fyp * x3p[oidx + PZ])) +
+                    (fzm * x3p[oidx - 1] + fzp * x3p[oidx + 1]);
+      const T val = x3b + omega_b * (rm_ - ih2 * (diag * x3b - off)) * drcp(ih2 * diag);
+      const size_t e = base + ((size_t)qr * n + oy) * LP + oz + LO;
+      __builtin_nontemporal_store(val, &xout[e]);
+      if (partial) dot += (double)rm_ * (double)val;
+    }
+
+    // advance one plane
+    x3a = x3b;
+    x3b = x3c;
+    rm_ = orc;
+    obmm = obm;
+    oym = oyc; oyc = oyp; oyp = on.x + ocn;
+    obm = obc; obc = obp; obp = cvt(on.a);
+    orc = orp; orp = on.b;
+    if (s_on) {
+      sym = syc; syc = syp; syp = sn.x + scn;
+      sbm = sbc; sbc = sbp; sbp = cvt(sn.a);
+      src = srp; srp = sn.b;
+    }
+  }
+  if (partial != nullptr && prob >= top_begin) {
+    const double s = block_sum<NT>(dot, sred);
+    if (threadIdx.x == 0) partial[poff[prob] + tile] = s;
+  }
+}
+
+template <typename T>
+bool march_post2(const GridArgs& g, const T* xin, const T* xc, const T* b, T* xout,
+                 double omega_a, double omega_b, const int* poff, double* partial, int top_begin,
+                 hipStream_t s) {
+  if (!fused_tiles(g) || !xc) return false;
+  if (g.rows <= 0) return true;
+  const int nblk = g.rows * g.t.tiles_per_row;
+#define MLSGD_LAUNCH(TY_, TZ_, CK_)                                                        \
+  hipLaunchKernelGGL((k_post2<T, TY_, TZ_, CK_>), dim3(nblk), dim3(TY_ * TZ_), 0, s, g, xin, \
+                     xc, b, xout, poff, partial, top_begin, (T)omega_a, (T)omega_b)
+#define MLSGD_LAUNCH2(TY_, TZ_)  \
+  if (b16)                       \
+    MLSGD_LAUNCH(TY_, TZ_, 2);   \
+  else                           \
+    MLSGD_LAUNCH(TY_, TZ_, 1)
+  const bool b16 = sizeof(T) == 4 && g.cache_bf16;
+  if (g.t.TZ == 16) {
+    MLSGD_LAUNCH2(16, 16);
+  } else if (g.t.TZ == 32) {
+    MLSGD_LAUNCH2(8, 32);
+  } else if (g.t.TY == 8) {
+    MLSGD_LAUNCH2(8, 64);
+  } else {
+    MLSGD_LAUNCH2(16, 64);
+  }
+#undef MLSGD_LAUNCH2
+#undef MLSGD_LAUNCH
+  return true;
+}
+template bool march_post2<double>(const GridArgs&, const double*, const double*, const double*,
+                                  double*, double, double, const int*, double*, int, hipStream_t);
+template bool march_post2<float>(const GridArgs&, const float*, const float*, const float*,
+                                 float*, double, double, const int*, double*, int, hipStream_t);
 
 // Reciprocal diagonal drcp(h^-2 ((fxm + fxp) + (fym + fyp)) + (fzm + fzp)) of
 // every interior vertex, with the faces and the summation order of k_march,

@@ -178,9 +178,11 @@ struct mlsgd_ctx {
   int tile_y = 8;           // y extent of the stencil tiles on large grids
   int xchunk = 32;          // x planes per workgroup
   bool pre2r = true;        // fused pre-smoothing and residual pass where it applies
+  bool post2 = true;        // fused two-step post-smoothing pass where it applies
   // event timing of the smoothing passes on one grid size (roofline figures)
   struct Timing {
     bool on = false;
+    int kind = 1;            // 1 plain smoothing step, 2 fused post-smoothing pass
     int n = 0;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pool;
     size_t used = 0;
@@ -537,9 +539,9 @@ void timed_sweep(mlsgd_ctx* c, const GridArgs& g, const T* xin, const T* xc, con
 }
 
 template <typename F>
-void timed_launch(mlsgd_ctx* c, const GridArgs& g, double bytes, F&& fn) {
+void timed_launch(mlsgd_ctx* c, const GridArgs& g, double bytes, F&& fn, int kind = 1) {
   mlsgd_ctx::Timing& tm = c->tm;
-  const bool rec = tm.on && g.n == tm.n && g.rows > 0;
+  const bool rec = tm.on && tm.kind == kind && g.n == tm.n && g.rows > 0;
   if (rec) {
     if (tm.used == tm.pool.size()) {
       hipEvent_t a, e;
@@ -580,6 +582,16 @@ double jac_bytes(int n, int rows, bool x_zero, bool prolong, const GridArgs& g) 
   double b = 2.0 * e + (x_zero ? 0.0 : e) + ce;
   if (prolong) b += e / 8.0;
   return N * b;
+}
+
+// Algorithmic bytes of the fused post-smoothing pass: x, b and 1/a read, x''
+// written, coarse rows read once.
+template <typename T>
+double post2_bytes(int n, int rows, const GridArgs& g) {
+  const double N = (double)rows * (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
+  const double e = (double)sizeof(T);
+  const double ce = g.cache_bf16 ? 2.0 : e;
+  return N * (3.0 * e + ce + e / 8.0);
 }
 
 // Symmetric V(1,1) cycle with degree-nu Chebyshev smoothing (a polynomial in
@@ -625,8 +637,8 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
     int cur = 0;
     int j0 = 1;
     const T* dinv = dinv_of<T>(L);
-    if (deg == 2 && dinv && c->pre2r &&
-        march_pre2r<T>(g, dinv, v.B, A[1], A[0], om[0], om[1], c->stream)) {
+    if (deg == 2 && dinv && c->pre2r && fused_tiles(g)) {
+      march_pre2r<T>(g, dinv, v.B, A[1], A[0], om[0], om[1], c->stream);
       // both pre-smoothing steps and the residual in one pass: x2 in A[1], r in A[0]
       restrict_rows<T>(L.n, L.rows, 0, P->d_scal, A[0], mg_view<T>(P->sizes[k + 1]).B,
                        c->stream);
@@ -664,7 +676,18 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
     const T* xc = Lc.cur ? vc.R : vc.X;
     GridArgs g = args(L);
     int cur = L.cur;
-    for (int j = 0; j < deg; ++j) {
+    int j = 0;
+    if (deg >= 2 && c->post2 && fused_tiles(g)) {
+      // the step with the coarse-grid correction and the next one in one pass
+      timed_launch(c, g, post2_bytes<T>(L.n, L.rows, g), [&] {
+        march_post2<T>(g, A[cur], xc, v.B, A[cur ^ 1], om[deg - 1], om[deg - 2],
+                       deg == 2 ? P->d_poff : nullptr, deg == 2 ? P->d_partial : nullptr,
+                       L.top_begin, c->stream);
+      }, 2);
+      cur ^= 1;
+      j = 2;
+    }
+    for (; j < deg; ++j) {
       const bool last = j == deg - 1;
       const T* corr = j == 0 ? xc : nullptr;
       if (corr) {   // the step with the folded correction is a separate kernel; not timed
@@ -1521,6 +1544,7 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     if (const char* e = getenv("MLSGD_TY64")) c->tile_y = atoi(e);
     if (const char* e = getenv("MLSGD_XCHUNK")) c->xchunk = atoi(e);
     if (const char* e = getenv("MLSGD_PRE2R")) c->pre2r = atoi(e) != 0;
+    if (const char* e = getenv("MLSGD_POST2")) c->post2 = atoi(e) != 0;
     c->nfin = pb->grid_n[pb->n_levels - 1];
     const size_t NF = cube(c->nfin);
     c->d_f = (double*)dalloc(c.get(), sizeof(double) * NF);
@@ -1577,7 +1601,9 @@ int mlsgd_kernel_timing(mlsgd_ctx* c, int enable, int n, double* ms_total, int64
     if (launches) *launches = c->tm.launches;
     if (bytes) *bytes = c->tm.total_bytes;
     if (enable >= 0) {
+      require(enable <= 2, "enable must be -1, 0, 1 or 2");
       c->tm.on = enable != 0;
+      c->tm.kind = enable != 0 ? enable : 1;
       c->tm.n = n;
       c->tm.ms = 0.0;
       c->tm.total_bytes = 0.0;

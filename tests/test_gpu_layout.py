@@ -151,15 +151,16 @@ def test_padded_state_adjoint_outputs(mm, orc):
     (GRID, M, "fp64", {"tile_y": 16, "xchunk": 40}),
     (GRID, M, "mixed", {"tile_y": 8, "xchunk": 24}),
 ])
-def test_fused_presmoothing_equals_separate_passes(mm, orc, monkeypatch, grid, M, precision, tuning):
-    """The one-pass pre-smoothing with its residual (64-wide tiles) computes
-    what the two-step pass followed by the residual pass computes, with the
-    same faces, neighbours and summation order; only the compiler's fused
-    multiply-adds may differ.  Whole estimates then agree to rounding (a wrong
+def test_fused_smoothing_equals_separate_passes(mm, orc, monkeypatch, grid, M, precision, tuning):
+    """The one-pass pre-smoothing with its residual and the one-pass
+    post-smoothing (64-wide tiles) compute what the separate passes compute
+    (two-step pass and residual pass; step with the folded coarse-grid
+    correction and plain step), with the same faces, neighbours and summation
+    order; only the compiler's fused multiply-adds may differ.  Whole estimates then agree to rounding (a wrong
     neighbour or plane would change the preconditioner and move the Krylov
     iterates, and the result, by about the solver tolerance) with identical
     iteration counts, and both match the oracle."""
-    print("fused presmoothing", grid, precision, tuning, flush=True)
+    print("fused smoothing", grid, precision, tuning, flush=True)
     nL = grid[-1]
     yd = inputs.target_sin(nL)
     u = inputs.control_xyz(nL) + 15.0 * yd
@@ -167,6 +168,7 @@ def test_fused_presmoothing_equals_separate_passes(mm, orc, monkeypatch, grid, M
     out = []
     for flag in ("0", "1"):
         monkeypatch.setenv("MLSGD_PRE2R", flag)
+        monkeypatch.setenv("MLSGD_POST2", flag)
         ctx = mm.Context(mm.Problem(grid_n=grid, y_d=yd, rtol=1e-12, precision=prec, **KW),
                          use_tuned=False)
         if tuning:
