@@ -924,8 +924,14 @@ __global__ void __launch_bounds__(TY* TZ)
   constexpr int CSLAB = CYN * CZN;
   static_assert(CSLAB <= NT, "coarse slab larger than the workgroup");
   using CR = typename std::conditional<CK == 2, uint16_t, T>::type;
+  // FP64 shares faces through LDS (its reciprocal costs five operations);
+  // FP32 forms every face from 1/a (one reciprocal instruction)
+  constexpr bool SHARE = sizeof(T) == 8;
+  constexpr int NF = SHARE ? 3 : 1, NB = SHARE ? 1 : 3;
   __shared__ T s1[PLANE];      // y, plane q
-  __shared__ T sb[3][PLANE];   // 1/a, plane q in slot q % 3
+  __shared__ T sb[NB][PLANE];  // 1/a: plane q + 1 (SHARE) or plane q in slot q % 3
+  __shared__ T fy[NF][SHARE ? PLANE : 1];  // face to +y, plane p in slot p % 3
+  __shared__ T fz[NF][SHARE ? PLANE : 1];  // face to +z, plane p in slot p % 3
   __shared__ T s3[2][PLANE];   // x3, plane q in slot q & 1
   __shared__ T scs[4 * CSLAB]; // coarse plane J in slot J & 3
   __shared__ double sred[NT / 64];
@@ -1044,8 +1050,26 @@ __global__ void __launch_bounds__(TY* TZ)
   // On entry to step q: y and 1/a at q-1, q, q+1 and b at q, q+1 for the
   // patch column (o*) and the slot (s*; two-point ring slots and corners use
   // plane q only)
-  T oym, oyc, oyp, obm, obc, obp, orc, orp;
-  T sym = T(0), syc = T(0), syp = T(0), sbm = T(1), sbc = T(1), sbp = T(1), src = T(0), srp = T(0);
+  // Faces.  A face is shared by its two vertices: every position forms the
+  // faces to +y and +z of plane p once into LDS (from 1/a of plane p, stored
+  // one step ahead), and every stencil column forms the face to +x of its
+  // plane and keeps the one to -x from the plane before.  Faces of the last
+  // row and column of the patch-with-rings are never read and not formed.
+  T* __restrict__ sa = sb[0];
+  auto faces_yz = [&](int p, int idx) {
+    if constexpr (SHARE) {
+      const int r = idx / PZ, cc = idx - (idx / PZ) * PZ;
+      if (r < TY + 3) fy[p % 3][idx] = face(sa[idx], sa[idx + PZ]);
+      if (cc < TZ + 3) fz[p % 3][idx] = face(sa[idx], sa[idx + 1]);
+    }
+  };
+
+  // On entry to step q: y at q-1, q, q+1, 1/a at q, q+1, b at q, q+1 and the
+  // face to +x of plane q-1 for the patch column (o*) and the slot (s*;
+  // two-point ring slots and corners use plane q only)
+  T oym, oyc, oyp, obm, obc, obp, orc, orp, ofb;
+  T sym = T(0), syc = T(0), syp = T(0), sbm = T(1), sbc = T(1), sbp = T(1), src = T(0), srp = T(0),
+    sfb = T(0);
   {
     const Raw m = load(ixs, oy, oz, o_grid, o_int), c = load(ixs + 1, oy, oz, o_grid, o_int),
               p = load(ixs + 2, oy, oz, o_grid, o_int);
@@ -1053,7 +1077,9 @@ __global__ void __launch_bounds__(TY* TZ)
     oyc = c.x + corr(pco, ixs + 1, o_int);
     oyp = p.x + corr(pco, ixs + 2, o_int);
     obm = cvt(m.a); obc = cvt(c.a); obp = cvt(p.a);
+    ofb = face(obm, obc);
     orc = c.b; orp = p.b;
+    if (SHARE) sa[oidx] = obc;
     if (s_on) {
       const Raw sm = load(ixs, sy, sz, s_grid, s_int), sc = load(ixs + 1, sy, sz, s_grid, s_int),
                 sp = load(ixs + 2, sy, sz, s_grid, s_int);
@@ -1061,12 +1087,20 @@ __global__ void __launch_bounds__(TY* TZ)
       syc = sc.x + corr(pcs, ixs + 1, s_int);
       syp = sp.x + corr(pcs, ixs + 2, s_int);
       sbm = cvt(sm.a); sbc = cvt(sc.a); sbp = cvt(sp.a);
+      sfb = face(sbm, sbc);
       src = sc.b; srp = sp.b;
+      if (SHARE) sa[sidx] = sbc;
     }
   }
+  if (SHARE) {
+    __syncthreads();
+    faces_yz(ixs + 1, oidx);
+    if (s_on) faces_yz(ixs + 1, sidx);
+    __syncthreads();
+  }
 
-  // patch column: x3 at q-2, q-1, b at q-1 and 1/a at q-2
-  T x3a = T(0), x3b = T(0), rm_ = T(0), obmm = T(1);
+  // patch column: x3 at q-2, q-1, b at q-1, 1/a and the face to +x of plane q-2
+  T x3a = T(0), x3b = T(0), rm_ = T(0), ofa = T(0), obmm = T(1);
   double dot = 0.0;
 
   for (int q = x0 - 1; q <= x1; ++q) {
@@ -1079,24 +1113,38 @@ __global__ void __launch_bounds__(TY* TZ)
       cnext = cload(chi + 1);
     }
 
-    T* __restrict__ b3 = sb[q % 3];
+    T* __restrict__ b3 = sb[SHARE ? 0 : q % 3];  // 1/a of plane q (without SHARE)
     s1[oidx] = oyc;
-    b3[oidx] = obc;
+    b3[oidx] = SHARE ? obp : obc;
     if (s_on) {
       s1[sidx] = syc;
-      b3[sidx] = sbc;
+      b3[sidx] = SHARE ? sbp : sbc;
     }
     __syncthreads();
     const T ocn = corr(pco, q + 2, o_int);
     const T scn = s_on ? corr(pcs, q + 2, s_int) : T(0);
+    faces_yz(q + 1, oidx);
+    if (s_on) faces_yz(q + 1, sidx);
 
     // x3 on plane q: patch and one-point ring
     const bool qin = q >= 1 && q <= n - 2;
+    const T* __restrict__ fyq = fy[SHARE ? q % 3 : 0];
+    const T* __restrict__ fzq = fz[SHARE ? q % 3 : 0];
+    // faces to -y, +y, -z, +z of LDS position idx (centre 1/a bv) on plane q
+    auto yz4 = [&](int idx, T bv, T& fym, T& fyp, T& fzm, T& fzp) {
+      if constexpr (SHARE) {
+        fym = fyq[idx - PZ]; fyp = fyq[idx]; fzm = fzq[idx - 1]; fzp = fzq[idx];
+      } else {
+        fym = face(bv, b3[idx - PZ]); fyp = face(bv, b3[idx + PZ]);
+        fzm = face(bv, b3[idx - 1]); fzp = face(bv, b3[idx + 1]);
+      }
+    };
+    const T ofc = face(obc, obp);
     T x3c = T(0);
     if (qin && o_int) {
-      const T fxm = face(obc, obm), fxp = face(obc, obp);
-      const T fym = face(obc, b3[oidx - PZ]), fyp = face(obc, b3[oidx + PZ]);
-      const T fzm = face(obc, b3[oidx - 1]), fzp = face(obc, b3[oidx + 1]);
+      const T fxm = ofb, fxp = ofc;
+      T fym, fyp, fzm, fzp;
+      yz4(oidx, obc, fym, fyp, fzm, fzp);
       const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
       const T off = ((fxm * oym + fxp * oyp) + (fym * s1[oidx - PZ] + fyp * s1[oidx + PZ])) +
                     (fzm * s1[oidx - 1] + fzp * s1[oidx + 1]);
@@ -1104,12 +1152,13 @@ __global__ void __launch_bounds__(TY* TZ)
     }
     T* __restrict__ x3s = s3[q & 1];
     x3s[oidx] = x3c;
+    const T sfc = face(sbc, sbp);
     if (ring1) {
       T v = T(0);
       if (qin && s_int) {
-        const T hxm = face(sbc, sbm), hxp = face(sbc, sbp);
-        const T hym = face(sbc, b3[sidx - PZ]), hyp = face(sbc, b3[sidx + PZ]);
-        const T hzm = face(sbc, b3[sidx - 1]), hzp = face(sbc, b3[sidx + 1]);
+        const T hxm = sfb, hxp = sfc;
+        T hym, hyp, hzm, hzp;
+        yz4(sidx, sbc, hym, hyp, hzm, hzp);
         const T hd = ((hxm + hxp) + (hym + hyp)) + (hzm + hzp);
         const T hoff = ((hxm * sym + hxp * syp) + (hym * s1[sidx - PZ] + hyp * s1[sidx + PZ])) +
                        (hzm * s1[sidx - 1] + hzp * s1[sidx + 1]);
@@ -1119,15 +1168,22 @@ __global__ void __launch_bounds__(TY* TZ)
     }
     __syncthreads();
 
-    // x4 on plane q-1 from x3 of planes q-2, q-1 (LDS with ring), q; the
-    // faces of plane q-1 are formed again from 1/a (registers and LDS)
+    // x4 on plane q-1 from x3 of planes q-2, q-1 (LDS with ring), q and the
+    // faces of plane q-1
     const int qr = q - 1;
     if (qr >= x0 && o_int) {
       const T* __restrict__ x3p = s3[qr & 1];
-      const T* __restrict__ bq = sb[qr % 3];
-      const T fxm = face(obm, obmm), fxp = face(obm, obc);
-      const T fym = face(obm, bq[oidx - PZ]), fyp = face(obm, bq[oidx + PZ]);
-      const T fzm = face(obm, bq[oidx - 1]), fzp = face(obm, bq[oidx + 1]);
+      const T fxm = ofa, fxp = ofb;
+      T fym, fyp, fzm, fzp;
+      if constexpr (SHARE) {
+        const T* __restrict__ fyr = fy[qr % 3];
+        const T* __restrict__ fzr = fz[qr % 3];
+        fym = fyr[oidx - PZ]; fyp = fyr[oidx]; fzm = fzr[oidx - 1]; fzp = fzr[oidx];
+      } else {
+        const T* __restrict__ bq = sb[qr % 3];
+        fym = face(obm, bq[oidx - PZ]); fyp = face(obm, bq[oidx + PZ]);
+        fzm = face(obm, bq[oidx - 1]); fzp = face(obm, bq[oidx + 1]);
+      }
       const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
       const T off = ((fxm * x3a + fxp * x3c) + (fym * x3p[oidx - PZ] + fyp * x3p[oidx + PZ])) +
                     (fzm * x3p[oidx - 1] + fzp * x3p[oidx + 1]);
@@ -1141,11 +1197,13 @@ __global__ void __launch_bounds__(TY* TZ)
     x3a = x3b;
     x3b = x3c;
     rm_ = orc;
+    ofa = ofb; ofb = ofc;
     obmm = obm;
     oym = oyc; oyc = oyp; oyp = on.x + ocn;
     obm = obc; obc = obp; obp = cvt(on.a);
     orc = orp; orp = on.b;
     if (s_on) {
+      sfb = sfc;
       sym = syc; syc = syp; syp = sn.x + scn;
       sbm = sbc; sbc = sbp; sbp = cvt(sn.a);
       src = srp; srp = sn.b;
