@@ -908,7 +908,13 @@ template bool march_pre2r<float>(const GridArgs&, const float*, const float*, fl
 // one-point ring, x4 on plane q - 1.  The coarse planes covering the
 // two-point ring's footprint sit in a four-plane LDS ring (TY/2 + 3 by
 // TZ/2 + 3 coarse points); every column forms its prolonged correction with
-// ProlongLds, two planes ahead of its use.
+// ProlongLds, two planes ahead of its use.  Every stencil column forms its
+// face to +x once and keeps the one to -x from the plane before.  In FP64
+// the faces to +y and +z are also formed once per position and plane, into
+// LDS (three plane slots, from 1/a stored one plane ahead), so both stencils
+// read their y and z faces instead of forming them; in FP32, whose
+// reciprocal is one instruction, they are formed from 1/a where used (a
+// three-plane 1/a ring), which measured faster.
 // ---------------------------------------------------------------------------
 template <typename T, int TY, int TZ, int CK>
 __global__ void __launch_bounds__(TY* TZ)

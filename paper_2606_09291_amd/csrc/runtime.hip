@@ -107,6 +107,7 @@ struct Plan {
   int dense_N = 0;
   void* arena = nullptr;
   size_t arena_bytes = 0;
+  uint64_t last_use = 0;   // plan-cache clock at the latest get_plan
 };
 
 }  // namespace
@@ -150,6 +151,7 @@ struct mlsgd_ctx {
   std::map<std::string, GraphEntry> graphs;
   int* d_flag = nullptr;
   std::map<std::string, std::unique_ptr<Plan>> plans;
+  uint64_t plan_clock = 0;
   std::map<int, double*> const_rhs;        // constant interior right-hand sides per grid
   long long* d_dst_off = nullptr;          // packed-output offsets of one solve batch
   size_t dst_off_len = 0;
@@ -230,6 +232,54 @@ struct Carver {
 };
 
 void plan_fields(mlsgd_ctx* c, Plan* P);
+void drop_graphs(mlsgd_ctx* c);
+
+// Plan cache bounds.  Layouts are kept per batch shape; beyond kMaxPlans
+// plans or kPlanBytes of arenas the least recently used one is freed (its
+// captured graphs with it), so a caller that meets ever new shapes -- the
+// adaptive batch controller's -- keeps a bounded footprint.
+constexpr size_t kMaxPlans = 8;
+constexpr size_t kPlanBytes = (size_t)96 << 30;
+
+// Free one allocation of dalloc (after the context's queued work, which may
+// still use it).
+void dfree(mlsgd_ctx* c, void* p) {
+  if (!p) return;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (size_t i = 0; i < c->allocs.size(); ++i)
+    if (c->allocs[i] == p) {
+      c->allocs[i] = c->allocs.back();
+      c->allocs.pop_back();
+      break;
+    }
+  HIPCHK(hipFree(p));
+}
+
+void free_plan(mlsgd_ctx* c, Plan* P) {
+  dfree(c, P->arena);
+  P->arena = nullptr;
+}
+
+void drop_plans(mlsgd_ctx* c) {
+  drop_graphs(c);   // captured graphs point into the plans' memory
+  for (auto& kv : c->plans) free_plan(c, kv.second.get());
+  c->plans.clear();
+}
+
+// Make room for a new plan of `need` arena bytes (not yet in the cache).
+void evict_plans(mlsgd_ctx* c, size_t need) {
+  for (;;) {
+    size_t total = 0;
+    for (const auto& kv : c->plans) total += kv.second->arena_bytes;
+    if (c->plans.empty() || (c->plans.size() < kMaxPlans && total + need <= kPlanBytes)) return;
+    auto lru = c->plans.begin();
+    for (auto it = c->plans.begin(); it != c->plans.end(); ++it)
+      if (it->second->last_use < lru->second->last_use) lru = it;
+    drop_graphs(c);
+    free_plan(c, lru->second.get());
+    c->plans.erase(lru);
+  }
+}
 
 // Build (or reuse) the layout for a list of blocks (grid sizes
 // non-increasing) and upload this call's draws; `fields` also regenerates
@@ -349,6 +399,7 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks, bool fields = tru
         P->ainv = cv.take<double>((size_t)P->sizes.back().rows * P->dense_N * P->dense_N);
       if (pass == 0) {
         P->arena_bytes = cv.off + 256;
+        evict_plans(c, P->arena_bytes);
         P->arena = dalloc(c, P->arena_bytes);
       }
     }
@@ -359,6 +410,7 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks, bool fields = tru
                           c->stream));
     c->plans[key] = std::move(up);
   }
+  P->last_use = ++c->plan_clock;
   // draws of this call
   int p = 0;
   for (const auto& b : blocks)
@@ -1138,12 +1190,18 @@ std::vector<LevelRows> level_rows(Plan* P, mlsgd_ctx* c, int L, const int64_t* M
   return out;
 }
 
+// Epilogue buffers grow to the largest estimate seen (the old buffer is
+// freed; captured graphs that point into it are dropped).
 void ensure_epi(mlsgd_ctx* c, size_t part_len, size_t dx_len) {
   if (part_len > c->epi_part_len) {
+    drop_graphs(c);
+    dfree(c, c->d_epi_part);
     c->d_epi_part = (double*)dalloc(c, sizeof(double) * part_len);
     c->epi_part_len = part_len;
   }
   if (dx_len > c->dxpart_len) {
+    drop_graphs(c);
+    dfree(c, c->d_dxpart);
     c->d_dxpart = (double*)dalloc(c, sizeof(double) * dx_len);
     c->dxpart_len = dx_len;
   }
@@ -1367,12 +1425,17 @@ int run_estimate_graph(mlsgd_ctx* c, const double* u, int L, const int64_t* M,
     c->graphs[key] = ge;
     return rc;
   }
-  mlsgd_ctx::GraphEntry& ge = it->second;
   check_u(c, u);
   hipStream_t s = c->stream;
+  // upload this call's draws; a plan or buffer change drops the graphs, and
+  // the shape then runs eagerly and is captured again
+  (void)estimate_prep(c, L, M, first, false);
+  it = c->graphs.find(key);
+  if (it == c->graphs.end() || !it->second.exec)
+    return run_estimate_eager(c, u, L, M, first, grad_out, J_out, st);
+  mlsgd_ctx::GraphEntry& ge = it->second;
   HIPCHK(hipMemcpyAsync(c->d_u_graph, u, sizeof(double) * cube(c->nfin), hipMemcpyDeviceToDevice,
                         s));
-  (void)estimate_prep(c, L, M, first, false);
   HIPCHK(hipEventRecord(c->ev[0], s));
   HIPCHK(hipGraphLaunch(ge.exec, s));
   HIPCHK(hipEventRecord(c->ev[1], s));
@@ -1662,8 +1725,7 @@ int mlsgd_set_tuning(mlsgd_ctx* c, const mlsgd_tuning* t) {
       c->cache32 = t->cache != 0;
     else
       c->cache64 = t->cache != 0;
-    drop_graphs(c);     // captured graphs point into the plans' memory
-    c->plans.clear();   // layouts depend on the tiling and the caches
+    drop_plans(c);      // layouts depend on the tiling and the caches
     return MLSGD_OK;
   });
 }
