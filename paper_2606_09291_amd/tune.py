@@ -18,7 +18,7 @@ import time
 
 def candidates(precision):
     cand = []
-    for deg, lo in itertools.product([2, 3, 4], [0.1, 0.25]):
+    for deg, lo in itertools.product([2, 3, 4], [0.1, 0.125, 0.15, 0.2, 0.25]):
         cand.append({"smoother": 2, "sweeps": deg, "cheb_lo": lo})
     cand.append({"smoother": 0, "sweeps": 2, "omega": 1.0})
     cand.append({"smoother": 1, "sweeps": 2, "omega": 1.0})
