@@ -189,3 +189,39 @@ def test_fused_smoothing_equals_separate_passes(mm, orc, monkeypatch, grid, M, p
         pb = orc.make_problem(grid, rtol=1e-13, **KW)
         go, _ = orc.mlmc_gradient(pb, None, u, yd, M, first=[2] * len(M))
         assert _rel(out[1][0], go) <= (1e-9 if precision == "fp64" else 1e-8)
+
+
+def test_largest_grids(mm, orc):
+    """The largest grids mlsgd_solve_sizes takes, solved to rtol 1e-10 (an
+    FP64 solve cannot reach 1e-12 there: its attainable relative residual
+    grows with the condition number of A, about h^-2, and is printed).
+    513^3 (pitch 528): the oracle applies its own operator, built from its own
+    vertex coefficients, to the unpacked solution, and the residual f - A y is
+    at most 2e-10 of f.  1025^3 (pitch 1040, about 110 GB of solver rows): the
+    solve converges and the library's FP64 true residual is within rtol."""
+    import torch
+    print("largest grids", flush=True)
+    for rtol in (1e-12, 1e-10):
+        ctx = mm.Context(mm.Problem(grid_n=[9, 17, 33, 65], y_d=inputs.target_sin(65), rtol=rtol),
+                         use_tuned=False)
+        ys, st = ctx.solve_sizes([513], level=6, first=4, f_value=1.0, allow_noconv=rtol < 1e-10)
+        print("513^3 at rtol", rtol, st, flush=True)
+        if rtol < 1e-10:
+            ctx.close()
+            continue
+        assert st["nonconverged"] == 0
+        y = ys[0].cpu().numpy()
+        del ys
+        n = 513
+        assert y[0].max() == 0 and y[:, -1].max() == 0 and y[:, :, 0].max() == 0
+        c = orc.kl_coeffs(0, 6, 4, 4, 1.0)
+        r = (1.0 - orc.apply(n, c, y))[1:-1, 1:-1, 1:-1]
+        rel = float(np.linalg.norm(r) / np.sqrt(r.size))
+        print("513^3 oracle residual / |f|", rel, flush=True)
+        assert rel <= 2e-10
+        del y, r
+        _, st = ctx.solve_sizes([1025], level=6, first=5, f_value=1.0, want_y=False)
+        print("1025^3", st, flush=True)
+        assert st["nonconverged"] == 0 and st["max_relres"] <= 1e-10
+        ctx.close()
+    torch.cuda.empty_cache()
