@@ -118,6 +118,22 @@ bool march_post2(const GridArgs& g, const T* xin, const T* xc, const T* b, T* xo
                  double omega_a, double omega_b, const int* poff, double* partial, int top_begin,
                  hipStream_t s);
 
+// The V-cycle from 9^3 down (9^3 -> 5^3 -> 3^3 and back) for `rows` problems
+// in one kernel: b9 rows in, z rows out (dense 9^3), Chebyshev steps om[0 ..
+// deg-1] (deg <= 8) down and reversed up, exact 3^3 solve, and partials of
+// <b, z> for the problems >= top_begin (partial nullable; one slot each).
+// c9, c5, c3: cached 1/a of the three grids (bfloat16 when cache_bf16).
+struct VsArgs {
+  double om[8];
+  int deg;
+  int top_begin;
+};
+constexpr int VS_MAXDEG = 8;
+template <typename T>
+void vcycle_small(int rows, const double* om, int deg, int top_begin, const CgScal* scal,
+                  const T* b9, const void* c9, const void* c5, const void* c3, int cache_bf16,
+                  T* xout, const int* poff, double* partial, hipStream_t s);
+
 // ---- batched grid transfers (rows of one grid size) ----
 template <typename T>
 void restrict_rows(int nf, int rows, int row0, const CgScal* scal, const T* fine,

@@ -1255,6 +1255,207 @@ template bool march_post2<double>(const GridArgs&, const double*, const double*,
 template bool march_post2<float>(const GridArgs&, const float*, const float*, const float*,
                                  float*, double, double, const int*, double*, int, hipStream_t);
 
+// ---------------------------------------------------------------------------
+// The V-cycle from a 9^3 grid down in one kernel: 9^3 -> 5^3 -> 3^3 and back
+// for every problem of the plan at once, with the level-by-level path's
+// smoothing steps (faces, summation order), transfers and exact 3^3 solve.
+// One workgroup per problem holds all three grids in LDS (right-hand sides,
+// two iterate buffers, reciprocal coefficients): one launch reads b and 1/a
+// and writes z, where the level-by-level cycle makes a dozen launches over
+// these small rows.  The last post-smoothing step forms <b, z> for the
+// problems whose top grid is 9^3 (one partial slot per problem).
+// ---------------------------------------------------------------------------
+template <typename T, int N>
+struct VsGrid {  // one grid of the small cycle in LDS (dense N^3, boundary zero)
+  static constexpr int M = N - 2, M3 = M * M * M, V = N * N * N;
+  __device__ static int vtx(int i) { return ((1 + i / (M * M)) * N + 1 + (i / M) % M) * N + 1 + i % M; }
+  // one damped Jacobi step x' = x + omega D^-1 (b - A x) (x_zero: x = 0);
+  // returns this thread's share of <b, x'>
+  __device__ static double jac(const T* x, T* xo, const T* b, const T* c, T omega, bool x_zero,
+                               T ih2) {
+    double dot = 0.0;
+    for (int i = threadIdx.x; i < M3; i += blockDim.x) {
+      const int v = vtx(i);
+      const T bc = c[v];
+      const T fxm = face(bc, c[v - N * N]), fxp = face(bc, c[v + N * N]);
+      const T fym = face(bc, c[v - N]), fyp = face(bc, c[v + N]);
+      const T fzm = face(bc, c[v - 1]), fzp = face(bc, c[v + 1]);
+      const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
+      T val;
+      if (x_zero) {
+        val = T(0) + omega * (b[v] - ih2 * (diag * T(0) - T(0))) * drcp(ih2 * diag);
+      } else {
+        const T off = ((fxm * x[v - N * N] + fxp * x[v + N * N]) + (fym * x[v - N] + fyp * x[v + N])) +
+                      (fzm * x[v - 1] + fzp * x[v + 1]);
+        val = x[v] + omega * (b[v] - ih2 * (diag * x[v] - off)) * drcp(ih2 * diag);
+      }
+      xo[v] = val;
+      dot += (double)b[v] * (double)val;
+    }
+    return dot;
+  }
+  __device__ static void resid(const T* x, const T* b, const T* c, T* r, T ih2) {
+    for (int i = threadIdx.x; i < M3; i += blockDim.x) {
+      const int v = vtx(i);
+      const T bc = c[v];
+      const T fxm = face(bc, c[v - N * N]), fxp = face(bc, c[v + N * N]);
+      const T fym = face(bc, c[v - N]), fyp = face(bc, c[v + N]);
+      const T fzm = face(bc, c[v - 1]), fzp = face(bc, c[v + 1]);
+      const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
+      const T off = ((fxm * x[v - N * N] + fxp * x[v + N * N]) + (fym * x[v - N] + fyp * x[v + N])) +
+                    (fzm * x[v - 1] + fzp * x[v + 1]);
+      r[v] = b[v] - ih2 * (diag * x[v] - off);
+    }
+  }
+  // full weighting of the fine residual r onto this (coarse) grid's b
+  __device__ static void restrict_from(const T* r, T* bc) {
+    constexpr int NF = 2 * (N - 1) + 1;
+    for (int i = threadIdx.x; i < M3; i += blockDim.x) {
+      const int jx = 1 + i / (M * M), jy = 1 + (i / M) % M, jz = 1 + i % M;
+      T acc = T(0);
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) {
+        const T wx = dx == 0 ? T(0.5) : T(0.25);
+        T ay = T(0);
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+          const T wy = dy == 0 ? T(0.5) : T(0.25);
+          const T* p = r + ((2 * jx + dx) * NF + (2 * jy + dy)) * NF + 2 * jz;
+          ay += wy * (T(0.25) * p[-1] + T(0.5) * p[0] + T(0.25) * p[1]);
+        }
+        acc += wx * ay;
+      }
+      bc[vtx(i)] = acc;
+    }
+  }
+  // x (this fine grid) += trilinear prolongation of the coarse xc
+  __device__ static void prolong_add(const T* xc, T* x) {
+    constexpr int NC = (N - 1) / 2 + 1;
+    for (int i = threadIdx.x; i < M3; i += blockDim.x) {
+      const int v = vtx(i);
+      const int ix = 1 + i / (M * M), iy = 1 + (i / M) % M, iz = 1 + i % M;
+      x[v] += prolong_val<T>(NC, xc, ix, iy, iz);
+    }
+  }
+};
+
+template <typename T, int CK>
+__global__ void __launch_bounds__(256)
+    k_vsmall(VsArgs va, const CgScal* __restrict__ scal, const T* __restrict__ b9,
+             const void* __restrict__ c9, const void* __restrict__ c5,
+             const void* __restrict__ c3, T* __restrict__ xout, const int* __restrict__ poff,
+             double* __restrict__ partial) {
+  using CR = typename std::conditional<CK == 2, uint16_t, T>::type;
+  using G9 = VsGrid<T, 9>;
+  using G5 = VsGrid<T, 5>;
+  using G3 = VsGrid<T, 3>;
+  __shared__ T sb9[729], sx9[2][729], sc9[729];
+  __shared__ T sb5[125], sx5[2][125], sc5[125];
+  __shared__ T sb3[27], sx3[27], sc3[27];
+  __shared__ double sred[4];
+  const int prob = blockIdx.x;
+  if (scal && !scal[prob].active) return;  // uniform per workgroup
+  const int tid = threadIdx.x;
+  auto cvt = [&](CR v) -> T {
+    if constexpr (CK == 2)
+      return (T)from_bf16(v);
+    else
+      return v;
+  };
+  const CR* C9 = (const CR*)c9 + (size_t)prob * 729;
+  const CR* C5 = (const CR*)c5 + (size_t)prob * 125;
+  const CR* C3 = (const CR*)c3 + (size_t)prob * 27;
+  for (int v = tid; v < 729; v += 256) {
+    sb9[v] = b9[(size_t)prob * 729 + v];
+    sc9[v] = cvt(C9[v]);
+    sx9[0][v] = T(0);
+    sx9[1][v] = T(0);
+  }
+  for (int v = tid; v < 125; v += 256) {
+    sc5[v] = cvt(C5[v]);
+    sb5[v] = T(0);
+    sx5[0][v] = T(0);
+    sx5[1][v] = T(0);
+  }
+  if (tid < 27) {
+    sc3[tid] = cvt(C3[tid]);
+    sb3[tid] = T(0);
+    sx3[tid] = T(0);
+  }
+  __syncthreads();
+  const T ih9 = T(64), ih5 = T(16), ih3 = T(4);
+  const int deg = va.deg;
+  // pre-smoothing from zero and residual on 9^3, restriction to 5^3
+  int c9c = 0;
+  for (int j = 0; j < deg; ++j) {
+    G9::jac(sx9[c9c], sx9[c9c ^ 1], sb9, sc9, (T)va.om[j], j == 0, ih9);
+    c9c ^= 1;
+    __syncthreads();
+  }
+  G9::resid(sx9[c9c], sb9, sc9, sx9[c9c ^ 1], ih9);
+  __syncthreads();
+  G5::restrict_from(sx9[c9c ^ 1], sb5);
+  __syncthreads();
+  // the same on 5^3, restriction to 3^3
+  int c5c = 0;
+  for (int j = 0; j < deg; ++j) {
+    G5::jac(sx5[c5c], sx5[c5c ^ 1], sb5, sc5, (T)va.om[j], j == 0, ih5);
+    c5c ^= 1;
+    __syncthreads();
+  }
+  G5::resid(sx5[c5c], sb5, sc5, sx5[c5c ^ 1], ih5);
+  __syncthreads();
+  G3::restrict_from(sx5[c5c ^ 1], sb3);
+  __syncthreads();
+  // exact solve of the single 3^3 unknown
+  G3::jac(sx3, sx3, sb3, sc3, T(1), true, ih3);
+  __syncthreads();
+  // up: correction and post-smoothing on 5^3, then on 9^3
+  G5::prolong_add(sx3, sx5[c5c]);
+  __syncthreads();
+  for (int j = 0; j < deg; ++j) {
+    G5::jac(sx5[c5c], sx5[c5c ^ 1], sb5, sc5, (T)va.om[deg - 1 - j], false, ih5);
+    c5c ^= 1;
+    __syncthreads();
+  }
+  G9::prolong_add(sx5[c5c], sx9[c9c]);
+  __syncthreads();
+  double dot = 0.0;
+  for (int j = 0; j < deg; ++j) {
+    dot = G9::jac(sx9[c9c], sx9[c9c ^ 1], sb9, sc9, (T)va.om[deg - 1 - j], false, ih9);
+    c9c ^= 1;
+    __syncthreads();
+  }
+  for (int v = tid; v < 729; v += 256) xout[(size_t)prob * 729 + v] = sx9[c9c][v];
+  if (partial != nullptr && prob >= va.top_begin) {
+    const double s = block_sum<256>(dot, sred);
+    if (tid == 0) partial[poff[prob]] = s;
+  }
+}
+
+template <typename T>
+void vcycle_small(int rows, const double* om, int deg, int top_begin, const CgScal* scal,
+                  const T* b9, const void* c9, const void* c5, const void* c3, int cache_bf16,
+                  T* xout, const int* poff, double* partial, hipStream_t s) {
+  if (rows <= 0) return;
+  VsArgs va{};
+  for (int j = 0; j < deg && j < VS_MAXDEG; ++j) va.om[j] = om[j];
+  va.deg = deg;
+  va.top_begin = top_begin;
+  if (sizeof(T) == 4 && cache_bf16)
+    hipLaunchKernelGGL((k_vsmall<T, 2>), dim3(rows), dim3(256), 0, s, va, scal, b9, c9, c5, c3,
+                       xout, poff, partial);
+  else
+    hipLaunchKernelGGL((k_vsmall<T, 1>), dim3(rows), dim3(256), 0, s, va, scal, b9, c9, c5, c3,
+                       xout, poff, partial);
+}
+template void vcycle_small<double>(int, const double*, int, int, const CgScal*, const double*,
+                                   const void*, const void*, const void*, int, double*, const int*,
+                                   double*, hipStream_t);
+template void vcycle_small<float>(int, const double*, int, int, const CgScal*, const float*,
+                                  const void*, const void*, const void*, int, float*, const int*,
+                                  double*, hipStream_t);
+
 // Reciprocal diagonal drcp(h^-2 ((fxm + fxp) + (fym + fyp)) + (fzm + fzp)) of
 // every interior vertex, with the faces and the summation order of k_march,
 // so the first smoothing step formed from it equals the one k_march forms.

@@ -181,6 +181,7 @@ struct mlsgd_ctx {
   int xchunk = 32;          // x planes per workgroup
   bool pre2r = true;        // fused pre-smoothing and residual pass where it applies
   bool post2 = true;        // fused two-step post-smoothing pass where it applies
+  bool vsmall = true;       // the cycle from 9^3 down as one kernel where it applies
   // event timing of the smoothing passes on one grid size (roofline figures)
   struct Timing {
     bool on = false;
@@ -669,11 +670,31 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
   auto args = [&](SizeLvl& L) {
     return sizeof(T) == 8 ? args_size(c, P, L) : args_size32(c, P, L);
   };
+  // the levels from 9^3 down run as one LDS-resident kernel where the
+  // hierarchy ends 9^3, 5^3, 3^3 with cached coefficients and every problem
+  // on 5^3 and 3^3 comes down from 9^3 (none has its top grid there)
+  int ks = S;
+  if (c->vsmall && S >= 3 && !P->ainv && P->sizes[S - 3].n == 9 && P->sizes[S - 2].n == 5 &&
+      P->sizes[S - 1].n == 3 && (int)om.size() <= VS_MAXDEG &&
+      P->sizes[S - 2].top_begin == P->sizes[S - 2].rows &&
+      P->sizes[S - 1].top_begin == P->sizes[S - 1].rows &&
+      P->sizes[S - 2].rows == P->sizes[S - 3].rows) {
+    const GridArgs g9 = args(P->sizes[S - 3]), g5 = args(P->sizes[S - 2]),
+                   g3 = args(P->sizes[S - 1]);
+    if (g9.cache && g5.cache && g3.cache) ks = S - 3;
+  }
   for (int k = 0; k < S; ++k) {
     SizeLvl& L = P->sizes[k];
     MgView<T> v = mg_view<T>(L);
     T* A[2] = {v.X, v.R};
     GridArgs g = args(L);
+    if (k == ks) {
+      const GridArgs g5 = args(P->sizes[k + 1]), g3 = args(P->sizes[k + 2]);
+      vcycle_small<T>(L.rows, om.data(), deg, L.top_begin, P->d_scal, v.B, g.cache, g5.cache,
+                      g3.cache, g.cache_bf16, A[0], P->d_poff, P->d_partial, c->stream);
+      L.cur = 0;
+      break;
+    }
     if (k == S - 1) {
       if (P->ainv) {
         dense_apply<T>(L.n, L.rows, P->d_scal, P->ainv, v.B, A[0], c->stream);
@@ -719,7 +740,8 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
                      c->stream);
     L.cur = cur;
   }
-  for (int k = S - 2; k >= 0; --k) {
+  // up from the level above the coarsest one handled (the small cycle's 9^3, or S - 1)
+  for (int k = (ks < S ? ks : S - 1) - 1; k >= 0; --k) {
     SizeLvl& L = P->sizes[k];
     MgView<T> v = mg_view<T>(L);
     T* A[2] = {v.X, v.R};
@@ -1608,6 +1630,7 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     if (const char* e = getenv("MLSGD_XCHUNK")) c->xchunk = atoi(e);
     if (const char* e = getenv("MLSGD_PRE2R")) c->pre2r = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_POST2")) c->post2 = atoi(e) != 0;
+    if (const char* e = getenv("MLSGD_VSMALL")) c->vsmall = atoi(e) != 0;
     c->nfin = pb->grid_n[pb->n_levels - 1];
     const size_t NF = cube(c->nfin);
     c->d_f = (double*)dalloc(c.get(), sizeof(double) * NF);

@@ -144,6 +144,8 @@ def test_padded_state_adjoint_outputs(mm, orc):
 
 
 @pytest.mark.parametrize("grid,M,precision,tuning", [
+    ([9, 17, 33], [16, 8, 4], "fp64", {}),
+    ([9, 17, 33], [16, 8, 4], "mixed", {}),
     ([17, 33, 65], [8, 4, 3], "fp64", {}),
     ([17, 33, 65], [8, 4, 3], "mixed", {}),
     ([17, 33, 65], [8, 4, 3], "bf16", {}),
@@ -151,12 +153,14 @@ def test_padded_state_adjoint_outputs(mm, orc):
     (GRID, M, "fp64", {"tile_y": 16, "xchunk": 40}),
     (GRID, M, "mixed", {"tile_y": 8, "xchunk": 24}),
 ])
-def test_fused_smoothing_equals_separate_passes(mm, orc, monkeypatch, grid, M, precision, tuning):
-    """The one-pass pre-smoothing with its residual and the one-pass
-    post-smoothing (64-wide tiles) compute what the separate passes compute
-    (two-step pass and residual pass; step with the folded coarse-grid
-    correction and plain step), with the same faces, neighbours and summation
-    order; only the compiler's fused multiply-adds may differ.  Whole estimates then agree to rounding (a wrong
+def test_fused_passes_equal_level_by_level_passes(mm, orc, monkeypatch, grid, M, precision, tuning):
+    """The one-pass pre-smoothing with its residual, the one-pass
+    post-smoothing, and the one-kernel cycle from 9^3 down compute what the
+    level-by-level passes compute (two-step pass and residual pass; step with
+    the folded coarse-grid correction and plain step; every step, transfer
+    and coarse solve below 17^3), with the same faces, neighbours and
+    summation order; only the compiler's fused multiply-adds and the
+    association of the trilinear prolongation may differ.  Whole estimates then agree to rounding (a wrong
     neighbour or plane would change the preconditioner and move the Krylov
     iterates, and the result, by about the solver tolerance) with identical
     iteration counts, and both match the oracle."""
@@ -169,6 +173,7 @@ def test_fused_smoothing_equals_separate_passes(mm, orc, monkeypatch, grid, M, p
     for flag in ("0", "1"):
         monkeypatch.setenv("MLSGD_PRE2R", flag)
         monkeypatch.setenv("MLSGD_POST2", flag)
+        monkeypatch.setenv("MLSGD_VSMALL", flag)
         ctx = mm.Context(mm.Problem(grid_n=grid, y_d=yd, rtol=1e-12, precision=prec, **KW),
                          use_tuned=False)
         if tuning:
