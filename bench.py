@@ -85,7 +85,7 @@ def make_ctx(m, w, dev):
     return m.Context(pb, device=dev)
 
 
-def run(args, m, w, dev, steps, warmup, timing_n=None, graph=False, timing_kind=2):
+def run(args, m, w, dev, steps, warmup, timing_n=None, graph=False, timing_kind=2, u0=None):
     """Warm up, then time `steps` estimates with fresh samples each.  graph:
     the first warm-up call captures the batch shape as a HIP graph and every
     later call replays it (no event timing then).  timing_kind selects the
@@ -97,7 +97,7 @@ def run(args, m, w, dev, steps, warmup, timing_n=None, graph=False, timing_kind=
         ctx.set_graph(True)
         timing_n = None
         warmup = max(warmup, 1)
-    u = torch.as_tensor(w.u0(), device=dev).contiguous()
+    u = torch.as_tensor(w.u0() if u0 is None else u0, device=dev).contiguous()
     L = len(w.grid_n)
     off = [0] * L
     for k in range(warmup):
@@ -522,10 +522,14 @@ def main():
         wp = inputs.WORKLOADS["paper_law_65"]
         log(args, "Sec. 5 law workload")
         kp = max(2, args.steps)
-        rp = run(args, m, wp, dev, kp, 1)
+        # at the initial control u = 0 every state solve is trivial; time the
+        # estimate at a control away from it so both solves iterate
+        up0 = inputs.control_xyz(wp.grid_n[-1]) + 3.0 * wp.y_d()
+        rp = run(args, m, wp, dev, kp, 1, u0=up0)
         sp, up = problem_counts(wp.grid_n, wp.M)
         vp = kp / rp["dt"]
-        out["paper_law"] = {"workload": wp.name, "value": vp, "unit": "gradient estimates/s",
+        out["paper_law"] = {"workload": wp.name + ", control 0.1xyz + 3 y_d",
+                            "value": vp, "unit": "gradient estimates/s",
                             "ms_per_step": 1e3 / vp, "solves_per_s": sp * vp,
                             "iters_state": max(x["iters_state"] for x in rp["stats"]),
                             "iters_adjoint": max(x["iters_adjoint"] for x in rp["stats"])}
