@@ -48,6 +48,8 @@ struct CgScal {
   double alpha, beta;
   int active;     // 1 while the problem iterates
   int iters;
+  int pending;    // x += alpha p of the last step not yet applied
+  int pbuf;       // which of the two direction buffers holds that p
 };
 
 // Arguments common to every launch over one grid size.
@@ -70,9 +72,12 @@ struct GridArgs {
 // ---- stencil kernels (marching LDS tiles, coefficient regenerated) ----
 template <typename T>
 void march_resid(const GridArgs& g, const T* x, const T* b, T* r, hipStream_t s);
+// p_new = z + beta p_old, q = A p_new, <p_new, q>; with x non-null also the
+// step of the previous iteration, x += alpha p_old (alpha still in the
+// problem's scalars), which the update then leaves out
 template <typename T, typename TZ>
 void march_matvec(const GridArgs& g, const TZ* z, const T* p_old, T* p_new, T* q,
-                  const int* poff, double* partial, hipStream_t s);
+                  const int* poff, double* partial, hipStream_t s, T* x = nullptr);
 template <typename T>
 void march_gs(const GridArgs& g, T* x, const T* b, int color, int x_zero,
               const int* poff, double* partial, int top_begin, double omega, hipStream_t s);
@@ -176,6 +181,13 @@ void group_dot(const GridArgs& g, const double* a, const double* b, const int* p
 void group_update(const GridArgs& g, double* x, const double* p, double* r,
                   const double* q, const int* poff, double* partial, float* r32,
                   hipStream_t s);
+// r -= alpha q and <r, r> (x is updated by the next matvec or group_xflush)
+void group_rupdate(const GridArgs& g, double* r, const double* q, const int* poff,
+                   double* partial, float* r32, hipStream_t s);
+// x += alpha p for every problem with a pending step, p from buffer p0 or p1
+// as its scalars record (g.scal must be set; active or not)
+void group_xflush(const GridArgs& g, double* x, const double* p0, const double* p1,
+                  hipStream_t s);
 // b = y - y_d on the interior (y_d dense), y reset to 0, partials of |b|^2
 void group_misfit(const GridArgs& g, double* y, const double* yd, double* b_rows,
                   const int* poff, double* partial, hipStream_t s);
@@ -185,15 +197,15 @@ enum ScalPhase {
   PH_INIT_BB = 0,    // bb = rr = sum; active = bb > 0; iters = 0
   PH_RZ0 = 1,        // rz = sum; beta = 0
   PH_RZ0_RR = 2,     // unpreconditioned start: rz = rr; beta = 0
-  PH_ALPHA = 3,      // pq = sum; alpha = rz / pq
+  PH_ALPHA = 3,      // pq = sum; alpha = rz / pq; x += alpha p pending, p in buffer aux
   PH_RR = 4,         // rr = sum; ++iters; converged or out of iterations -> inactive
   PH_RZ = 5,         // rz_new = sum; beta = rz_new / rz; rz = rz_new
   PH_RZ_RR = 6,      // unpreconditioned: rz_new = rr
-  PH_TRUE = 7,       // rr = sum (true residual); active = rr > rtol^2 bb
+  PH_TRUE = 7,       // rr = sum (true residual); active = rr > rtol^2 bb; nothing pending
 };
 void cg_scalar(int phase, CgScal* scal, int nprob, const int* poff, const int* pcnt,
                const double* partial, double rtol, int max_iters, int* active_count,
-               hipStream_t s);
+               hipStream_t s, int aux = 0);
 void scal_to_stats(const CgScal* scal, int nprob, double rtol, int* iters_max,
                    int* nonconv, double* relres_max, hipStream_t s);
 void sum_partials(int nprob, const int* poff, const int* pcnt, const double* partial,

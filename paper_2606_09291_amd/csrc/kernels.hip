@@ -115,7 +115,9 @@ Tiling make_tiling(int n, int tile_y, int xchunk) {
 // from the per-estimate cache of 1/a written by k_coef_cache (CACHED).
 //
 // OP_RESID : r = b - A x
-// OP_MATVEC: p = z + beta p (on the fly, halo included), q = A p, <p, q>
+// OP_MATVEC: p = z + beta p (on the fly, halo included), q = A p, <p, q>;
+//            with xdef non-null also xdef += alpha p_old, the previous
+//            iteration's step of the iterate (alpha still in the scalars)
 // OP_GS    : one colour of a red-black Gauss-Seidel sweep in place with
 //            relaxation omega (x_zero: start from x = 0; partial: <b, x>)
 // OP_JAC   : one damped Jacobi step out of place, x' = x + omega D^-1 (b - A x)
@@ -202,7 +204,7 @@ template <typename T, typename TI, int TY, int TZ, int OP, int CK>
 __global__ void __launch_bounds__(TY* TZ)
     k_march(GridArgs g, const TI* in, const T* in2, const T* rhs, T* out, T* out2,
             const int* __restrict__ poff, double* __restrict__ partial, int color,
-            int x_zero, int top_begin, T omega) {
+            int x_zero, int top_begin, T omega, T* __restrict__ xdef) {
   constexpr bool CACHED = CK != 0;   // 0: regenerate, 1: cache of type T, 2: bfloat16 cache
   constexpr int NT = TY * TZ;
   constexpr int PZ = TZ + 2;
@@ -267,6 +269,8 @@ __global__ void __launch_bounds__(TY* TZ)
 
   T beta = T(0);
   if (OP == OP_MATVEC) beta = (T)g.scal[prob].beta;
+  const bool XD = OP == OP_MATVEC && xdef != nullptr;
+  const T alpha_prev = XD ? (T)g.scal[prob].alpha : T(0);
   const T omega1 = (T)g.omega1;
 
   const int x0 = 1 + xc * g.t.xchunk;
@@ -439,6 +443,12 @@ __global__ void __launch_bounds__(TY* TZ)
       (OP == OP_RESID || OP == OP_GS || OP == OP_JAC || OP == OP_JACP || OP == OP_JAC2Z);
   T bv = T(0);
   if (USES_B && own) bv = rhs[base + ((size_t)x0 * n + iy) * LP + iz + LO];
+  // deferred step: the iterate one plane ahead, the old direction as loaded
+  T xv = T(0), pold = T(0);
+  if (OP == OP_MATVEC) {
+    pold = xcr.c;
+    if (XD && own) xv = xdef[base + ((size_t)x0 * n + iy) * LP + iz + LO];
+  }
   double dot = 0.0;
   const int cidx = (ly + 1) * PZ + (lz + 1);
   const int hidx = hly * PZ + hlz;
@@ -460,6 +470,8 @@ __global__ void __launch_bounds__(TY* TZ)
       hbnn = coefr(ix + 2, hy, hz, Sh);
     }
     if (USES_B && own && ix + 1 < x1) bvn = __builtin_nontemporal_load(&rhs[base + ((size_t)(ix + 1) * n + iy) * LP + iz + LO]);
+    T xvn = T(0);
+    if (XD && own && ix + 1 < x1) xvn = xdef[base + ((size_t)(ix + 1) * n + iy) * LP + iz + LO];
     if (OP == OP_JACP && ((ix + 3) >> 1) > chi) {
       ++chi;
       cstore(chi, cnext);
@@ -496,6 +508,7 @@ __global__ void __launch_bounds__(TY* TZ)
         const T q = own ? ih2 * (diag * xcur - off) : T(0);
         __builtin_nontemporal_store(q, &out[idx]);
         __builtin_nontemporal_store(xcur, &out2[idx]);
+        if (XD) __builtin_nontemporal_store(own ? xv + alpha_prev * pold : T(0), &xdef[idx]);
         dot += (double)xcur * (double)q;
       } else if (OP == OP_JAC || OP == OP_JACP || OP == OP_JAC2Z) {
         const T v = xcur + omega * (bv - ih2 * (diag * xcur - off)) * drcp(ih2 * diag);
@@ -521,6 +534,10 @@ __global__ void __launch_bounds__(TY* TZ)
     }
     xm = xcur;
     xcur = xp;
+    if (OP == OP_MATVEC) {
+      pold = xn.c;
+      xv = xvn;
+    }
     xn = xnn;
     bm = bc;
     bc = bp;
@@ -544,11 +561,12 @@ __global__ void __launch_bounds__(TY* TZ)
 template <typename T, typename TI, int OP, int CK>
 static void launch_march2(const GridArgs& g, const TI* in, const T* in2, const T* rhs, T* out,
                           T* out2, const int* poff, double* partial, int color, int x_zero,
-                          int top_begin, T omega, hipStream_t s) {
+                          int top_begin, T omega, hipStream_t s, T* xdef) {
   const int nblk = g.rows * g.t.tiles_per_row;
 #define MLSGD_LAUNCH(TY_, TZ_)                                                              \
   hipLaunchKernelGGL((k_march<T, TI, TY_, TZ_, OP, CK>), dim3(nblk), dim3(TY_ * TZ_), 0, s, \
-                     g, in, in2, rhs, out, out2, poff, partial, color, x_zero, top_begin, omega)
+                     g, in, in2, rhs, out, out2, poff, partial, color, x_zero, top_begin, omega, \
+                     xdef)
   if (g.t.TZ == 8) {
     MLSGD_LAUNCH(8, 8);
   } else if (g.t.TZ == 16) {
@@ -568,17 +586,17 @@ static void launch_march2(const GridArgs& g, const TI* in, const T* in2, const T
 template <typename T, typename TI, int OP>
 static void launch_march(const GridArgs& g, const TI* in, const T* in2, const T* rhs, T* out,
                          T* out2, const int* poff, double* partial, int color, int x_zero,
-                         int top_begin, T omega, hipStream_t s) {
+                         int top_begin, T omega, hipStream_t s, T* xdef = nullptr) {
   if (g.rows <= 0) return;
   if (!g.cache)
     launch_march2<T, TI, OP, 0>(g, in, in2, rhs, out, out2, poff, partial, color, x_zero,
-                                top_begin, omega, s);
+                                top_begin, omega, s, xdef);
   else if (sizeof(T) == 4 && g.cache_bf16)
     launch_march2<T, TI, OP, 2>(g, in, in2, rhs, out, out2, poff, partial, color, x_zero,
-                                top_begin, omega, s);
+                                top_begin, omega, s, xdef);
   else
     launch_march2<T, TI, OP, 1>(g, in, in2, rhs, out, out2, poff, partial, color, x_zero,
-                                top_begin, omega, s);
+                                top_begin, omega, s, xdef);
 }
 
 template <typename T>
@@ -587,8 +605,9 @@ void march_resid(const GridArgs& g, const T* x, const T* b, T* r, hipStream_t s)
 }
 template <typename T, typename TZ>
 void march_matvec(const GridArgs& g, const TZ* z, const T* p_old, T* p_new, T* q,
-                  const int* poff, double* partial, hipStream_t s) {
-  launch_march<T, TZ, OP_MATVEC>(g, z, p_old, nullptr, q, p_new, poff, partial, 0, 0, 0, T(1), s);
+                  const int* poff, double* partial, hipStream_t s, T* x) {
+  launch_march<T, TZ, OP_MATVEC>(g, z, p_old, nullptr, q, p_new, poff, partial, 0, 0, 0, T(1), s,
+                                 x);
 }
 template <typename T>
 void march_gs(const GridArgs& g, T* x, const T* b, int color, int x_zero, const int* poff,
@@ -601,9 +620,10 @@ template void march_resid<double>(const GridArgs&, const double*, const double*,
 template void march_resid<float>(const GridArgs&, const float*, const float*, float*,
                                  hipStream_t);
 template void march_matvec<double, double>(const GridArgs&, const double*, const double*,
-                                           double*, double*, const int*, double*, hipStream_t);
+                                           double*, double*, const int*, double*, hipStream_t,
+                                           double*);
 template void march_matvec<double, float>(const GridArgs&, const float*, const double*, double*,
-                                          double*, const int*, double*, hipStream_t);
+                                          double*, const int*, double*, hipStream_t, double*);
 template void march_gs<double>(const GridArgs&, double*, const double*, int, int, const int*,
                                double*, int, double, hipStream_t);
 template void march_gs<float>(const GridArgs&, float*, const float*, int, int, const int*,
@@ -1263,7 +1283,9 @@ template bool march_post2<float>(const GridArgs&, const float*, const float*, co
 // two iterate buffers, reciprocal coefficients): one launch reads b and 1/a
 // and writes z, where the level-by-level cycle makes a dozen launches over
 // these small rows.  The last post-smoothing step forms <b, z> for the
-// problems whose top grid is 9^3 (one partial slot per problem).
+// problems whose top grid is 9^3 (one partial slot per problem).  As for
+// every grid size, row r of the 9^3, 5^3 and 3^3 rows is problem r, so the
+// workgroup index serves as both.
 // ---------------------------------------------------------------------------
 template <typename T, int N>
 struct VsGrid {  // one grid of the small cycle in LDS (dense N^3, boundary zero)
@@ -2290,7 +2312,7 @@ void rows_zero(long long count, double* x, hipStream_t s) {
   hipLaunchKernelGGL(k_zero, dim3(grid_for(count, 256)), dim3(256), 0, s, count, x);
 }
 
-enum GroupOp { G_DOT = 0, G_UPDATE = 1, G_MISFIT = 2 };
+enum GroupOp { G_DOT = 0, G_UPDATE = 1, G_MISFIT = 2, G_RUPDATE = 3, G_XFLUSH = 4 };
 
 // Elementwise step of one group op at solver-row element k (interior vertex
 // (ix, iy, iz)); returns the term of the workgroup's partial sum.
@@ -2301,8 +2323,12 @@ __device__ __forceinline__ double group_elem(size_t k, int n, int ix, int iy, in
                                              const double* __restrict__ d,
                                              float* __restrict__ cf) {
   if (OP == G_DOT) return a[k] * b[k];
-  if (OP == G_UPDATE) {
+  if (OP == G_XFLUSH) {
     a[k] = a[k] + al * b[k];
+    return 0.0;
+  }
+  if (OP == G_UPDATE || OP == G_RUPDATE) {
+    if (OP == G_UPDATE) a[k] = a[k] + al * b[k];
     const double r = c[k] - al * d[k];
     c[k] = r;
     if (cf) cf[k] = (float)r;
@@ -2320,6 +2346,11 @@ __device__ __forceinline__ double group_elem(size_t k, int n, int ix, int iy, in
 //   G_DOT    : <a, b>
 //   G_UPDATE : a += alpha b (x += alpha p), c -= alpha d (r -= alpha q),
 //              <c, c>; cf (nullable) receives c in FP32
+//   G_RUPDATE: G_UPDATE without a (the matvec applies x's step one
+//              iteration later)
+//   G_XFLUSH : a += alpha b, b being d where the scalars say the pending
+//              step's direction is in the second buffer; every problem with
+//              a pending step, active or not; no partial sums
 //   G_MISFIT : c = a - y_d (b: dense y_d, shared), a = 0, <c, c>
 // Only interior vertices are visited: boundary vertices and padding of these
 // rows hold zeros that every op leaves unchanged.  On grids of 65 and more
@@ -2343,10 +2374,18 @@ __global__ void __launch_bounds__(256)
   const int row = blockIdx.x / tpr;
   const int tile = blockIdx.x - row * tpr;
   const int prob = g.row0 + row;
-  if (g.scal && !g.scal[prob].active) return;
+  if (OP == G_XFLUSH) {
+    if (!g.scal[prob].pending) return;  // uniform per workgroup
+  } else if (g.scal && !g.scal[prob].active) {
+    return;
+  }
   const int n = g.n, m = n - 2;
   const size_t base = (size_t)row * (size_t)g.stride;
-  const double al = OP == G_UPDATE ? g.scal[prob].alpha : 0.0;
+  constexpr bool STEP = OP == G_UPDATE || OP == G_RUPDATE || OP == G_XFLUSH;
+  constexpr bool LOAD_AB = OP == G_DOT || OP == G_UPDATE || OP == G_XFLUSH;
+  constexpr bool LOAD_CD = OP == G_UPDATE || OP == G_RUPDATE;
+  const double al = STEP ? g.scal[prob].alpha : 0.0;
+  if (OP == G_XFLUSH && g.scal[prob].pbuf) b = d;
   double acc = 0.0;
   if constexpr (NZ >= 0) {
     const int lp = lay_pitch(n), lo = lay_off(n);
@@ -2371,9 +2410,11 @@ __global__ void __launch_bounds__(256)
             ok[u][j] = ll < l1 && iz <= m + 1;
             k[u][j] = lb + iz;
             if (ok[u][j]) {
-              va[u][j] = a[k[u][j]];
-              vb[u][j] = b[k[u][j]];
-              if (OP == G_UPDATE) {
+              if (LOAD_AB) {
+                va[u][j] = a[k[u][j]];
+                vb[u][j] = b[k[u][j]];
+              }
+              if (LOAD_CD) {
                 vc[u][j] = c[k[u][j]];
                 vd[u][j] = d[k[u][j]];
               }
@@ -2387,8 +2428,10 @@ __global__ void __launch_bounds__(256)
             if (!ok[u][j]) continue;
             if (OP == G_DOT) {
               acc += va[u][j] * vb[u][j];
-            } else {
+            } else if (OP == G_XFLUSH) {
               a[k[u][j]] = va[u][j] + al * vb[u][j];
+            } else {
+              if (OP == G_UPDATE) a[k[u][j]] = va[u][j] + al * vb[u][j];
               const double r = vc[u][j] - al * vd[u][j];
               c[k[u][j]] = r;
               if (cf) cf[k[u][j]] = (float)r;
@@ -2424,9 +2467,11 @@ __global__ void __launch_bounds__(256)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
           const size_t k = base + i + u * 256;
-          va[u] = a[k];
-          vb[u] = b[k];
-          if (OP == G_UPDATE) {
+          if (LOAD_AB) {
+            va[u] = a[k];
+            vb[u] = b[k];
+          }
+          if (LOAD_CD) {
             vc[u] = c[k];
             vd[u] = d[k];
           }
@@ -2436,8 +2481,10 @@ __global__ void __launch_bounds__(256)
           const size_t k = base + i + u * 256;
           if (OP == G_DOT) {
             acc += va[u] * vb[u];
-          } else {
+          } else if (OP == G_XFLUSH) {
             a[k] = va[u] + al * vb[u];
+          } else {
+            if (OP == G_UPDATE) a[k] = va[u] + al * vb[u];
             const double r = vc[u] - al * vd[u];
             c[k] = r;
             if (cf) cf[k] = (float)r;
@@ -2448,8 +2495,10 @@ __global__ void __launch_bounds__(256)
       for (; i < hi; i += 256) acc += group_elem<OP>(base + i, n, 0, 0, 0, al, a, b, c, d, cf);
     }
   }
-  const double sum = block_sum<256>(acc, sred);
-  if (threadIdx.x == 0) partial[poff[prob] + tile] = sum;
+  if constexpr (OP != G_XFLUSH) {
+    const double sum = block_sum<256>(acc, sred);
+    if (threadIdx.x == 0) partial[poff[prob] + tile] = sum;
+  }
 }
 
 template <int OP>
@@ -2483,6 +2532,14 @@ void group_misfit(const GridArgs& g, double* y, const double* yd, double* b_rows
                   const int* poff, double* partial, hipStream_t s) {
   launch_group<G_MISFIT>(g, y, yd, b_rows, nullptr, poff, partial, nullptr, s);
 }
+void group_rupdate(const GridArgs& g, double* r, const double* q, const int* poff,
+                   double* partial, float* r32, hipStream_t s) {
+  launch_group<G_RUPDATE>(g, nullptr, nullptr, r, q, poff, partial, r32, s);
+}
+void group_xflush(const GridArgs& g, double* x, const double* p0, const double* p1,
+                  hipStream_t s) {
+  launch_group<G_XFLUSH>(g, x, p0, nullptr, p1, nullptr, nullptr, nullptr, s);
+}
 
 // ---------------------------------------------------------------------------
 // Per-problem scalar steps, one workgroup for all problems (fixed summation
@@ -2494,7 +2551,7 @@ void group_misfit(const GridArgs& g, double* y, const double* yd, double* b_rows
 __global__ void __launch_bounds__(256)
     k_cg_scalar(int phase, CgScal* scal, int nprob, const int* __restrict__ poff,
                 const int* __restrict__ pcnt, const double* __restrict__ partial, double rtol,
-                int max_iters, int* active_count) {
+                int max_iters, int* active_count, int aux) {
   __shared__ int scount[256];
   int cnt = 0;
   const double rt2 = rtol * rtol;
@@ -2517,27 +2574,37 @@ __global__ void __launch_bounds__(256)
         sc.beta = 0.0;
         sc.rz = 0.0;
         sc.pq = 0.0;
+        sc.pending = 0;
+        sc.pbuf = 0;
         break;
       case PH_RZ0:
         if (sc.active) {
           sc.rz = sum;
           sc.beta = 0.0;
+          sc.pending = 0;
         }
         break;
       case PH_RZ0_RR:
         if (sc.active) {
           sc.rz = sc.rr;
           sc.beta = 0.0;
+          sc.pending = 0;
         }
         break;
       case PH_ALPHA:
+        // the matvec just run applied the previous step of x; this one is
+        // pending until the next matvec (or the flush before the residual
+        // check) applies it from direction buffer aux
         if (sc.active) {
           sc.pq = sum;
           if (sum > 0.0) {
             sc.alpha = sc.rz / sum;
+            sc.pending = 1;
+            sc.pbuf = aux;
           } else {
             sc.alpha = 0.0;
             sc.active = 0;
+            sc.pending = 0;
           }
         }
         break;
@@ -2565,6 +2632,7 @@ __global__ void __launch_bounds__(256)
         sc.active = (sc.bb > 0.0) && (sum > rt2 * sc.bb) && (sc.iters < max_iters);
         sc.alpha = 0.0;
         sc.beta = 0.0;
+        sc.pending = 0;
         break;
     }
     scal[p] = sc;
@@ -2586,10 +2654,10 @@ __global__ void k_zero_int(int* x) {
 
 void cg_scalar(int phase, CgScal* scal, int nprob, const int* poff, const int* pcnt,
                const double* partial, double rtol, int max_iters, int* active_count,
-               hipStream_t s) {
+               hipStream_t s, int aux) {
   if (active_count) hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, s, active_count);
   hipLaunchKernelGGL(k_cg_scalar, dim3((nprob + 255) / 256), dim3(256), 0, s, phase, scal, nprob,
-                     poff, pcnt, partial, rtol, max_iters, active_count);
+                     poff, pcnt, partial, rtol, max_iters, active_count, aux);
 }
 
 __global__ void __launch_bounds__(1024)

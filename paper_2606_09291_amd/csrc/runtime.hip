@@ -182,6 +182,7 @@ struct mlsgd_ctx {
   bool pre2r = true;        // fused pre-smoothing and residual pass where it applies
   bool post2 = true;        // fused two-step post-smoothing pass where it applies
   bool vsmall = true;       // the cycle from 9^3 down as one kernel where it applies
+  bool xdefer = true;       // x's Krylov step applied by the next matvec
   // event timing of the smoothing passes on one grid size (roofline figures)
   struct Timing {
     bool on = false;
@@ -681,7 +682,8 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
       P->sizes[S - 2].rows == P->sizes[S - 3].rows) {
     const GridArgs g9 = args(P->sizes[S - 3]), g5 = args(P->sizes[S - 2]),
                    g3 = args(P->sizes[S - 1]);
-    if (g9.cache && g5.cache && g3.cache) ks = S - 3;
+    // the kernel writes a problem's <r, z> partial into its one 9^3 slot
+    if (g9.cache && g5.cache && g3.cache && g9.t.tiles_per_row == 1) ks = S - 3;
   }
   for (int k = 0; k < S; ++k) {
     SizeLvl& L = P->sizes[k];
@@ -930,6 +932,57 @@ int read_count(mlsgd_ctx* c) {
   return *c->h_count;
 }
 
+// One Krylov step of every active problem after z = M r: p = z + beta p,
+// q = A p and alpha, then r -= alpha q with <r, r>.  With xdefer the step
+// x += alpha p is applied by the next iteration's matvec, which reads that p
+// anyway (8 B per point less than updating x here); the step of a problem's
+// last iteration stays pending in its scalars, with the direction buffer
+// that holds its p, until flush_steps.  Every iterate is the same in both
+// modes: the same x + alpha p is formed, one pass later.
+void krylov_step(mlsgd_ctx* c, Plan* P, bool mg, int it) {
+  hipStream_t s = c->stream;
+  const double rtol = c->pb.rtol;
+  const int maxit = c->pb.max_iters;
+  const bool defer = c->xdefer;
+  int pslot = 0;  // every group writes the new direction into p[pcur ^ 1]
+  for (auto& gr : P->groups) {
+    GridArgs g = args_group(c, P, gr, true);
+    SizeLvl& L = P->sizes[gr.sl];
+    double* xd = (defer && it > 0) ? gr.x : nullptr;
+    if (mg && c->mixed) {
+      march_matvec<double, float>(g, z32(c, P, gr), gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q,
+                                  P->d_poff, P->d_partial, s, xd);
+    } else {
+      const double* z = mg ? z64(c, P, gr) : rows_of(L.B, gr);
+      march_matvec<double, double>(g, z, gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q, P->d_poff,
+                                   P->d_partial, s, xd);
+    }
+    pslot = gr.pcur ^ 1;
+  }
+  cg_scalar(PH_ALPHA, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
+            c->d_count, s, pslot);
+  for (auto& gr : P->groups) {
+    GridArgs g = args_group(c, P, gr, true);
+    float* r32 = (mg && c->mixed) ? P->sizes[gr.sl].Bf + (size_t)gr.p0 * srow(gr.n) : nullptr;
+    if (defer)
+      group_rupdate(g, rows_of(P->sizes[gr.sl].B, gr), gr.q, P->d_poff, P->d_partial, r32, s);
+    else
+      group_update(g, gr.x, gr.p[gr.pcur ^ 1], rows_of(P->sizes[gr.sl].B, gr), gr.q,
+                   P->d_poff, P->d_partial, r32, s);
+    gr.pcur ^= 1;
+  }
+}
+
+// Apply every pending step x += alpha p (active problems and those that
+// converged earlier alike) before x is read.
+void flush_steps(mlsgd_ctx* c, Plan* P) {
+  if (!c->xdefer) return;
+  for (auto& gr : P->groups) {
+    GridArgs g = args_group(c, P, gr, true);
+    group_xflush(g, gr.x, gr.p[0], gr.p[1], c->stream);
+  }
+}
+
 // Batched (preconditioned) CG on every problem of the plan.  On entry the
 // B rows of each top grid hold the right-hand side b, b0 a copy of it, x = 0.
 void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* relres_out) {
@@ -961,28 +1014,7 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
                 c->d_count, s);
     }
     for (int it = 0; it < maxit; ++it) {
-      for (auto& gr : P->groups) {
-        GridArgs g = args_group(c, P, gr, true);
-        SizeLvl& L = P->sizes[gr.sl];
-        if (mg && c->mixed) {
-          const float* z = z32(c, P, gr);
-          march_matvec<double, float>(g, z, gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q, P->d_poff,
-                                      P->d_partial, s);
-        } else {
-          const double* z = mg ? z64(c, P, gr) : rows_of(L.B, gr);
-          march_matvec<double, double>(g, z, gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q, P->d_poff,
-                                       P->d_partial, s);
-        }
-      }
-      cg_scalar(PH_ALPHA, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
-                c->d_count, s);
-      for (auto& gr : P->groups) {
-        GridArgs g = args_group(c, P, gr, true);
-        float* r32 = (mg && c->mixed) ? P->sizes[gr.sl].Bf + (size_t)gr.p0 * srow(gr.n) : nullptr;
-        group_update(g, gr.x, gr.p[gr.pcur ^ 1], rows_of(P->sizes[gr.sl].B, gr), gr.q,
-                     P->d_poff, P->d_partial, r32, s);
-        gr.pcur ^= 1;
-      }
+      krylov_step(c, P, mg, it);
       cg_scalar(PH_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
                 c->d_count, s);
       HIPCHK(hipGetLastError());
@@ -997,6 +1029,7 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
       }
     }
     // true residual b0 - A x into q, its norm; restart the problems that drifted
+    flush_steps(c, P);
     for (auto& gr : P->groups) {
       GridArgs g = args_group(c, P, gr, false);
       march_resid<double>(g, gr.x, gr.b0, gr.q, s);
@@ -1053,26 +1086,7 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
   };
   auto iterate = [&](int count) {
     for (int it = 0; it < count; ++it) {
-      for (auto& gr : P->groups) {
-        GridArgs g = args_group(c, P, gr, true);
-        SizeLvl& L = P->sizes[gr.sl];
-        if (mg && c->mixed) {
-          march_matvec<double, float>(g, z32(c, P, gr), gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q,
-                                      P->d_poff, P->d_partial, s);
-        } else {
-          const double* z = mg ? z64(c, P, gr) : rows_of(L.B, gr);
-          march_matvec<double, double>(g, z, gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q, P->d_poff,
-                                       P->d_partial, s);
-        }
-      }
-      cg(PH_ALPHA, P->d_partial);
-      for (auto& gr : P->groups) {
-        GridArgs g = args_group(c, P, gr, true);
-        float* r32 = (mg && c->mixed) ? P->sizes[gr.sl].Bf + (size_t)gr.p0 * srow(gr.n) : nullptr;
-        group_update(g, gr.x, gr.p[gr.pcur ^ 1], rows_of(P->sizes[gr.sl].B, gr), gr.q,
-                     P->d_poff, P->d_partial, r32, s);
-        gr.pcur ^= 1;
-      }
+      krylov_step(c, P, mg, it);
       cg(PH_RR, P->d_partial);
       if (mg) {
         precondition(c, P);
@@ -1083,6 +1097,7 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
     }
   };
   auto true_residual = [&]() {
+    flush_steps(c, P);
     for (auto& gr : P->groups) {
       GridArgs g = args_group(c, P, gr, false);
       march_resid<double>(g, gr.x, gr.b0, gr.q, s);
@@ -1631,6 +1646,7 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     if (const char* e = getenv("MLSGD_PRE2R")) c->pre2r = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_POST2")) c->post2 = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_VSMALL")) c->vsmall = atoi(e) != 0;
+    if (const char* e = getenv("MLSGD_XDEFER")) c->xdefer = atoi(e) != 0;
     c->nfin = pb->grid_n[pb->n_levels - 1];
     const size_t NF = cube(c->nfin);
     c->d_f = (double*)dalloc(c.get(), sizeof(double) * NF);
