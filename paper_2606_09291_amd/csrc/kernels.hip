@@ -60,6 +60,24 @@ __device__ __forceinline__ int xcd_swizzle(int b, int nb) {
   return (xcd < r ? xcd * (q + 1) : r * (q + 1) + (xcd - r) * q) + loc;
 }
 
+// Sum of a problem's c partial slots in slot order.  The loads are issued
+// sixteen at a time before their additions, so one thread's slots are in
+// flight together; the additions keep the sequential order, so the sum is
+// the same to the bit as a plain loop's.
+__device__ __forceinline__ double slot_sum(const double* __restrict__ v, int c) {
+  double sum = 0.0;
+  int j = 0;
+  for (; j + 16 <= c; j += 16) {
+    double t[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) t[u] = v[j + u];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) sum += t[u];
+  }
+  for (; j < c; ++j) sum += v[j];
+  return sum;
+}
+
 template <int NT>
 __device__ __forceinline__ double block_sum(double v, double* sred) {
 #pragma unroll
@@ -2561,7 +2579,7 @@ __global__ void __launch_bounds__(256)
     double sum = 0.0;
     if (partial) {
       const int o = poff[p], c = pcnt[p];
-      for (int j = 0; j < c; ++j) sum += partial[o + j];
+      sum = slot_sum(partial + o, c);
     }
     CgScal sc = scal[p];
     switch (phase) {
@@ -2702,9 +2720,7 @@ __global__ void k_sum_partials(int nprob, const int* poff, const int* pcnt,
                                const double* partial, double scale, double* dst) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= nprob) return;
-  double sum = 0.0;
-  for (int j = 0; j < pcnt[p]; ++j) sum += partial[poff[p] + j];
-  dst[p] = scale * sum;
+  dst[p] = scale * slot_sum(partial + poff[p], pcnt[p]);
 }
 void sum_partials(int nprob, const int* poff, const int* pcnt, const double* partial,
                   double scale, double* dst, hipStream_t s) {
