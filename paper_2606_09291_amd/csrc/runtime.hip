@@ -176,7 +176,7 @@ struct mlsgd_ctx {
   bool mixed = false;       // FP32 V-cycles inside the FP64 Krylov iteration
   bool bf16 = false;        // mixed, with the smoother's coefficient stored as bfloat16
   int smoother = 2;         // 0 red-black GS (two in-place passes), 1 fused red-black, 2 Chebyshev
-  double cheb_lo = 1.0 / 6.0;  // Chebyshev interval [cheb_lo * 2, 2] for D^-1 A
+  double cheb_lo = 0.15;    // Chebyshev interval [cheb_lo * 2, 2] for D^-1 A
   int tile_y = 8;           // y extent of the stencil tiles on large grids
   int xchunk = 32;          // x planes per workgroup
   bool pre2r = true;        // fused pre-smoothing and residual pass where it applies
@@ -1629,9 +1629,10 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     c->stream = (hipStream_t)stream;
     c->mixed = pb->precision == MLSGD_MIXED_FP32 || pb->precision == MLSGD_MIXED_BF16;
     c->bf16 = pb->precision == MLSGD_MIXED_BF16;
-    // measured defaults (Chebyshev smoothing; degree and interval per precision)
-    c->nu = c->mixed ? 3 : 2;
-    c->cheb_lo = c->mixed ? 0.1 : 0.25;
+    // measured defaults: Chebyshev smoothing of degree 2 on [0.3, 2], the
+    // autotuner's choice for FP64, FP32 and bfloat16-coefficient V-cycles
+    c->nu = 2;
+    c->cheb_lo = 0.15;
     if (const char* e = getenv("MLSGD_NU")) c->nu = std::max(1, atoi(e));
     if (const char* e = getenv("MLSGD_OMEGA")) c->omega = atof(e);
     if (const char* e = getenv("MLSGD_CACHE64")) c->cache64 = atoi(e) != 0;

@@ -28,16 +28,21 @@ def _setup(mm, grid, **kw):
     return ctx, u, yd
 
 
-@pytest.mark.parametrize("grid,M,n_dirs", [([65], [256], 20), ([9, 17, 33], [32, 8, 4], 8)])
-def test_backward_matches_central_differences(mm, grid, M, n_dirs):
+@pytest.mark.parametrize("grid,M,n_dirs,rtol", [([65], [256], 20, 1e-12),
+                                                ([9, 17, 33], [32, 8, 4], 8, 1e-13)])
+def test_backward_matches_central_differences(mm, grid, M, n_dirs, rtol):
     """Central differences, eps = 1e-6, against <dJ/du, d> from backward, in
-    random smooth directions (sine-mode combinations).  White-noise directions
-    have a directional derivative ~sqrt(N) smaller, which puts the quotient
-    at the solver's noise floor (|dJ| ~ 1e-13 |J| at rtol 1e-12) for eps = 1e-6."""
+    random smooth directions (sine-mode combinations).  The quotient carries
+    the solver's noise: each J is exact only to about rtol |J|, so the
+    quotient is off by up to ~rtol |J| / eps, which at rtol 1e-12 is the
+    order of the 1e-6 bar wherever |dJ| is well below |J|.  The three-level
+    case is therefore solved to 1e-13 (its finest grid's FP64 residual floor
+    is near 2e-14).  White-noise directions have a directional derivative
+    ~sqrt(N) smaller still and would sit at the noise floor."""
     import torch
     from paper_2606_09291_amd.autograd import objective
-    print("autograd FD", grid, M, flush=True)
-    ctx, u, _ = _setup(mm, grid, theta=1.0, alpha=1e-3, rtol=1e-12)
+    print("autograd FD", grid, M, rtol, flush=True)
+    ctx, u, _ = _setup(mm, grid, theta=1.0, alpha=1e-3, rtol=rtol)
     first = [3] * len(grid)
     uu = u.clone().requires_grad_(True)
     J = objective(uu, ctx, M, first)
