@@ -1143,8 +1143,10 @@ __global__ void __launch_bounds__(TY* TZ)
     __syncthreads();
   }
 
-  // patch column: x3 at q-2, q-1, b at q-1, 1/a and the face to +x of plane q-2
-  T x3a = T(0), x3b = T(0), rm_ = T(0), ofa = T(0), obmm = T(1);
+  // patch column: x3 at q-2, q-1, b at q-1, 1/a and the face to +x of plane
+  // q-2, and the reciprocal diagonal of plane q-1 (formed by the x3 step
+  // there, from the faces and in the order the x4 step would use)
+  T x3a = T(0), x3b = T(0), rm_ = T(0), ofa = T(0), obmm = T(1), odb = T(0);
   double dot = 0.0;
 
   for (int q = x0 - 1; q <= x1; ++q) {
@@ -1184,7 +1186,7 @@ __global__ void __launch_bounds__(TY* TZ)
       }
     };
     const T ofc = face(obc, obp);
-    T x3c = T(0);
+    T x3c = T(0), odc = T(0);
     if (qin && o_int) {
       const T fxm = ofb, fxp = ofc;
       T fym, fyp, fzm, fzp;
@@ -1192,7 +1194,8 @@ __global__ void __launch_bounds__(TY* TZ)
       const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
       const T off = ((fxm * oym + fxp * oyp) + (fym * s1[oidx - PZ] + fyp * s1[oidx + PZ])) +
                     (fzm * s1[oidx - 1] + fzp * s1[oidx + 1]);
-      x3c = oyc + omega_a * (orc - ih2 * (diag * oyc - off)) * drcp(ih2 * diag);
+      odc = drcp(ih2 * diag);
+      x3c = oyc + omega_a * (orc - ih2 * (diag * oyc - off)) * odc;
     }
     T* __restrict__ x3s = s3[q & 1];
     x3s[oidx] = x3c;
@@ -1231,7 +1234,11 @@ __global__ void __launch_bounds__(TY* TZ)
       const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
       const T off = ((fxm * x3a + fxp * x3c) + (fym * x3p[oidx - PZ] + fyp * x3p[oidx + PZ])) +
                     (fzm * x3p[oidx - 1] + fzp * x3p[oidx + 1]);
-      const T val = x3b + omega_b * (rm_ - ih2 * (diag * x3b - off)) * drcp(ih2 * diag);
+      // FP64: odb is drcp(ih2 * diag) of this column and plane as the x3
+      // step formed it (a five-operation reciprocal); FP32 forms it again
+      // (one instruction, and the kept value would cost occupancy)
+      const T dinv = sizeof(T) == 8 ? odb : drcp(ih2 * diag);
+      const T val = x3b + omega_b * (rm_ - ih2 * (diag * x3b - off)) * dinv;
       const size_t e = base + ((size_t)qr * n + oy) * LP + oz + LO;
       __builtin_nontemporal_store(val, &xout[e]);
       if (partial) dot += (double)rm_ * (double)val;
@@ -1240,6 +1247,7 @@ __global__ void __launch_bounds__(TY* TZ)
     // advance one plane
     x3a = x3b;
     x3b = x3c;
+    odb = odc;
     rm_ = orc;
     ofa = ofb; ofb = ofc;
     obmm = obm;
