@@ -146,6 +146,15 @@ void restrict_rows(int nf, int rows, int row0, const CgScal* scal, const T* fine
 template <typename T>
 void prolong_add_rows(int nc, int rows, int row0, const CgScal* scal, const T* coarse,
                       T* fine, hipStream_t s);
+// fine rows = trilinear prolongation of the coarse rows (interior vertices;
+// every row)
+template <typename T>
+void prolong_rows(int nc, int rows, const T* coarse, T* fine, hipStream_t s);
+// dst rows (FP64, n^3 solver rows) = src rows for the problems row0.. that
+// are active; the rows of inactive problems are left as they are
+template <typename TS>
+void copy_active_rows(int n, int rows, int row0, const CgScal* scal, const TS* src, double* dst,
+                      hipStream_t s);
 
 // ---- dense coarsest-grid solve (hierarchies that stop above 3^3) ----
 void dense_coarse_inv(int n, int rows, const double* coef, int K, const double* cosT,

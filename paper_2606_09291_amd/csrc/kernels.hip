@@ -1903,7 +1903,7 @@ __global__ void k_restrict_rows(int nf, int rows, int row0, const CgScal* scal,
 
 template <typename T>
 __global__ void k_prolong_add_rows(int nc, int rows, int row0, const CgScal* scal,
-                                   const T* __restrict__ coarse, T* __restrict__ fine) {
+                                   const T* __restrict__ coarse, T* __restrict__ fine, int set) {
   const int nf = 2 * (nc - 1) + 1, mf = nf - 2;
   const long long per = (long long)mf * mf * mf;
   const long long total = per * rows;
@@ -1936,7 +1936,11 @@ __global__ void k_prolong_add_rows(int nc, int rows, int row0, const CgScal* sca
         if (iz & 1) v += cv(bx, by, bz);
       }
     }
-    fine[(size_t)row * sf + ((size_t)ix * nf + iy) * fp + iz + fo] += wx * wy * wz * v;
+    T* dst = &fine[(size_t)row * sf + ((size_t)ix * nf + iy) * fp + iz + fo];
+    if (set)
+      *dst = wx * wy * wz * v;
+    else
+      *dst += wx * wy * wz * v;
   }
 }
 
@@ -1971,8 +1975,43 @@ void prolong_add_rows(int nc, int rows, int row0, const CgScal* scal, const T* c
   const int mf = 2 * (nc - 1) - 1;
   const long long total = (long long)mf * mf * mf * rows;
   hipLaunchKernelGGL(k_prolong_add_rows<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, nc,
-                     rows, row0, scal, coarse, fine);
+                     rows, row0, scal, coarse, fine, 0);
 }
+template <typename T>
+void prolong_rows(int nc, int rows, const T* coarse, T* fine, hipStream_t s) {
+  if (rows <= 0) return;
+  const int mf = 2 * (nc - 1) - 1;
+  const long long total = (long long)mf * mf * mf * rows;
+  hipLaunchKernelGGL(k_prolong_add_rows<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, nc,
+                     rows, 0, nullptr, coarse, fine, 1);
+}
+template void prolong_rows<double>(int, int, const double*, double*, hipStream_t);
+template void prolong_rows<float>(int, int, const float*, float*, hipStream_t);
+
+// dst rows = src rows (widened to FP64) for the active problems; the rows of
+// inactive problems are left as they are
+template <typename TS>
+__global__ void k_copy_active_rows(long long per, int rows, int row0, const CgScal* scal,
+                                   const TS* __restrict__ src, double* __restrict__ dst) {
+  const long long total = per * rows;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int row = (int)(i / per);
+    if (scal[row0 + row].active) dst[i] = (double)src[i];
+  }
+}
+template <typename TS>
+void copy_active_rows(int n, int rows, int row0, const CgScal* scal, const TS* src, double* dst,
+                      hipStream_t s) {
+  if (rows <= 0) return;
+  const long long per = (long long)lay_row(n);
+  hipLaunchKernelGGL(k_copy_active_rows<TS>, dim3(grid_for(per * rows, 256)), dim3(256), 0, s,
+                     per, rows, row0, scal, src, dst);
+}
+template void copy_active_rows<double>(int, int, int, const CgScal*, const double*, double*,
+                                       hipStream_t);
+template void copy_active_rows<float>(int, int, int, const CgScal*, const float*, double*,
+                                      hipStream_t);
 template void restrict_rows<double>(int, int, int, const CgScal*, const double*, double*,
                                     hipStream_t);
 template void restrict_rows<float>(int, int, int, const CgScal*, const float*, float*,

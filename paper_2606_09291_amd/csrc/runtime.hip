@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <functional>
 #include <cmath>
 #include <cstdio>
@@ -183,6 +184,7 @@ struct mlsgd_ctx {
   bool post2 = true;        // fused two-step post-smoothing pass where it applies
   bool vsmall = true;       // the cycle from 9^3 down as one kernel where it applies
   bool xdefer = true;       // x's Krylov step applied by the next matvec
+  bool fmg = false;         // full-multigrid start of the Krylov solves (default: FP32 cycles)
   // event timing of the smoothing passes on one grid size (roofline figures)
   struct Timing {
     bool on = false;
@@ -663,19 +665,27 @@ const double* dinv_of<double>(const SizeLvl& L) { return L.Di; }
 template <>
 const float* dinv_of<float>(const SizeLvl& L) { return L.Dif; }
 
+//
+// k0, rlim, xinit serve the full-multigrid start: the cycle then begins on
+// grid size k0, covers rows 0 .. rlim-1 of every size (the problems whose top
+// grid is k0 or larger), and its pre-smoothing on k0 starts from the guess
+// in the X rows instead of from zero.
 template <typename T>
-void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
+void vcycle_cheb(mlsgd_ctx* c, Plan* P, int k0 = 0, int rlim = INT_MAX, bool xinit = false) {
   const int S = (int)P->sizes.size();
   const int deg = c->nu;
   const std::vector<double> om = cheb_omegas(deg, c->cheb_lo);
   auto args = [&](SizeLvl& L) {
-    return sizeof(T) == 8 ? args_size(c, P, L) : args_size32(c, P, L);
+    GridArgs g = sizeof(T) == 8 ? args_size(c, P, L) : args_size32(c, P, L);
+    g.rows = std::min(g.rows, rlim);
+    return g;
   };
   // the levels from 9^3 down run as one LDS-resident kernel where the
   // hierarchy ends 9^3, 5^3, 3^3 with cached coefficients and every problem
   // on 5^3 and 3^3 comes down from 9^3 (none has its top grid there)
   int ks = S;
-  if (c->vsmall && S >= 3 && !P->ainv && P->sizes[S - 3].n == 9 && P->sizes[S - 2].n == 5 &&
+  if (c->vsmall && S >= 3 && S - 3 >= k0 && !(xinit && S - 3 == k0) && !P->ainv &&
+      P->sizes[S - 3].n == 9 && P->sizes[S - 2].n == 5 &&
       P->sizes[S - 1].n == 3 && (int)om.size() <= VS_MAXDEG &&
       P->sizes[S - 2].top_begin == P->sizes[S - 2].rows &&
       P->sizes[S - 1].top_begin == P->sizes[S - 1].rows &&
@@ -685,23 +695,23 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
     // the kernel writes a problem's <r, z> partial into its one 9^3 slot
     if (g9.cache && g5.cache && g3.cache && g9.t.tiles_per_row == 1) ks = S - 3;
   }
-  for (int k = 0; k < S; ++k) {
+  for (int k = k0; k < S; ++k) {
     SizeLvl& L = P->sizes[k];
     MgView<T> v = mg_view<T>(L);
     T* A[2] = {v.X, v.R};
     GridArgs g = args(L);
     if (k == ks) {
       const GridArgs g5 = args(P->sizes[k + 1]), g3 = args(P->sizes[k + 2]);
-      vcycle_small<T>(L.rows, om.data(), deg, L.top_begin, P->d_scal, v.B, g.cache, g5.cache,
+      vcycle_small<T>(g.rows, om.data(), deg, L.top_begin, P->d_scal, v.B, g.cache, g5.cache,
                       g3.cache, g.cache_bf16, A[0], P->d_poff, P->d_partial, c->stream);
       L.cur = 0;
       break;
     }
     if (k == S - 1) {
       if (P->ainv) {
-        dense_apply<T>(L.n, L.rows, P->d_scal, P->ainv, v.B, A[0], c->stream);
+        dense_apply<T>(L.n, g.rows, P->d_scal, P->ainv, v.B, A[0], c->stream);
       } else {
-        timed_launch(c, g, jac_bytes<T>(L.n, L.rows, true, false, g), [&] {
+        timed_launch(c, g, jac_bytes<T>(L.n, g.rows, true, false, g), [&] {
           march_jac<T>(g, nullptr, nullptr, v.B, A[0], 1, 1.0, P->d_poff, P->d_partial,
                        L.top_begin, c->stream);
         });
@@ -712,10 +722,23 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
     int cur = 0;
     int j0 = 1;
     const T* dinv = dinv_of<T>(L);
+    if (xinit && k == k0) {
+      // pre-smoothing from the guess in the X rows
+      for (int j = 0; j < deg; ++j) {
+        march_jac<T>(g, A[cur], nullptr, v.B, A[cur ^ 1], 0, om[j], nullptr, nullptr, 0,
+                     c->stream);
+        cur ^= 1;
+      }
+      march_resid<T>(g, A[cur], v.B, A[cur ^ 1], c->stream);
+      restrict_rows<T>(L.n, g.rows, 0, P->d_scal, A[cur ^ 1], mg_view<T>(P->sizes[k + 1]).B,
+                       c->stream);
+      L.cur = cur;
+      continue;
+    }
     if (deg == 2 && dinv && c->pre2r && fused_tiles(g)) {
       march_pre2r<T>(g, dinv, v.B, A[1], A[0], om[0], om[1], c->stream);
       // both pre-smoothing steps and the residual in one pass: x2 in A[1], r in A[0]
-      restrict_rows<T>(L.n, L.rows, 0, P->d_scal, A[0], mg_view<T>(P->sizes[k + 1]).B,
+      restrict_rows<T>(L.n, g.rows, 0, P->d_scal, A[0], mg_view<T>(P->sizes[k + 1]).B,
                        c->stream);
       L.cur = 1;
       continue;
@@ -726,24 +749,24 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
       cur = 1;
       j0 = 2;
     } else {
-      timed_launch(c, g, jac_bytes<T>(L.n, L.rows, true, false, g), [&] {
+      timed_launch(c, g, jac_bytes<T>(L.n, g.rows, true, false, g), [&] {
         march_jac<T>(g, nullptr, nullptr, v.B, A[0], 1, om[0], nullptr, nullptr, 0, c->stream);
       });
     }
     for (int j = j0; j < deg; ++j) {
-      timed_launch(c, g, jac_bytes<T>(L.n, L.rows, false, false, g), [&] {
+      timed_launch(c, g, jac_bytes<T>(L.n, g.rows, false, false, g), [&] {
         march_jac<T>(g, A[cur], nullptr, v.B, A[cur ^ 1], 0, om[j], nullptr, nullptr, 0,
                      c->stream);
       });
       cur ^= 1;
     }
     march_resid<T>(g, A[cur], v.B, A[cur ^ 1], c->stream);
-    restrict_rows<T>(L.n, L.rows, 0, P->d_scal, A[cur ^ 1], mg_view<T>(P->sizes[k + 1]).B,
+    restrict_rows<T>(L.n, g.rows, 0, P->d_scal, A[cur ^ 1], mg_view<T>(P->sizes[k + 1]).B,
                      c->stream);
     L.cur = cur;
   }
   // up from the level above the coarsest one handled (the small cycle's 9^3, or S - 1)
-  for (int k = (ks < S ? ks : S - 1) - 1; k >= 0; --k) {
+  for (int k = (ks < S ? ks : S - 1) - 1; k >= k0; --k) {
     SizeLvl& L = P->sizes[k];
     MgView<T> v = mg_view<T>(L);
     T* A[2] = {v.X, v.R};
@@ -755,7 +778,7 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
     int j = 0;
     if (deg >= 2 && c->post2 && fused_tiles(g)) {
       // the step with the coarse-grid correction and the next one in one pass
-      timed_launch(c, g, post2_bytes<T>(L.n, L.rows, g), [&] {
+      timed_launch(c, g, post2_bytes<T>(L.n, g.rows, g), [&] {
         march_post2<T>(g, A[cur], xc, v.B, A[cur ^ 1], om[deg - 1], om[deg - 2],
                        deg == 2 ? P->d_poff : nullptr, deg == 2 ? P->d_partial : nullptr,
                        L.top_begin, c->stream);
@@ -771,7 +794,7 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P) {
                      last ? P->d_poff : nullptr, last ? P->d_partial : nullptr, L.top_begin,
                      c->stream);
       } else {
-        timed_launch(c, g, jac_bytes<T>(L.n, L.rows, false, false, g), [&] {
+        timed_launch(c, g, jac_bytes<T>(L.n, g.rows, false, false, g), [&] {
           march_jac<T>(g, A[cur], nullptr, v.B, A[cur ^ 1], 0, om[deg - 1 - j],
                        last ? P->d_poff : nullptr, last ? P->d_partial : nullptr, L.top_begin,
                        c->stream);
@@ -932,6 +955,67 @@ int read_count(mlsgd_ctx* c) {
   return *c->h_count;
 }
 
+// Full-multigrid start of the Krylov solves (Chebyshev cycles, hierarchies
+// ending at 3^3): b restricted to every grid, the exact solve on 3^3, then on
+// each larger grid the prolonged solution of the grid below improved by one
+// cycle from that grid, over the problems whose top grid is that size or
+// larger.  A problem's result on its top grid becomes its starting iterate x0
+// (active problems only; the others keep x = 0) and the B rows of the top
+// grids receive r0 = b - A x0.  bb must already hold |b|^2.
+bool fmg_applies(mlsgd_ctx* c, Plan* P) {
+  return c->fmg && c->pb.solver == MLSGD_SOLVER_MGPCG && c->smoother == 2 && !P->ainv &&
+         P->sizes.size() >= 2 && P->sizes.back().n == 3;
+}
+
+template <typename T>
+void fmg_start(mlsgd_ctx* c, Plan* P) {
+  hipStream_t s = c->stream;
+  const int S = (int)P->sizes.size();
+  if (sizeof(T) == 4) {
+    for (auto& gr : P->groups) {
+      SizeLvl& L = P->sizes[gr.sl];
+      to_f32((long long)gr.count * srow(gr.n), rows_of(L.B, gr),
+             L.Bf + (size_t)gr.p0 * srow(gr.n), s);
+    }
+  }
+  for (int k = 0; k + 1 < S; ++k) {
+    SizeLvl& L = P->sizes[k];
+    restrict_rows<T>(L.n, L.rows, 0, nullptr, mg_view<T>(L).B, mg_view<T>(P->sizes[k + 1]).B, s);
+  }
+  {
+    SizeLvl& L = P->sizes[S - 1];
+    GridArgs g = sizeof(T) == 8 ? args_size(c, P, L) : args_size32(c, P, L);
+    march_jac<T>(g, nullptr, nullptr, mg_view<T>(L).B, mg_view<T>(L).X, 1, 1.0, nullptr, nullptr,
+                 0, s);
+    L.cur = 0;
+  }
+  for (int k = S - 2; k >= 0; --k) {
+    SizeLvl& L = P->sizes[k];
+    SizeLvl& Lc = P->sizes[k + 1];
+    const T* xc = Lc.cur ? mg_view<T>(Lc).R : mg_view<T>(Lc).X;
+    prolong_rows<T>(Lc.n, L.rows, xc, mg_view<T>(L).X, s);
+    vcycle_cheb<T>(c, P, k, L.rows, true);
+    const T* xk = L.cur ? mg_view<T>(L).R : mg_view<T>(L).X;
+    for (auto& gr : P->groups)
+      if (gr.sl == k)
+        copy_active_rows<T>(gr.n, gr.count, gr.p0, P->d_scal, xk + (size_t)gr.p0 * srow(gr.n),
+                            gr.x, s);
+  }
+  for (auto& gr : P->groups) {
+    GridArgs g = args_group(c, P, gr, false);
+    march_resid<double>(g, gr.x, gr.b0, rows_of(P->sizes[gr.sl].B, gr), s);
+  }
+  HIPCHK(hipGetLastError());
+}
+
+void fmg(mlsgd_ctx* c, Plan* P) {
+  if (!fmg_applies(c, P)) return;
+  if (c->mixed)
+    fmg_start<float>(c, P);
+  else
+    fmg_start<double>(c, P);
+}
+
 // One Krylov step of every active problem after z = M r: p = z + beta p,
 // q = A p and alpha, then r -= alpha q with <r, r>.  With xdefer the step
 // x += alpha p is applied by the next iteration's matvec, which reads that p
@@ -997,6 +1081,7 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
   }
   cg_scalar(PH_INIT_BB, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
             c->d_count, s);
+  fmg(c, P);
   for (int restart = 0; restart < 3; ++restart) {
     if (mg && c->mixed) {
       for (auto& gr : P->groups) {
@@ -1111,6 +1196,7 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
     group_dot(g, r, r, P->d_poff, P->d_partial, s);
   }
   cg(PH_INIT_BB, P->d_partial);
+  fmg(c, P);
   start();
   iterate(iters);
   true_residual();
@@ -1633,6 +1719,10 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     // autotuner's choice for FP64, FP32 and bfloat16-coefficient V-cycles
     c->nu = 2;
     c->cheb_lo = 0.15;
+    // measured: with FP32 cycles the full-multigrid start saves more than it
+    // costs; with FP64 cycles its cycles, the r0 pass and the extra restarts
+    // near the FP64 residual floor cost more than the iterations saved
+    c->fmg = c->mixed;
     if (const char* e = getenv("MLSGD_NU")) c->nu = std::max(1, atoi(e));
     if (const char* e = getenv("MLSGD_OMEGA")) c->omega = atof(e);
     if (const char* e = getenv("MLSGD_CACHE64")) c->cache64 = atoi(e) != 0;
@@ -1648,6 +1738,7 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     if (const char* e = getenv("MLSGD_POST2")) c->post2 = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_VSMALL")) c->vsmall = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_XDEFER")) c->xdefer = atoi(e) != 0;
+    if (const char* e = getenv("MLSGD_FMG")) c->fmg = atoi(e) != 0;
     c->nfin = pb->grid_n[pb->n_levels - 1];
     const size_t NF = cube(c->nfin);
     c->d_f = (double*)dalloc(c.get(), sizeof(double) * NF);
