@@ -184,7 +184,8 @@ struct mlsgd_ctx {
   bool post2 = true;        // fused two-step post-smoothing pass where it applies
   bool vsmall = true;       // the cycle from 9^3 down as one kernel where it applies
   bool xdefer = true;       // x's Krylov step applied by the next matvec
-  bool fmg = false;         // full-multigrid start of the Krylov solves (default: FP32 cycles)
+  bool fmg = true;          // full-multigrid start of the Krylov solves
+  double fmg_margin = 0.5;  // recursive-residual target as a fraction of rtol after that start
   // event timing of the smoothing passes on one grid size (roofline figures)
   struct Timing {
     bool on = false;
@@ -1082,6 +1083,12 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
   cg_scalar(PH_INIT_BB, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
             c->d_count, s);
   fmg(c, P);
+  // after a full-multigrid start r0 carries the evaluation error of b - A x0
+  // (near the FP64 residual floor, a few tenths of rtol on 129^3 grids), which
+  // the recursion keeps; a recursive target of half of rtol leaves room for
+  // it, so the true-residual check at exit (still against rtol) rarely has to
+  // restart a solve
+  const double rtol_rr = fmg_applies(c, P) ? c->fmg_margin * rtol : rtol;
   for (int restart = 0; restart < 3; ++restart) {
     if (mg && c->mixed) {
       for (auto& gr : P->groups) {
@@ -1100,7 +1107,7 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
     }
     for (int it = 0; it < maxit; ++it) {
       krylov_step(c, P, mg, it);
-      cg_scalar(PH_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
+      cg_scalar(PH_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol_rr, maxit,
                 c->d_count, s);
       HIPCHK(hipGetLastError());
       if (read_count(c) == 0) break;
@@ -1172,7 +1179,8 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
   auto iterate = [&](int count) {
     for (int it = 0; it < count; ++it) {
       krylov_step(c, P, mg, it);
-      cg(PH_RR, P->d_partial);
+      cg_scalar(PH_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial,
+                fmg_applies(c, P) ? c->fmg_margin * rtol : rtol, maxit, c->d_count, s);
       if (mg) {
         precondition(c, P);
         cg(PH_RZ, P->d_partial);
@@ -1719,10 +1727,6 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     // autotuner's choice for FP64, FP32 and bfloat16-coefficient V-cycles
     c->nu = 2;
     c->cheb_lo = 0.15;
-    // measured: with FP32 cycles the full-multigrid start saves more than it
-    // costs; with FP64 cycles its cycles, the r0 pass and the extra restarts
-    // near the FP64 residual floor cost more than the iterations saved
-    c->fmg = c->mixed;
     if (const char* e = getenv("MLSGD_NU")) c->nu = std::max(1, atoi(e));
     if (const char* e = getenv("MLSGD_OMEGA")) c->omega = atof(e);
     if (const char* e = getenv("MLSGD_CACHE64")) c->cache64 = atoi(e) != 0;
@@ -1739,6 +1743,8 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     if (const char* e = getenv("MLSGD_VSMALL")) c->vsmall = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_XDEFER")) c->xdefer = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_FMG")) c->fmg = atoi(e) != 0;
+    if (const char* e = getenv("MLSGD_FMG_MARGIN")) c->fmg_margin = atof(e);
+    if (!(c->fmg_margin > 0.0 && c->fmg_margin <= 1.0)) c->fmg_margin = 0.5;
     c->nfin = pb->grid_n[pb->n_levels - 1];
     const size_t NF = cube(c->nfin);
     c->d_f = (double*)dalloc(c.get(), sizeof(double) * NF);
