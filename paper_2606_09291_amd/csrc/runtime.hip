@@ -989,6 +989,10 @@ void fmg_start(mlsgd_ctx* c, Plan* P) {
     march_jac<T>(g, nullptr, nullptr, mg_view<T>(L).B, mg_view<T>(L).X, 1, 1.0, nullptr, nullptr,
                  0, s);
     L.cur = 0;
+    for (auto& gr : P->groups)
+      if (gr.sl == S - 1)
+        copy_active_rows<T>(gr.n, gr.count, gr.p0, P->d_scal,
+                            mg_view<T>(L).X + (size_t)gr.p0 * srow(gr.n), gr.x, s);
   }
   for (int k = S - 2; k >= 0; --k) {
     SizeLvl& L = P->sizes[k];
