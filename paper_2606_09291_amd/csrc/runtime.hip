@@ -185,7 +185,7 @@ struct mlsgd_ctx {
   bool vsmall = true;       // the cycle from 9^3 down as one kernel where it applies
   bool xdefer = true;       // x's Krylov step applied by the next matvec
   bool fmg = true;          // full-multigrid start of the Krylov solves
-  double fmg_margin = 0.5;  // recursive-residual target as a fraction of rtol after that start
+  double fmg_margin = 0.7;  // recursive-residual target as a fraction of rtol after that start
   // event timing of the smoothing passes on one grid size (roofline figures)
   struct Timing {
     bool on = false;
@@ -1088,10 +1088,10 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
             c->d_count, s);
   fmg(c, P);
   // after a full-multigrid start r0 carries the evaluation error of b - A x0
-  // (near the FP64 residual floor, a few tenths of rtol on 129^3 grids), which
-  // the recursion keeps; a recursive target of half of rtol leaves room for
-  // it, so the true-residual check at exit (still against rtol) rarely has to
-  // restart a solve
+  // (near the FP64 residual floor, about 0.3 rtol on 129^3 grids), which the
+  // recursion keeps; a recursive target of 0.7 rtol leaves room for it, so the
+  // true-residual check at exit (still against rtol) rarely has to restart a
+  // solve
   const double rtol_rr = fmg_applies(c, P) ? c->fmg_margin * rtol : rtol;
   for (int restart = 0; restart < 3; ++restart) {
     if (mg && c->mixed) {
@@ -1748,7 +1748,7 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     if (const char* e = getenv("MLSGD_XDEFER")) c->xdefer = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_FMG")) c->fmg = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_FMG_MARGIN")) c->fmg_margin = atof(e);
-    if (!(c->fmg_margin > 0.0 && c->fmg_margin <= 1.0)) c->fmg_margin = 0.5;
+    if (!(c->fmg_margin > 0.0 && c->fmg_margin <= 1.0)) c->fmg_margin = 0.7;
     c->nfin = pb->grid_n[pb->n_levels - 1];
     const size_t NF = cube(c->nfin);
     c->d_f = (double*)dalloc(c.get(), sizeof(double) * NF);
