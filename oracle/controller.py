@@ -7,7 +7,9 @@ iteration's statistics; the factor is 2/eps^2, which makes the sampling
 error of the unrounded batch exactly eps^2/2 (the stated target); the cost
 per sample is the number of interior unknowns of the fine and coarse grid;
 the bias estimate extrapolates each level's correction to the finest level
-with the fitted rate; eps = 0.9 |g| of the gradient just computed.
+with the fitted rate; eps = 0.9 |g| of the gradient just computed; every
+level's batch, an added level's included, is capped at the number of samples
+whose solver arrays fit a 32 GiB share of device memory (batch_cap).
 """
 import math
 
@@ -25,6 +27,14 @@ def level_costs(grid):
     return C
 
 
+def batch_cap(n):
+    """Largest batch of one level on an n^3 grid: the samples whose solver
+    arrays (14 arrays of n^3 doubles each) fit 32 GiB.  The paper bounds the
+    samples computed at once by memory (M^max in eq:optimal-parallelization)
+    without giving a number; at least 2."""
+    return max(2, math.floor(32.0 * 2 ** 30 / (14.0 * 8.0 * n ** 3)))
+
+
 def power_sums(stats, theta, L):
     """v^2_l = sum |dX - mean dX|^2 + C_hat sum |dY - mean dY|^2 (unshifted),
     C_hat = |E^ML X|^2 / E^ML[Y]^2."""
@@ -34,14 +44,21 @@ def power_sums(stats, theta, L):
     return v2, chat, sc
 
 
-def optimal_batch(v2, M, C, eps, ceil=True):
-    """M_l = (2/eps^2) sqrt(V_l / C_l) sum_l' sqrt(V_l' C_l'), V = v^2/(M-1)."""
+def optimal_batch(v2, M, C, eps, ceil=True, caps=None):
+    """M_l = (2/eps^2) sqrt(V_l / C_l) sum_l' sqrt(V_l' C_l'), V = v^2/(M-1),
+    rounded up, at least 2 and at most caps[l] when caps are given."""
     V = [v / max(m - 1, 1) for v, m in zip(v2, M)]
     tot = sum(math.sqrt(v * c) for v, c in zip(V, C))
-    raw = [(2.0 / eps ** 2) * math.sqrt(v / c) * tot for v, c in zip(V, C)]
+    with np.errstate(all="ignore"):
+        raw = [(2.0 / eps ** 2) * math.sqrt(v / c) * tot if eps > 0 else math.inf
+               for v, c in zip(V, C)]
     if not ceil:
         return raw
-    return [max(2, int(math.ceil(r))) for r in raw]
+    out = []
+    for i, r in enumerate(raw):
+        cap = caps[i] if caps is not None else math.inf
+        out.append(max(2, cap if not math.isfinite(r) or r > cap else int(math.ceil(r))))
+    return out
 
 
 def sampling_error(v2, M):
@@ -77,14 +94,14 @@ def control(stats, M, grid, theta, grad_norm, n_levels_max=None):
     v2, chat, sc = power_sums(stats, theta, L)
     eps = 0.9 * grad_norm
     C = level_costs(grid[:L])
-    Mn = optimal_batch(v2, M, C, eps)
+    Mn = optimal_batch(v2, M, C, eps, caps=[batch_cap(n) for n in grid[:L]])
     e2 = [(stats["norm2_mean_dX"][i] + chat * stats["mean_dY"][i] ** 2) * sc * sc
           for i in range(L)]
     ahat = fit_rate([math.sqrt(e) for e in e2])
     err_num = bias_estimate(e2, ahat, L)
     Lnew = L
     if n_levels_max is not None and err_num > 0.5 * eps ** 2 and L < n_levels_max:
-        Mn = Mn + [max(2, Mn[-1] // 4)]
+        Mn = Mn + [max(2, min(batch_cap(grid[L]), Mn[-1] // 4))]
         Lnew = L + 1
     return {"M_next": Mn, "L": Lnew, "err_sam": sampling_error(v2, M), "err_num": err_num,
             "eps": eps, "alpha_hat": ahat, "v2": v2}

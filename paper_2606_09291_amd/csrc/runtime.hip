@@ -1607,12 +1607,19 @@ int run_estimate(mlsgd_ctx* c, const double* u, int L, const int64_t* M, const i
 // X, Y (statistics are rescaled by e^{theta s}).  Costs: the deterministic
 // model C_i = interior unknowns (fine + coarse) per sample, so the batch
 // sequence is reproducible.  eps = 0.9 |g| of the gradient just computed.
-// M is capped by what fits a 32 GiB share of device memory per level.
+// Every level's batch, an added level's included, is capped at the samples
+// whose solver arrays (14 arrays of n^3 doubles each) fit 32 GiB.
 struct CtrlOut {
   int64_t M[MLSGD_MAX_LEVELS];
   int L;
   double err_sam, err_num, eps, alpha_hat;
 };
+
+// Largest batch of one level on an n^3 grid (at least 2).
+int64_t batch_cap(int n) {
+  const double per_sample = 14.0 * 8.0 * (double)n * n * n;
+  return std::max<int64_t>(2, (int64_t)std::floor(32.0 * (double)(1ull << 30) / per_sample));
+}
 
 CtrlOut controller(const mlsgd_ctx* c, const mlsgd_grad_stats& g, int L, const int64_t* M) {
   CtrlOut o{};
@@ -1637,9 +1644,7 @@ CtrlOut controller(const mlsgd_ctx* c, const mlsgd_grad_stats& g, int L, const i
     err_sam += v2[i] / (Mi * std::max(Mi - 1.0, 1.0));
     double mo = (2.0 / (eps * eps)) *
                 std::sqrt(v2[i] / ((double)std::max<int64_t>(M[i] - 1, 1) * C[i])) * sum;
-    const double n = (double)c->pb.grid_n[i];
-    const double per_sample = 14.0 * 8.0 * n * n * n;            // arrays a sample occupies
-    const double mmax = std::max(2.0, std::floor(32.0 * (1ull << 30) / per_sample));
+    const double mmax = (double)batch_cap(c->pb.grid_n[i]);
     if (!std::isfinite(mo) || mo > mmax) mo = mmax;
     o.M[i] = std::max<int64_t>(2, (int64_t)std::ceil(mo));
   }
@@ -1673,7 +1678,7 @@ CtrlOut controller(const mlsgd_ctx* c, const mlsgd_grad_stats& g, int L, const i
   // level update: one more level when the bias dominates (capped at the grid list)
   o.L = L;
   if (err_num > 0.5 * eps * eps && L < c->pb.n_levels) {
-    o.M[L] = std::max<int64_t>(2, o.M[L - 1] / 4);
+    o.M[L] = std::max<int64_t>(2, std::min<int64_t>(batch_cap(c->pb.grid_n[L]), o.M[L - 1] / 4));
     o.L = L + 1;
   }
   return o;

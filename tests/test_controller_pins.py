@@ -97,3 +97,18 @@ def test_adaptive_step_is_exact_line_search_on_quadratics():
                                   np.linalg.norm(gc0))
             assert t == pytest.approx(1.0 / (c * lam[j]), rel=1e-12)
     assert ctl.adaptive_step(1.0, 2.0, 0.5, 0.1, 1.0) == 0.0
+
+
+def test_batch_cap_bounds_every_level_including_an_added_one():
+    """A vanishing eps asks for unbounded batches; each level, and the level
+    the bias adds, stays within the samples whose 14 solver arrays of n^3
+    doubles fit 32 GiB (257^3: 18 samples; 9^3: 420 827)."""
+    assert ctl.batch_cap(257) == 18 and ctl.batch_cap(9) == 420827
+    assert ctl.batch_cap(1025) == 2
+    stats = {"s": 0.0, "EY_shifted": 1.0, "norm2_EX": 1.0,
+             "m2_dX": [3.0, 1.0, 0.5], "m2_dY": [0.0, 0.0, 0.0],
+             "norm2_mean_dX": [1.0, 0.5, 0.4], "mean_dY": [1.0, 0.0, 0.0]}
+    grid = [65, 129, 257, 513]
+    out = ctl.control(stats, [4, 4, 4], grid, theta=0.0, grad_norm=1e-9, n_levels_max=4)
+    assert out["L"] == 4
+    assert out["M_next"] == [ctl.batch_cap(n) for n in grid]

@@ -348,59 +348,63 @@ def test_gradient_matches_central_differences(orc, grid, M, theta):
         assert fd == pytest.approx(an, rel=1e-6, abs=1e-11)
 
 
-def test_mlmc_brute_force_numpy(orc):
-    """Brute-force MLMC on {5,9,17}^3 with LAPACK dense solves on the oracle's
-    matrices and numpy transfers written from the definitions."""
+def _fw_numpy(nf, x):
+    """Full weighting written from its definition: the tensor product of the
+    1-D weights (1/4, 1/2, 1/4) around every coarse interior vertex."""
+    nc = (nf - 1) // 2 + 1
+    w = {-1: 0.25, 0: 0.5, 1: 0.25}
+    out = np.zeros((nc, nc, nc))
+    for jx in range(1, nc - 1):
+        for jy in range(1, nc - 1):
+            for jz in range(1, nc - 1):
+                s = 0.0
+                for dx in (-1, 0, 1):
+                    for dy in (-1, 0, 1):
+                        for dz in (-1, 0, 1):
+                            s += w[dx] * w[dy] * w[dz] * x[2 * jx + dx, 2 * jy + dy, 2 * jz + dz]
+                out[jx, jy, jz] = s
+    return out
+
+
+def _zero_boundary(x):
+    x = x.copy()
+    x[0] = x[-1] = 0
+    x[:, 0] = x[:, -1] = 0
+    x[:, :, 0] = x[:, :, -1] = 0
+    return x
+
+
+def _tri_numpy(nc, x):
+    """Trilinear interpolation as the tensor product of 1-D linear
+    interpolation matrices."""
+    nf = 2 * (nc - 1) + 1
+    P1 = np.zeros((nf, nc))
+    for i in range(nf):
+        if i % 2 == 0:
+            P1[i, i // 2] = 1.0
+        else:
+            P1[i, i // 2] = 0.5
+            P1[i, i // 2 + 1] = 0.5
+    out = np.einsum("ia,jb,kc,abc->ijk", P1, P1, P1, _zero_boundary(x))
+    return _zero_boundary(out)
+
+
+def _brute_force_mlmc(orc, grid, M, theta, alpha, seed, u, f, yd_L, first=None, sigma2=1.0):
+    """The MLMC estimate and its per-level statistics written out from Sec. 2.2
+    (eq:gradient_estimator with the max{1, .} truncation, eq:ml_estimator_*,
+    eq:shorthand-notation, eq:delta-notation) and Sec. 4.1 (eq:sec-order-sum),
+    with LAPACK dense solves on the oracle's matrices.  Statistics are
+    returned in the oracle's reporting units: weights e^{theta (Phi - s)}
+    with s the largest misfit of the estimate."""
     import scipy.linalg as sla
-    grid, M = [5, 9, 17], [5, 3, 2]
-    theta, alpha, seed = 2.0, 1e-3, 4
+    L = len(grid)
+    first = first or [0] * L
     nL = grid[-1]
-    yd_L = inputs.target_sin(nL)
-    u = 30.0 * yd_L + inputs.random_field(nL, 2, 1.0)
-    f = inputs.constant(nL, 0.5)
-
-    def fw(nf, x):  # full weighting from the definition
-        nc = (nf - 1) // 2 + 1
-        w = {-1: 0.25, 0: 0.5, 1: 0.25}
-        out = np.zeros((nc, nc, nc))
-        for jx in range(1, nc - 1):
-            for jy in range(1, nc - 1):
-                for jz in range(1, nc - 1):
-                    s = 0.0
-                    for dx in (-1, 0, 1):
-                        for dy in (-1, 0, 1):
-                            for dz in (-1, 0, 1):
-                                s += w[dx] * w[dy] * w[dz] * x[2 * jx + dx, 2 * jy + dy, 2 * jz + dz]
-                    out[jx, jy, jz] = s
-        return out
-
-    def tri(nc, x):  # trilinear interpolation, 1-D then tensor
-        nf = 2 * (nc - 1) + 1
-        P1 = np.zeros((nf, nc))
-        for i in range(nf):
-            if i % 2 == 0:
-                P1[i, i // 2] = 1.0
-            else:
-                P1[i, i // 2] = 0.5
-                P1[i, i // 2 + 1] = 0.5
-        xm = x.copy()
-        xm[0] = xm[-1] = 0
-        xm[:, 0] = xm[:, -1] = 0
-        xm[:, :, 0] = xm[:, :, -1] = 0
-        out = np.einsum("ia,jb,kc,abc->ijk", P1, P1, P1, xm)
-        out[0] = out[-1] = 0
-        out[:, 0] = out[:, -1] = 0
-        out[:, :, 0] = out[:, :, -1] = 0
-        return out
-
-    bL = f + u
-    bL[0] = bL[-1] = 0
-    bL[:, 0] = bL[:, -1] = 0
-    bL[:, :, 0] = bL[:, :, -1] = 0
-    b = {nL: bL}
-    for i in range(len(grid) - 1, 0, -1):
-        b[grid[i - 1]] = fw(grid[i], b[grid[i]])
-    ydl = {n: yd_L[::(nL - 1) // (n - 1), ::(nL - 1) // (n - 1), ::(nL - 1) // (n - 1)] for n in grid}
+    b = {nL: _zero_boundary(f + u)}
+    for i in range(L - 1, 0, -1):
+        b[grid[i - 1]] = _fw_numpy(grid[i], b[grid[i]])
+    ydl = {n: yd_L[::(nL - 1) // (n - 1), ::(nL - 1) // (n - 1), ::(nL - 1) // (n - 1)]
+           for n in grid}
 
     def solve(n, c, rhs):
         A = orc.assemble_dense(n, c)
@@ -409,36 +413,127 @@ def test_mlmc_brute_force_numpy(orc):
             (n - 2,) * 3)
         return x
 
-    recs = []
+    def misfit(n, y):
+        return 0.5 / (n - 1) ** 3 * float(np.sum(_interior(y - ydl[n]) ** 2))
+
+    recs = []   # (level, Phi fine, P p fine, Phi coarse, P p coarse prolonged)
     for i, n in enumerate(grid):
         for m in range(M[i]):
-            c = orc.kl_coeffs(seed, i, m, 4, 1.0)
+            c = orc.kl_coeffs(seed, i, first[i] + m, 4, sigma2)
             y = solve(n, c, b[n])
             pf = solve(n, c, y - ydl[n])
-            phif = 0.5 / (n - 1) ** 3 * float(np.sum(_interior(y - ydl[n]) ** 2))
             if i > 0:
                 nc = grid[i - 1]
                 yc = solve(nc, c, b[nc])
                 pc = solve(nc, c, yc - ydl[nc])
-                phic = 0.5 / (nc - 1) ** 3 * float(np.sum(_interior(yc - ydl[nc]) ** 2))
-                recs.append((i, phif, pf, phic, tri(nc, pc)))
+                recs.append((i, misfit(n, y), pf, misfit(nc, yc), _tri_numpy(nc, pc)))
             else:
-                recs.append((i, phif, pf, None, None))
-    EY, EX = 0.0, None
+                recs.append((i, misfit(n, y), pf, None, None))
+    s = max(max(r[1] for r in recs), max(r[3] for r in recs if r[0] > 0) if L > 1 else -1e300)
+    out = {"s": s, "mean_dY": [], "norm2_mean_dX": [], "m2_dX": [], "m2_dY": [],
+           "mean_phi_f": []}
+    EY_sh, EX_sh = 0.0, None
     for i, n in enumerate(grid):
         rs = [r for r in recs if r[0] == i]
-        mx = np.mean([math.exp(theta * r[1]) * r[2] - (math.exp(theta * r[3]) * r[4] if i else 0)
-                      for r in rs], axis=0)
-        EY += np.mean([math.exp(theta * r[1]) - (math.exp(theta * r[3]) if i else 0) for r in rs])
-        EX = mx if EX is None else tri(grid[i - 1], EX) + mx
-    gref = EX / max(1.0, EY) + alpha * u
-    gref[0] = gref[-1] = 0
-    gref[:, 0] = gref[:, -1] = 0
-    gref[:, :, 0] = gref[:, :, -1] = 0
+        dX = [math.exp(theta * (r[1] - s)) * r[2]
+              - (math.exp(theta * (r[3] - s)) * r[4] if i else 0.0) for r in rs]
+        dY = [math.exp(theta * (r[1] - s)) - (math.exp(theta * (r[3] - s)) if i else 0.0)
+              for r in rs]
+        mX = sum(dX) / len(rs)
+        mY = sum(dY) / len(rs)
+        out["mean_dY"].append(mY)
+        out["norm2_mean_dX"].append(_ip(n, mX, mX))
+        out["m2_dX"].append(sum(_ip(n, d - mX, d - mX) for d in dX))
+        out["m2_dY"].append(sum((d - mY) ** 2 for d in dY))
+        out["mean_phi_f"].append(sum(r[1] for r in rs) / len(rs))
+        EY_sh += mY
+        EX_sh = mX if EX_sh is None else _tri_numpy(grid[i - 1], EX_sh) + mX
+    out["norm2_EX"] = _ip(nL, EX_sh, EX_sh)
+    EY = EY_sh * math.exp(theta * s)          # unshifted E^ML[Y]
+    EX = EX_sh * math.exp(theta * s)
+    out["EY"] = EY
+    out["truncated"] = EY < 1.0
+    out["g"] = _zero_boundary(EX / max(1.0, EY) + alpha * u)
+    out["J"] = math.log(max(1.0, EY)) / theta + 0.5 * alpha * _ip(nL, u, u)
+    return out
+
+
+def _check_against_brute_force(orc, ref, g, st, L):
+    assert np.max(np.abs(g - ref["g"])) <= 1e-12 * np.max(np.abs(ref["g"]))
+    assert st["J"] == pytest.approx(ref["J"], rel=1e-12, abs=1e-15)
+    assert bool(st["truncated"]) == ref["truncated"]
+    assert st["s"] == pytest.approx(ref["s"], rel=1e-13)
+    for key in ("mean_dY", "norm2_mean_dX", "m2_dX", "m2_dY", "mean_phi_f"):
+        for i in range(L):
+            assert st[key][i] == pytest.approx(ref[key][i], rel=1e-10, abs=1e-300), (key, i)
+    assert st["norm2_EX"] == pytest.approx(ref["norm2_EX"], rel=1e-10)
+
+
+def test_mlmc_brute_force_numpy(orc):
+    """Brute-force MLMC on {5,9,17}^3 with LAPACK dense solves on the oracle's
+    matrices and numpy transfers written from the definitions: gradient,
+    objective, shift and every per-level statistic the controller reads."""
+    grid, M = [5, 9, 17], [5, 3, 2]
+    theta, alpha, seed = 2.0, 1e-3, 4
+    nL = grid[-1]
+    yd_L = inputs.target_sin(nL)
+    u = 30.0 * yd_L + inputs.random_field(nL, 2, 1.0)
+    f = inputs.constant(nL, 0.5)
+    ref = _brute_force_mlmc(orc, grid, M, theta, alpha, seed, u, f, yd_L)
+    assert not ref["truncated"]
     pb = orc.make_problem(grid, seed=seed, theta=theta, alpha=alpha, rtol=1e-14)
     g, st = orc.mlmc_gradient(pb, f, u, yd_L, M)
-    assert np.max(np.abs(g - gref)) <= 1e-12 * np.max(np.abs(gref))
-    assert st["J"] == pytest.approx(math.log(EY) / theta + 0.5 * alpha * _ip(nL, u, u), rel=1e-12)
+    _check_against_brute_force(orc, ref, g, st, len(grid))
+    # the level statistics are not degenerate here
+    assert min(st["m2_dX"]) > 0 and min(st["m2_dY"]) > 0
+
+
+from estimator_cases import TRUNCATION_CASE  # noqa: E402
+
+
+def test_truncation_fires_and_matches_brute_force(orc):
+    """The truncated branch itself: E^ML[Y] < 0 < 1, the oracle flags it,
+    divides E^ML[X] by 1 and reports J = alpha/2 |u|^2 (log max{1, .} = 0),
+    all against the brute force."""
+    tc = TRUNCATION_CASE
+    grid, M = tc["grid"], tc["M"]
+    nL = grid[-1]
+    yd_L = tc["yd_scale"] * inputs.target_sin(nL)
+    u = tc["u_over_yd"] * yd_L
+    f = np.zeros_like(u)
+    ref = _brute_force_mlmc(orc, grid, M, tc["theta"], tc["alpha"], tc["seed"], u, f, yd_L,
+                            first=tc["first"])
+    assert ref["truncated"] and ref["EY"] < -100.0
+    pb = orc.make_problem(grid, seed=tc["seed"], theta=tc["theta"], alpha=tc["alpha"],
+                          rtol=1e-14)
+    g, st = orc.mlmc_gradient(pb, None, u, yd_L, M, first=tc["first"])
+    assert st["truncated"] == 1
+    _check_against_brute_force(orc, ref, g, st, len(grid))
+    assert st["J"] == pytest.approx(0.5 * tc["alpha"] * _ip(nL, u, u), rel=1e-13)
+    # the same estimate with the untruncated ratio would differ
+    EX = ref["g"] - tc["alpha"] * u
+    assert np.linalg.norm(EX / ref["EY"] - EX) > 0.5 * np.linalg.norm(EX)
+
+
+def test_level_statistics_vanish_without_randomness(orc):
+    """sigma = 0: every sample of a level is the same, so the power sums of
+    eq:sec-order-sum are zero, each level mean is that single value, and the
+    shifted level-0 weight is 1 at the largest misfit."""
+    grid, M = [5, 9, 17], [4, 3, 2]
+    nL = grid[-1]
+    yd = inputs.target_sin(nL)
+    u = 10.0 * yd + inputs.random_field(nL, 5, 0.5)
+    pb = orc.make_problem(grid, theta=2.0, alpha=1e-3, sigma2=0.0, rtol=1e-14)
+    g, st = orc.mlmc_gradient(pb, None, u, yd, M)
+    for i in range(len(grid)):
+        scale_x = max(st["norm2_mean_dX"][i], 1e-300)
+        assert st["m2_dX"][i] <= 1e-24 * M[i] * scale_x
+        assert st["m2_dY"][i] <= 1e-26 * M[i]
+    ref = _brute_force_mlmc(orc, grid, [1, 1, 1], 2.0, 1e-3, 0, u, np.zeros_like(u), yd,
+                            sigma2=0.0)
+    for i in range(len(grid)):
+        assert st["mean_dY"][i] == pytest.approx(ref["mean_dY"][i], rel=1e-12, abs=1e-15)
+        assert st["norm2_mean_dX"][i] == pytest.approx(ref["norm2_mean_dX"][i], rel=1e-10)
 
 
 def test_gradient_descent_closed_form_rate(orc):
@@ -458,20 +553,6 @@ def test_gradient_descent_closed_form_rate(orc):
     cstar = lam / (1 + alpha * lam * lam)
     rate = abs(1 - tau * (1 / lam ** 2 + alpha))
     assert rate < 1 and abs(ck - cstar) == pytest.approx(rate ** 4 * cstar, rel=1e-9)
-
-
-def test_truncation_flag(orc):
-    """E^ML[Y] < 1 can only happen through negative level corrections; a large
-    coarse-level misfit with theta > 0 forces it and the estimator divides by 1."""
-    grid, M = [5, 9], [1, 1]
-    yd = inputs.target_sin(9)
-    # u far from the target drives Phi up on the coarse grid of level 1 more
-    # than on the fine grid (R reduces the coarse data), so dY_1 < 0
-    u = 400.0 * inputs.random_field(9, 8)
-    pb = orc.make_problem(grid, theta=5.0, alpha=0.0, sigma2=1.0)
-    g, st = orc.mlmc_gradient(pb, None, u, yd, M)
-    EY = st["EY_shifted"] * math.exp(5.0 * st["s"])
-    assert (EY < 1.0) == bool(st["truncated"])
 
 
 # ----------------------------------------------------------------------------
