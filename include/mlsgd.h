@@ -172,6 +172,33 @@ int mlsgd_solve_state_adjoint(mlsgd_ctx* ctx, int level, int coarse,
                               double* p_out, double* phi_out,
                               mlsgd_solve_stats* st);
 
+/* Allocation-free form of mlsgd_solve_state_adjoint, for callers that
+ * cannot allocate device memory during the call: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, semantics, outputs and errors as mlsgd_solve_state_adjoint,
+ * and the same kernels; the solver rows, Krylov vectors, coefficient caches
+ * and partial sums of the call live in a fixed device array of 64 MiB
+ * (67108864 bytes) that the library holds on every GPU it runs on until the
+ * process ends, instead of a per-batch-shape arena.  The call performs no
+ * hipMalloc, hipFree or other device allocation (the context's own buffers
+ * come from mlsgd_create).  It clears the part of the array it uses before
+ * every call, so no call sees the previous call's contents.  All calls on one
+ * GPU share the array: calls that overlap in time on one GPU (two contexts,
+ * two streams, two threads) race and must be serialised by the caller.
+ * scratch_bytes: host, nullable; receives the bytes the batch needs (also
+ * when the call fails for size).  Errors: as mlsgd_solve_state_adjoint;
+ * MLSGD_EINVAL also when the batch needs more than the 64 MiB array (about
+ * 86 bytes per vertex of the solved grid in FP64: two 65^3 samples fit, three
+ * do not, and no 129^3 sample does), when kernel timing is on, or when the
+ * context's device is not current; such a call returns before any work is
+ * enqueued. */
+int mlsgd_solve_state_adjoint_noalloc(mlsgd_ctx* ctx, int level, int coarse,
+                                      int64_t first, int64_t count,
+                                      const double* u_fine, double* y_out,
+                                      double* p_out, double* phi_out,
+                                      mlsgd_solve_stats* st,
+                                      int64_t* scratch_bytes);
+
 /* Batched state solves of independent problems whose grids differ in size
  * (a batch of single-sample solves of the state equation, Sec. 2.1, on
  * grids of caller-chosen size, beside the MLMC levels).

@@ -23,7 +23,7 @@ EXPORTS = [
     "mlsgd_create", "mlsgd_destroy", "mlsgd_last_error", "mlsgd_sample_fields",
     "mlsgd_philox_words", "mlsgd_solve_state_adjoint", "mlsgd_solve_sizes", "mlsgd_mlmc_gradient",
     "mlsgd_mlmc_objective", "mlsgd_set_batch", "mlsgd_step", "mlsgd_kernel_timing",
-    "mlsgd_get_tuning", "mlsgd_set_tuning", "mlsgd_set_graph",
+    "mlsgd_get_tuning", "mlsgd_set_tuning", "mlsgd_set_graph", "mlsgd_solve_state_adjoint_noalloc",
 ]
 SMOOTHER_RBGS, SMOOTHER_RBGS_FUSED, SMOOTHER_CHEBYSHEV = 0, 1, 2
 ADAPT_BATCH, ADAPT_STEP = 1, 2
@@ -129,6 +129,8 @@ def lib():
     L.mlsgd_philox_words.argtypes = [ctypes.c_uint64, i32, i64, i32, i32, vp, vp]
     L.mlsgd_solve_state_adjoint.argtypes = [vp, i32, i32, i64, i64, vp, vp, vp, vp,
                                             P(_SolveStats)]
+    L.mlsgd_solve_state_adjoint_noalloc.argtypes = [vp, i32, i32, i64, i64, vp, vp, vp, vp,
+                                                    P(_SolveStats), P(i64)]
     L.mlsgd_solve_sizes.argtypes = [vp, i32, P(i32), i32, i64, ctypes.c_double, vp,
                                     P(_SolveStats)]
     L.mlsgd_mlmc_gradient.argtypes = [vp, vp, i32, P(i64), P(i64), vp, P(_GradStats)]
@@ -285,6 +287,24 @@ class Context:
         stats = {"iterations": st.iterations, "nonconverged": st.nonconverged,
                  "max_relres": st.max_relres}
         return y, p, phi, stats
+
+    def solve_state_adjoint_noalloc(self, level, coarse, first, count, u, y, p, phi,
+                                    allow_noconv=False):
+        """mlsgd_solve_state_adjoint_noalloc on caller-allocated outputs (device
+        float64 tensors: y and p of count*n^3 or None, phi of count or None).
+        Returns (stats, scratch bytes the batch needs)."""
+        uu = self._u(u)
+        st = _SolveStats()
+        need = ctypes.c_int64(0)
+        rc = self.lib.mlsgd_solve_state_adjoint_noalloc(
+            self._h, level, coarse, first, count, ctypes.c_void_p(uu.data_ptr()),
+            ctypes.c_void_p(y.data_ptr() if y is not None else 0),
+            ctypes.c_void_p(p.data_ptr() if p is not None else 0),
+            ctypes.c_void_p(phi.data_ptr() if phi is not None else 0), ctypes.byref(st),
+            ctypes.byref(need))
+        self._check(rc, allow_noconv)
+        return ({"iterations": st.iterations, "nonconverged": st.nonconverged,
+                 "max_relres": st.max_relres}, need.value)
 
     def solve_sizes(self, n_list, level=6, first=0, f_value=1.0, want_y=True,
                     allow_noconv=False):

@@ -21,11 +21,21 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <stdexcept>
 #include <string>
 #include <vector>
 
 using namespace mlsgd;
+
+// Device memory of mlsgd_solve_state_adjoint_noalloc: its solver rows,
+// Krylov vectors, coefficient caches and partial sums are carved from this
+// array instead of an arena of their own.  Every GPU the library runs on
+// holds one copy until the process ends.  Host code never uses the name
+// itself as an address: each device's address comes from
+// hipGetSymbolAddress at context creation (scratch_on_device).
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
 
 namespace {
 
@@ -106,6 +116,7 @@ struct Plan {
   double* d_w = nullptr;
   double* ainv = nullptr;  // coarsest-grid inverses [rows][N][N] when the hierarchy stops above 3^3
   int dense_N = 0;
+  long long npartial = 0;  // partial-sum slots (one per workgroup tile of every problem)
   void* arena = nullptr;
   size_t arena_bytes = 0;
   uint64_t last_use = 0;   // plan-cache clock at the latest get_plan
@@ -157,6 +168,8 @@ struct mlsgd_ctx {
   long long* d_dst_off = nullptr;          // packed-output offsets of one solve batch
   size_t dst_off_len = 0;
   std::vector<void*> allocs;
+  int device = 0;                          // device current at mlsgd_create
+  void* scratch = nullptr;                 // this device's address of `scratch`
   // batch used by mlsgd_step
   int cur_L = 0;
   int64_t cur_M[MLSGD_MAX_LEVELS] = {0};
@@ -286,137 +299,134 @@ void evict_plans(mlsgd_ctx* c, size_t need) {
   }
 }
 
-// Build (or reuse) the layout for a list of blocks (grid sizes
-// non-increasing) and upload this call's draws; `fields` also regenerates
-// the coefficient fields from them (kernels only: plan_fields).
-Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks, bool fields = true) {
-  std::string key;
-  for (const auto& b : blocks) key += std::to_string(b.n) + ":" + std::to_string(b.count) + ";";
-  auto it = c->plans.find(key);
-  Plan* P = nullptr;
-  const int K = c->pb.kl_K, K3 = K * K * K;
-  if (it != c->plans.end()) {
-    P = it->second.get();
-  } else {
-    auto up = std::make_unique<Plan>();
-    P = up.get();
-    P->key = key;
-    long long np = 0;
-    for (const auto& b : blocks) np += b.count;
-    require(np > 0 && np < (1LL << 30), "problem count out of range");
-    P->nprob = (int)np;
-    P->h_n.resize(np);
-    P->h_level.resize(np);
-    P->h_sample.resize(np);
-    // groups
-    int p = 0;
-    for (size_t bi = 0; bi < blocks.size(); ++bi) {
-      const Block& b = blocks[bi];
-      require(bi == 0 || b.n <= blocks[bi - 1].n, "blocks must have non-increasing grids");
-      if (P->groups.empty() || P->groups.back().n != b.n) {
-        Group g;
-        g.n = b.n;
-        g.p0 = p;
-        g.count = 0;
-        P->groups.push_back(g);
-      }
-      for (int64_t m = 0; m < b.count; ++m, ++p) P->h_n[p] = b.n;
-      P->groups.back().count += (int)b.count;
+// Host-side layout of a list of blocks (grid sizes non-increasing): problem
+// order, groups, the grid sizes of the hierarchy and the partial-sum slots.
+// Touches no device memory beyond the per-size cosine tables.
+void plan_layout(mlsgd_ctx* c, const std::vector<Block>& blocks, Plan* P) {
+  long long np = 0;
+  for (const auto& b : blocks) np += b.count;
+  require(np > 0 && np < (1LL << 30), "problem count out of range");
+  P->nprob = (int)np;
+  P->h_n.resize(np);
+  P->h_level.resize(np);
+  P->h_sample.resize(np);
+  // groups
+  int p = 0;
+  for (size_t bi = 0; bi < blocks.size(); ++bi) {
+    const Block& b = blocks[bi];
+    require(bi == 0 || b.n <= blocks[bi - 1].n, "blocks must have non-increasing grids");
+    if (P->groups.empty() || P->groups.back().n != b.n) {
+      Group g;
+      g.n = b.n;
+      g.p0 = p;
+      g.count = 0;
+      P->groups.push_back(g);
     }
-    // grid sizes from the largest top grid down to 3, or down to the first
-    // grid with an odd number of cells, which cannot be coarsened further
-    int nmax = blocks.front().n;
-    for (int n = nmax;; n = (n - 1) / 2 + 1) {
-      SizeLvl s;
-      s.n = n;
-      s.t = make_tiling(n, c->tile_y, c->xchunk);
-      int rows = 0, top = 0;
-      for (int q = 0; q < P->nprob; ++q) {
-        if (P->h_n[q] >= n) rows = q + 1;
-        if (P->h_n[q] > n) top = q + 1;
-      }
-      s.rows = rows;
-      s.top_begin = top;
-      s.cosT = cos_for(c, n);
-      P->sizes.push_back(s);
-      if (n <= 3 || ((n - 1) & 1)) break;
-    }
-    {
-      const SizeLvl& co = P->sizes.back();
-      if (co.n > 3) {
-        require(co.n <= 9, "the grid hierarchy must coarsen to at most 9^3");
-        require(P->sizes.size() >= 2 && co.top_begin == co.rows,
-                "a top grid cannot be the dense coarsest grid");
-        P->dense_N = (co.n - 2) * (co.n - 2) * (co.n - 2);
-      }
-    }
-    for (auto& g : P->groups) {
-      for (size_t k = 0; k < P->sizes.size(); ++k)
-        if (P->sizes[k].n == g.n) g.sl = (int)k;
-    }
-    P->h_pcnt.resize(np);
-    P->h_poff.resize(np);
-    long long off = 0;
-    for (int q = 0; q < P->nprob; ++q) {
-      P->h_pcnt[q] = make_tiling(P->h_n[q], c->tile_y, c->xchunk).tiles_per_row;
-      P->h_poff[q] = (int)off;
-      off += P->h_pcnt[q];
-    }
-    require(off < (1LL << 31), "partial buffer too large");
-    // carve (twice: measure, then assign)
-    for (int pass = 0; pass < 2; ++pass) {
-      Carver cv{pass == 0 ? nullptr : (char*)P->arena};
-      for (auto& s : P->sizes) {
-        const size_t e = (size_t)s.rows * srow(s.n);
-        s.B = cv.take<double>(e);
-        if (!c->mixed) {
-          s.X = cv.take<double>(e);
-          s.R = cv.take<double>(e);
-        } else {
-          s.Xf = cv.take<float>(e);
-          s.Bf = cv.take<float>(e);
-          s.Rf = cv.take<float>(e);
-          if (c->cache32 && c->bf16) s.Cb = cv.take<uint16_t>(e);
-          else if (c->cache32) s.Cf = cv.take<float>(e);
-          if (c->cache32) s.Dif = cv.take<float>(e);
-        }
-        if (c->cache64) s.C = cv.take<double>(e);
-        if (c->cache64 && !c->mixed) s.Di = cv.take<double>(e);
-      }
-      for (auto& g : P->groups) {
-        const size_t e = (size_t)g.count * srow(g.n);
-        g.x = cv.take<double>(e);
-        g.q = cv.take<double>(e);
-        g.b0 = cv.take<double>(e);
-        g.p[0] = cv.take<double>(e);
-        g.p[1] = cv.take<double>(e);
-      }
-      P->d_level = cv.take<int>(np);
-      P->d_sample = cv.take<int64_t>(np);
-      P->d_coef = cv.take<double>((size_t)np * K3);
-      P->d_scal = cv.take<CgScal>(np);
-      P->d_poff = cv.take<int>(np);
-      P->d_pcnt = cv.take<int>(np);
-      P->d_partial = cv.take<double>((size_t)off);
-      P->d_phi = cv.take<double>(np);
-      P->d_w = cv.take<double>(np);
-      if (P->dense_N)
-        P->ainv = cv.take<double>((size_t)P->sizes.back().rows * P->dense_N * P->dense_N);
-      if (pass == 0) {
-        P->arena_bytes = cv.off + 256;
-        evict_plans(c, P->arena_bytes);
-        P->arena = dalloc(c, P->arena_bytes);
-      }
-    }
-    HIPCHK(hipMemsetAsync(P->arena, 0, P->arena_bytes, c->stream));
-    HIPCHK(hipMemcpyAsync(P->d_poff, P->h_poff.data(), sizeof(int) * np, hipMemcpyHostToDevice,
-                          c->stream));
-    HIPCHK(hipMemcpyAsync(P->d_pcnt, P->h_pcnt.data(), sizeof(int) * np, hipMemcpyHostToDevice,
-                          c->stream));
-    c->plans[key] = std::move(up);
+    for (int64_t m = 0; m < b.count; ++m, ++p) P->h_n[p] = b.n;
+    P->groups.back().count += (int)b.count;
   }
-  P->last_use = ++c->plan_clock;
-  // draws of this call
+  // grid sizes from the largest top grid down to 3, or down to the first
+  // grid with an odd number of cells, which cannot be coarsened further
+  int nmax = blocks.front().n;
+  for (int n = nmax;; n = (n - 1) / 2 + 1) {
+    SizeLvl s;
+    s.n = n;
+    s.t = make_tiling(n, c->tile_y, c->xchunk);
+    int rows = 0, top = 0;
+    for (int q = 0; q < P->nprob; ++q) {
+      if (P->h_n[q] >= n) rows = q + 1;
+      if (P->h_n[q] > n) top = q + 1;
+    }
+    s.rows = rows;
+    s.top_begin = top;
+    s.cosT = cos_for(c, n);
+    P->sizes.push_back(s);
+    if (n <= 3 || ((n - 1) & 1)) break;
+  }
+  {
+    const SizeLvl& co = P->sizes.back();
+    if (co.n > 3) {
+      require(co.n <= 9, "the grid hierarchy must coarsen to at most 9^3");
+      require(P->sizes.size() >= 2 && co.top_begin == co.rows,
+              "a top grid cannot be the dense coarsest grid");
+      P->dense_N = (co.n - 2) * (co.n - 2) * (co.n - 2);
+    }
+  }
+  for (auto& g : P->groups) {
+    for (size_t k = 0; k < P->sizes.size(); ++k)
+      if (P->sizes[k].n == g.n) g.sl = (int)k;
+  }
+  P->h_pcnt.resize(np);
+  P->h_poff.resize(np);
+  long long off = 0;
+  for (int q = 0; q < P->nprob; ++q) {
+    P->h_pcnt[q] = make_tiling(P->h_n[q], c->tile_y, c->xchunk).tiles_per_row;
+    P->h_poff[q] = (int)off;
+    off += P->h_pcnt[q];
+  }
+  require(off < (1LL << 31), "partial buffer too large");
+  P->npartial = off;
+}
+
+// Assign the plan's arrays inside the arena at `base` (nullptr: only
+// measure); returns the arena bytes the layout needs.
+size_t plan_carve(mlsgd_ctx* c, Plan* P, char* base) {
+  const int K = c->pb.kl_K, K3 = K * K * K;
+  const long long np = P->nprob;
+  Carver cv{base};
+  for (auto& s : P->sizes) {
+    const size_t e = (size_t)s.rows * srow(s.n);
+    s.B = cv.take<double>(e);
+    if (!c->mixed) {
+      s.X = cv.take<double>(e);
+      s.R = cv.take<double>(e);
+    } else {
+      s.Xf = cv.take<float>(e);
+      s.Bf = cv.take<float>(e);
+      s.Rf = cv.take<float>(e);
+      if (c->cache32 && c->bf16) s.Cb = cv.take<uint16_t>(e);
+      else if (c->cache32) s.Cf = cv.take<float>(e);
+      if (c->cache32) s.Dif = cv.take<float>(e);
+    }
+    if (c->cache64) s.C = cv.take<double>(e);
+    if (c->cache64 && !c->mixed) s.Di = cv.take<double>(e);
+  }
+  for (auto& g : P->groups) {
+    const size_t e = (size_t)g.count * srow(g.n);
+    g.x = cv.take<double>(e);
+    g.q = cv.take<double>(e);
+    g.b0 = cv.take<double>(e);
+    g.p[0] = cv.take<double>(e);
+    g.p[1] = cv.take<double>(e);
+  }
+  P->d_level = cv.take<int>(np);
+  P->d_sample = cv.take<int64_t>(np);
+  P->d_coef = cv.take<double>((size_t)np * K3);
+  P->d_scal = cv.take<CgScal>(np);
+  P->d_poff = cv.take<int>(np);
+  P->d_pcnt = cv.take<int>(np);
+  P->d_partial = cv.take<double>((size_t)P->npartial);
+  P->d_phi = cv.take<double>(np);
+  P->d_w = cv.take<double>(np);
+  if (P->dense_N)
+    P->ainv = cv.take<double>((size_t)P->sizes.back().rows * P->dense_N * P->dense_N);
+  return ((cv.off + 255) & ~(size_t)255) + 256;
+}
+
+// Zero a freshly assigned arena (a fill kernel, so no memset node is ever
+// recorded) and upload the partial-sum slots.
+void plan_init(mlsgd_ctx* c, Plan* P) {
+  rows_zero((long long)(P->arena_bytes / sizeof(double)), (double*)P->arena, c->stream);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(P->d_poff, P->h_poff.data(), sizeof(int) * P->nprob,
+                        hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemcpyAsync(P->d_pcnt, P->h_pcnt.data(), sizeof(int) * P->nprob,
+                        hipMemcpyHostToDevice, c->stream));
+}
+
+// Upload the (level, sample) keys of this call's draws; `fields` also
+// regenerates the coefficient fields from them (kernels only: plan_fields).
+void plan_draws(mlsgd_ctx* c, Plan* P, const std::vector<Block>& blocks, bool fields) {
   int p = 0;
   for (const auto& b : blocks)
     for (int64_t m = 0; m < b.count; ++m, ++p) {
@@ -428,6 +438,31 @@ Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks, bool fields = tru
   HIPCHK(hipMemcpyAsync(P->d_sample, P->h_sample.data(), sizeof(int64_t) * P->nprob,
                         hipMemcpyHostToDevice, c->stream));
   if (fields) plan_fields(c, P);
+}
+
+// Build (or reuse) the layout for a list of blocks (grid sizes
+// non-increasing) in an arena of its own and upload this call's draws.
+Plan* get_plan(mlsgd_ctx* c, const std::vector<Block>& blocks, bool fields = true) {
+  std::string key;
+  for (const auto& b : blocks) key += std::to_string(b.n) + ":" + std::to_string(b.count) + ";";
+  auto it = c->plans.find(key);
+  Plan* P = nullptr;
+  if (it != c->plans.end()) {
+    P = it->second.get();
+  } else {
+    auto up = std::make_unique<Plan>();
+    P = up.get();
+    P->key = key;
+    plan_layout(c, blocks, P);
+    P->arena_bytes = plan_carve(c, P, nullptr);
+    evict_plans(c, P->arena_bytes);
+    P->arena = dalloc(c, P->arena_bytes);
+    plan_carve(c, P, (char*)P->arena);
+    plan_init(c, P);
+    c->plans[key] = std::move(up);
+  }
+  P->last_use = ++c->plan_clock;
+  plan_draws(c, P, blocks, fields);
   return P;
 }
 
@@ -1684,6 +1719,52 @@ CtrlOut controller(const mlsgd_ctx* c, const mlsgd_grad_stats& g, int L, const i
   return o;
 }
 
+// Address of `scratch` on each device, looked up once per device with that
+// device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {nullptr};
+
+void* scratch_on_device(int dev) {
+  require(dev >= 0 && dev < kMaxDevices, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* ptr = nullptr;
+    HIPCHK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+    require(ptr != nullptr, "no device address for the scratch array");
+    g_scratch_addr[dev] = ptr;
+  }
+  return g_scratch_addr[dev];
+}
+
+// State (and adjoint) solves of one level block on a prepared plan; shared
+// by mlsgd_solve_state_adjoint and its allocation-free variant.
+int solve_block(mlsgd_ctx* c, Plan* P, int n, int64_t count, double* y_out, double* p_out,
+                double* phi_out, mlsgd_solve_stats* st) {
+  int it1 = 0, nc1 = 0, it2 = 0, nc2 = 0;
+  double r1 = 0, r2 = 0;
+  state_phase(c, P, &it1, &nc1, &r1, y_out);
+  if (phi_out)
+    HIPCHK(hipMemcpyAsync(phi_out, P->d_phi, sizeof(double) * count, hipMemcpyDeviceToDevice,
+                          c->stream));
+  if (p_out) {
+    krylov(c, P, &it2, &nc2, &r2);
+    unpack_rows(n, (int)count, P->groups[0].x, p_out, c->stream);
+  }
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(c->stream));
+  if (st) {
+    st->iterations = std::max(it1, it2);
+    st->nonconverged = nc1 + nc2;
+    st->max_relres = std::max(r1, r2);
+  }
+  if (nc1 + nc2 > 0) {
+    c->err = "some solves missed rtol";
+    return MLSGD_ENOCONV;
+  }
+  return MLSGD_OK;
+}
+
 int guard_impl(mlsgd_ctx* c, const std::function<int()>& fn) {
   try {
     if (c) c->err.clear();
@@ -1788,6 +1869,15 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     HIPCHK(hipHostMalloc((void**)&c->h_stat, 2 * sizeof(mlsgd_ctx::StatDev),
                          hipHostMallocDefault));
     for (auto& e : c->ev) HIPCHK(hipEventCreate(&e));
+    // every grid of the hierarchy gets its cosine table now, so that a solve
+    // on these grids allocates nothing but its plan's arena
+    for (int i = 0; i < pb->n_levels; ++i)
+      for (int n = pb->grid_n[i];; n = (n - 1) / 2 + 1) {
+        cos_for(c.get(), n);
+        if (n <= 3) break;
+      }
+    HIPCHK(hipGetDevice(&c->device));
+    c->scratch = scratch_on_device(c->device);
     c->cur_L = pb->n_levels;
     HIPCHK(hipStreamSynchronize(c->stream));
     return MLSGD_OK;
@@ -1935,28 +2025,42 @@ int mlsgd_solve_state_adjoint(mlsgd_ctx* c, int level, int coarse, int64_t first
     level_rhs(c, u);
     std::vector<Block> b{Block{n, level, first, count}};
     Plan* P = get_plan(c, b);
-    int it1 = 0, nc1 = 0, it2 = 0, nc2 = 0;
-    double r1 = 0, r2 = 0;
-    state_phase(c, P, &it1, &nc1, &r1, y_out);
-    if (phi_out)
-      HIPCHK(hipMemcpyAsync(phi_out, P->d_phi, sizeof(double) * count, hipMemcpyDeviceToDevice,
-                            c->stream));
-    if (p_out) {
-      krylov(c, P, &it2, &nc2, &r2);
-      unpack_rows(n, (int)count, P->groups[0].x, p_out, c->stream);
-    }
-    HIPCHK(hipGetLastError());
-    HIPCHK(hipStreamSynchronize(c->stream));
-    if (st) {
-      st->iterations = std::max(it1, it2);
-      st->nonconverged = nc1 + nc2;
-      st->max_relres = std::max(r1, r2);
-    }
-    if (nc1 + nc2 > 0) {
-      c->err = "some solves missed rtol";
-      return MLSGD_ENOCONV;
-    }
-    return MLSGD_OK;
+    return solve_block(c, P, n, count, y_out, p_out, phi_out, st);
+  });
+}
+
+int mlsgd_solve_state_adjoint_noalloc(mlsgd_ctx* c, int level, int coarse, int64_t first,
+                                      int64_t count, const double* u, double* y_out,
+                                      double* p_out, double* phi_out, mlsgd_solve_stats* st,
+                                      int64_t* scratch_bytes) {
+  if (!c) return MLSGD_EINVAL;
+  return guard_impl(c, [&]() -> int {
+    require(level >= 0 && level < c->pb.n_levels, "level out of range");
+    require(coarse == 0 || (coarse == 1 && level >= 1), "coarse solve needs level >= 1");
+    require(first >= 0 && count >= 1, "need first >= 0 and count >= 1");
+    require(!c->tm.on, "kernel timing is on (its event pool may grow)");
+    require(c->scratch != nullptr, "no scratch address for this context's device");
+    int dev = -1;
+    HIPCHK(hipGetDevice(&dev));
+    require(dev == c->device, "the context's device must be current");
+    const int n = c->pb.grid_n[level - coarse];
+    std::vector<Block> b{Block{n, level, first, count}};
+    Plan T;   // transient: never enters the plan cache
+    plan_layout(c, b, &T);
+    const size_t need = plan_carve(c, &T, nullptr);
+    if (scratch_bytes) *scratch_bytes = (int64_t)need;
+    if (need > kScratchBytes)
+      throw Fail{MLSGD_EINVAL, "the batch needs " + std::to_string(need) +
+                                   " bytes of scratch; the limit is " +
+                                   std::to_string(kScratchBytes)};
+    check_u(c, u);
+    level_rhs(c, u);
+    T.arena = c->scratch;
+    T.arena_bytes = need;
+    plan_carve(c, &T, (char*)c->scratch);
+    plan_init(c, &T);   // the array keeps the previous call's contents
+    plan_draws(c, &T, b, true);
+    return solve_block(c, &T, n, count, y_out, p_out, phi_out, st);
   });
 }
 
