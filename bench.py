@@ -13,6 +13,7 @@ theta = 10, same grids and counts) is reported beside it.
 Prints one JSON line.  --gpus N > 1 is not supported (one GPU per run).
 """
 import argparse
+import dataclasses
 import hashlib
 import json
 import os
@@ -27,8 +28,18 @@ METRIC = "MLMC gradient estimates/s + state/adjoint solves/s, mixed vs FP64, % H
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILES = {  # committed counter summaries of the timed kernel, by timing kind
     2: os.path.join(ROOT, "profiles", "traffic_post_smoothing_129.json"),
-    1: os.path.join(ROOT, "profiles", "traffic_jacobi_step_129.json"),
 }
+# Bytes per interior point of the timed kernels by timing kind and element
+# size: the algorithmic bytes (coefficient regenerated, so 0 bytes) and the
+# per-call coefficient cache the kernels read on top of them.
+#   kind 2, fused post-smoothing pass: x and b read, x'' written, coarse
+#     correction read once (1/8 point);
+#   kind 1, plain smoothing step: x and b read, x' written.
+ALG_BYTES_PER_POINT = {2: lambda e: 3.0 * e + e / 8.0, 1: lambda e: 3.0 * e}
+# (kind 1 also has launches from a zero start, 2e, and with a folded
+# correction, 3e + e/8; the library reports each launch's own bytes)
+CACHE_BYTES_PER_POINT = {"fp64": 8.0, "mixed": 4.0, "mixed_bf16": 2.0}
+ELEM_BYTES = {"fp64": 8.0, "mixed": 4.0, "mixed_bf16": 4.0}
 
 
 def parse():
@@ -332,31 +343,117 @@ def run_mlsgd(args):
     print(json.dumps(out), flush=True)
 
 
-def cpu_baseline(w, threads):
-    """The oracle timed on the host cores: per level i, P pairs of level i
-    (fine + coarse state and adjoint solves) run on P threads; the per-pair
-    throughput of every level is extrapolated to the workload's M."""
+def host_threads():
+    """Host threads the oracle may use: the CPUs this process may run on,
+    bounded by OMP_NUM_THREADS where the environment sets it (the share of
+    the host that comes with one GPU)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    omp = os.environ.get("OMP_NUM_THREADS")
+    if omp and omp.isdigit() and int(omp) > 0:
+        n = min(n, int(omp))
+    return max(1, n)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def first_estimate(m, w, dev):
+    """One estimate of workload w at sample offsets 0 (the draws the oracle
+    reproduces for the accuracy figures), as a host array."""
+    import torch
+    ctx = make_ctx(m, w, dev)
+    u = torch.as_tensor(w.u0(), device=dev).contiguous()
+    g, _ = ctx.mlmc_gradient(u, w.M, first=[0] * len(w.M))
+    ctx.close()
+    return g.cpu().numpy()
+
+
+def cpu_baseline(w, threads, acc_grads):
+    """The oracle on the host cores.  Baseline: one complete estimate of the
+    headline workload w (every pair of every level, offsets 0) on `threads`
+    OpenMP threads, timed.  Accuracy: the relative L2 error of each GPU
+    estimate in acc_grads (same workload data and draws) against the oracle's
+    estimate of it; workloads sharing problem data share one oracle run."""
+    import numpy as np
     import oracle
-    from paper_2606_09291_amd import inputs
-    P = threads
-    per_pair = []
-    for i in range(len(w.grid_n)):
-        grid = w.grid_n[:i + 1]
-        nL = grid[-1]
-        yd = inputs.target_sin(nL)
-        u = inputs.control_xyz(nL)
-        pb = oracle.make_problem(grid, K=w.K, sigma2=w.sigma2, theta=w.theta, alpha=w.alpha,
-                                 rtol=w.rtol, nthreads=P)
-        M = [1] * i + [P]
-        t = time.perf_counter()
-        oracle.mlmc_gradient(pb, None, u, yd, M)
-        per_pair.append((time.perf_counter() - t) / P)
-    est = sum(mm * tp for mm, tp in zip(w.M, per_pair))
-    return {"value": 1.0 / est, "unit": "gradient estimates/s", "cores": P, "kind": "oracle",
-            "sample": (f"per level i, {P} pairs of level i (plus one pair of each lower level) "
-                       f"on {P} threads; per-pair wall times {[round(x, 4) for x in per_pair]} s "
-                       f"extrapolated to M={list(w.M)}"),
-            "seconds_per_estimate": est}
+    pb = oracle.make_problem(w.grid_n, K=w.K, sigma2=w.sigma2, theta=w.theta, alpha=w.alpha,
+                             rtol=w.rtol, nthreads=threads)
+    t = time.perf_counter()
+    g_ref, st = oracle.mlmc_gradient(pb, w.f() if w.f_value else None, w.u0(), w.y_d(), w.M,
+                                     first=[0] * len(w.M))
+    sec = time.perf_counter() - t
+    base = {"value": 1.0 / sec, "unit": "gradient estimates/s", "cores": threads,
+            "kind": "oracle",
+            "sample": (f"one complete estimate of the headline workload (M={list(w.M)}, "
+                       f"{sum(w.M)} level pairs, state and adjoint solves), FP64 MG-PCG to "
+                       f"rtol {w.rtol}, OpenMP over the pairs"),
+            "seconds_per_estimate": sec, "nproc": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
+            else None,
+            "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS"),
+            "cpu_model": cpu_model(), "oracle_max_iters": st["max_iters"]}
+    refs = {}
+
+    def key_of(wk):
+        return (tuple(wk.grid_n), tuple(wk.M), wk.K, wk.sigma2, wk.theta, wk.alpha, wk.f_value,
+                wk.law, wk.rho, wk.seed)
+
+    refs[key_of(w)] = g_ref
+    errs = {}
+    for name, (wk, g) in acc_grads.items():
+        k = key_of(wk)
+        if k not in refs:
+            pbk = oracle.make_problem(wk.grid_n, K=wk.K, sigma2=wk.sigma2, theta=wk.theta,
+                                      alpha=wk.alpha, rtol=1e-12, nthreads=threads)
+            refs[k], _ = oracle.mlmc_gradient(pbk, wk.f() if wk.f_value else None, wk.u0(),
+                                              wk.y_d(), wk.M, first=[0] * len(wk.M))
+        r = refs[k]
+        errs[name] = float(np.linalg.norm(g - r) / np.linalg.norm(r))
+    return base, errs
+
+
+def roofline(tm, kind, n, precision):
+    """Roofline record of the timed kernel: algorithmic bytes per launch (the
+    interior points times ALG_BYTES_PER_POINT) over its average launch time
+    from live HIP events, against 8 TB/s.  The coefficient-cache bytes the
+    kernel also reads are reported beside, not counted."""
+    launches = tm["launches"]
+    if not launches:
+        return {"kernel": KERNEL_NAMES[kind].format(n=n), "bound": "hbm", "achieved": None,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": None, "traffic": None}
+    avg_ms = tm["ms"] / launches
+    alg = tm["bytes"] / launches
+    e = ELEM_BYTES[precision]
+    achieved = alg / (avg_ms * 1e-3) / 1e9
+    # kind 2 launches all move the same bytes per point; kind 1 mixes starts
+    # from zero and folded corrections, so its point count is not derived
+    points = alg / ALG_BYTES_PER_POINT[kind](e) if kind == 2 else None
+    cache = points * CACHE_BYTES_PER_POINT[precision] if points else None
+    return {
+        "kernel": KERNEL_NAMES[kind].format(n=n),
+        "bound": "hbm",
+        "achieved": achieved,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": achieved / HBM_PEAK_GBS,
+        "traffic": traffic_for(alg, kind),
+        "avg_launch_ms": avg_ms,
+        "launches": launches,
+        "algorithmic_bytes_per_launch": alg,
+        "algorithmic_bytes_per_point": ALG_BYTES_PER_POINT[kind](e),
+        "interior_points_per_launch": points,
+        "coefficient_cache_bytes_per_launch": cache,
+        "frac_with_cache_bytes": ((alg + cache) / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
+                                  if cache else None),
+    }
 
 
 def source_hash():
@@ -375,7 +472,7 @@ def traffic_for(launch_bytes, kind):
     try:
         with open(TRAFFIC_FILES[kind]) as fh:
             t = json.load(fh)
-    except (OSError, ValueError):
+    except (KeyError, OSError, ValueError):
         return None
     if t.get("source_hash") != source_hash():
         return None
@@ -423,10 +520,8 @@ def main():
     log(args, f"timed {args.steps} steps in {dt:.3f} s")
     solves, unknowns = problem_counts(w.grid_n, w.M)
     value = args.steps / dt
+    acc_grads = {"fp64": (w, first_estimate(m, w, dev))}
     tm, kind = dominant_timing(args, m, w, dev, r["timing"], nfin)
-    avg_ms = tm["ms"] / max(tm["launches"], 1)
-    bytes_per_launch = tm["bytes"] / max(tm["launches"], 1)
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9 if tm["launches"] else None
     out = {
         "metric": METRIC,
         "value": value,
@@ -448,18 +543,7 @@ def main():
         "iters_state": max(s["iters_state"] for s in stats),
         "iters_adjoint": max(s["iters_adjoint"] for s in stats),
         "max_relres": max(s["max_relres"] for s in stats),
-        "roofline": {
-            "kernel": KERNEL_NAMES[kind].format(n=nfin),
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS if achieved else None,
-            "traffic": traffic_for(bytes_per_launch, kind) if achieved else None,
-            "avg_launch_ms": avg_ms,
-            "launches": tm["launches"],
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-        },
+        "roofline": roofline(tm, kind, nfin, w.precision),
     }
     if not args.no_mixed:
         wm = inputs.WORKLOADS[args.mixed_workload]
@@ -467,11 +551,25 @@ def main():
         rm = run(args, m, wm, dev, args.steps, args.warmup, timing_n=wm.grid_n[-1])
         vm = args.steps / rm["dt"]
         tmm, kind_m = dominant_timing(args, m, wm, dev, rm["timing"], wm.grid_n[-1])
-        avg_m = tmm["ms"] / max(tmm["launches"], 1)
-        bpl_m = tmm["bytes"] / max(tmm["launches"], 1)
-        gbps_m = bpl_m / (avg_m * 1e-3) / 1e9 if tmm["launches"] else None
+        rf_m = roofline(tmm, kind_m, wm.grid_n[-1], wm.precision)
         sm, um = problem_counts(wm.grid_n, wm.M)
         err = same_samples_error(m, wm, wm, dev)
+        # the FP64 path on the mixed workload's data (sigma^2 = 2, theta = 10):
+        # the like-for-like comparison for the mixed speed-up
+        wf = dataclasses.replace(wm, precision="fp64",
+                                 name=wm.name.replace("FP32 V-cycles in FP64 refinement",
+                                                      "FP64 MG-PCG"))
+        log(args, "FP64 on the mixed workload's data")
+        rf = run(args, m, wf, dev, args.steps, args.warmup)
+        vf = args.steps / rf["dt"]
+        out["fp64_on_mixed_data"] = {
+            "workload": wf.name, "value": vf, "unit": "gradient estimates/s",
+            "ms_per_step": 1e3 * rf["dt"] / args.steps,
+            "iters_state": max(s["iters_state"] for s in rf["stats"]),
+            "iters_adjoint": max(s["iters_adjoint"] for s in rf["stats"]),
+        }
+        acc_grads["fp64_on_mixed_data"] = (wf, first_estimate(m, wf, dev))
+        acc_grads["mixed"] = (wm, first_estimate(m, wm, dev))
         out["mixed"] = {
             "workload": wm.name,
             "value": vm,
@@ -481,11 +579,9 @@ def main():
             "unknown_solves_per_s": um * vm,
             "iters_state": max(s["iters_state"] for s in rm["stats"]),
             "iters_adjoint": max(s["iters_adjoint"] for s in rm["stats"]),
-            "grad_rel_err_vs_fp64_same_samples": err,
-            "smoothing_pass": KERNEL_NAMES[kind_m].format(n=wm.grid_n[-1]),
-            "smoothing_pass_GBps": gbps_m,
-            "smoothing_pass_frac": gbps_m / HBM_PEAK_GBS if gbps_m else None,
-            "speedup_vs_fp64_batched": vm / value,
+            "grad_rel_err_vs_fp64_gpu_same_samples": err,
+            "smoothing_pass": rf_m,
+            "speedup_vs_fp64_batched_same_data": vm / vf,
         }
         wb = inputs.WORKLOADS["mlmc_129_bf16"]
         log(args, "bfloat16-smoother workload")
@@ -496,8 +592,10 @@ def main():
             "ms_per_step": 1e3 * rb["dt"] / args.steps,
             "iters_state": max(s["iters_state"] for s in rb["stats"]),
             "iters_adjoint": max(s["iters_adjoint"] for s in rb["stats"]),
-            "grad_rel_err_vs_fp64_same_samples": same_samples_error(m, wb, wb, dev),
+            "grad_rel_err_vs_fp64_gpu_same_samples": same_samples_error(m, wb, wb, dev),
+            "speedup_vs_fp64_batched_same_data": vb / vf,
         }
+        acc_grads["mixed_bf16"] = (wb, first_estimate(m, wb, dev))
     if not args.no_extra:
         log(args, "single-level SGD workload")
         out["single_level_sgd"] = single_level_sgd(m, dev)
@@ -540,9 +638,14 @@ def main():
         if "mixed" in out:
             out["mixed"]["speedup_vs_fp64_per_sample"] = out["mixed"]["value"] / ps["value"]
     if not args.no_cpu_baseline:
-        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        threads = args.cpu_threads or host_threads()
         log(args, f"cpu baseline with {threads} threads")
-        out["cpu_baseline"] = cpu_baseline(w, threads)
+        cb, errs = cpu_baseline(w, threads, acc_grads)
+        out["cpu_baseline"] = cb
+        out["grad_rel_err_vs_oracle"] = errs
+        for key in ("mixed", "mixed_bf16", "fp64_on_mixed_data"):
+            if key in out and key in errs:
+                out[key]["grad_rel_err_vs_oracle"] = errs[key]
     print(json.dumps(out), flush=True)
 
 

@@ -552,9 +552,9 @@ double gs_pass_bytes(const mlsgd_ctx* c, int n, int rows, bool x_zero, bool cach
   const double e = (double)sizeof(T);
   double b = 0.5 * e + 0.5 * e;          // b and x on the updated half
   b += x_zero ? 0.5 * e : e;             // x read, or the other half zeroed
-  if (cached) b += e;
   if (dot) b += 0.5 * e;
   (void)c;
+  (void)cached;                          // the coefficient counts 0 bytes (regenerated)
   return N * b;
 }
 
@@ -596,13 +596,14 @@ void timing_collect(mlsgd_ctx* c) {
 }
 
 // Algorithmic bytes of one fused red-black sweep over `rows` rows: previous
-// iterate read (not on a zero start), b read, 1/a read, new iterate written,
-// and, when the coarse correction is folded in, the coarse rows read once.
+// iterate read (not on a zero start), b read, new iterate written, and, when
+// the coarse correction is folded in, the coarse rows read once (the
+// coefficient counts 0 bytes: it is regenerated from the draws).
 template <typename T>
 double sweep_bytes(int n, int rows, bool x_zero, bool prolong) {
   const double N = (double)rows * (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
   const double e = (double)sizeof(T);
-  double b = 3.0 * e + (x_zero ? 0.0 : e);
+  double b = 2.0 * e + (x_zero ? 0.0 : e);
   if (prolong) b += e / 8.0;
   return N * b;
 }
@@ -664,26 +665,27 @@ std::vector<double> cheb_omegas(int deg, double lo) {
   return w;
 }
 
-// Algorithmic bytes of one Jacobi step: x read (not from zero), b, 1/a, x'
-// written, coarse rows once when the correction is folded in.
+// Algorithmic bytes of one Jacobi step: x read (not from zero), b read, x'
+// written, coarse rows once when the correction is folded in.  The
+// coefficient counts 0 bytes: the method regenerates it from the draws (a
+// per-call cache that a kernel reads is an implementation choice, reported
+// apart from these bytes).
 template <typename T>
-double jac_bytes(int n, int rows, bool x_zero, bool prolong, const GridArgs& g) {
+double jac_bytes(int n, int rows, bool x_zero, bool prolong, const GridArgs&) {
   const double N = (double)rows * (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
   const double e = (double)sizeof(T);
-  const double ce = g.cache ? (g.cache_bf16 ? 2.0 : e) : 0.0;
-  double b = 2.0 * e + (x_zero ? 0.0 : e) + ce;
+  double b = e + (x_zero ? 0.0 : e) + e;
   if (prolong) b += e / 8.0;
   return N * b;
 }
 
-// Algorithmic bytes of the fused post-smoothing pass: x, b and 1/a read, x''
-// written, coarse rows read once.
+// Algorithmic bytes of the fused post-smoothing pass: x and b read, x''
+// written, coarse rows read once (coefficient: 0 bytes, as above).
 template <typename T>
-double post2_bytes(int n, int rows, const GridArgs& g) {
+double post2_bytes(int n, int rows, const GridArgs&) {
   const double N = (double)rows * (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
   const double e = (double)sizeof(T);
-  const double ce = g.cache_bf16 ? 2.0 : e;
-  return N * (3.0 * e + ce + e / 8.0);
+  return N * (3.0 * e + e / 8.0);
 }
 
 // Symmetric V(1,1) cycle with degree-nu Chebyshev smoothing (a polynomial in

@@ -53,3 +53,24 @@ def test_tuning_entries_are_usable():
         assert 8 <= t["xchunk"] <= 1024
         assert t["cache"] in (0, 1)
         assert entry["ms"] > 0
+
+
+def test_roofline_counts_algorithmic_bytes_only():
+    """The bench's roofline record for the fused post-smoothing pass divides
+    the algorithmic bytes (x and b read, x'' written, the coarse correction at
+    one eighth of a point: 25 B per interior point in FP64; the coefficient at
+    0 B, since the method regenerates it) by the live average launch time;
+    the coefficient cache it reads on top is reported apart."""
+    sys.path.insert(0, ROOT)
+    import bench
+    pts = 16 * 127 ** 3
+    tm = {"ms": 2.0 * 0.5, "launches": 2, "bytes": 2 * 25.0 * pts}
+    r = bench.roofline(tm, 2, 129, "fp64")
+    assert r["algorithmic_bytes_per_point"] == 25.0
+    assert r["interior_points_per_launch"] == pytest.approx(pts)
+    assert r["achieved"] == pytest.approx(25.0 * pts / 0.5e-3 / 1e9)
+    assert r["frac"] == pytest.approx(r["achieved"] / 8000.0)
+    assert r["coefficient_cache_bytes_per_launch"] == pytest.approx(8.0 * pts)
+    rm = bench.roofline({"ms": 1.0, "launches": 1, "bytes": 12.5 * pts}, 2, 129, "mixed")
+    assert rm["algorithmic_bytes_per_point"] == 12.5
+    assert rm["coefficient_cache_bytes_per_launch"] == pytest.approx(4.0 * pts)
