@@ -343,6 +343,30 @@ def run_mlsgd(args):
     print(json.dumps(out), flush=True)
 
 
+def level_rates(w, stats):
+    """Level rates of the headline hierarchy from the timed estimates
+    (fresh samples each): per-level |E dX_l|, Var dX_l and |E dY_l| averaged
+    over the estimates, then the least-squares exponents alpha (weak error),
+    beta (variance) and alpha_Y over the levels l >= 1 (rates.py).  gamma is
+    the exponent of the work per sample: interior unknowns of the fine and
+    coarse grid times the estimate's state plus adjoint iterations."""
+    from paper_2606_09291_amd import rates
+    acc = None
+    for st in stats:
+        cur = rates.level_statistics(st, w.M, w.theta)
+        acc = cur if acc is None else [[a + b for a, b in zip(x, y)] for x, y in zip(acc, cur)]
+    e, V, wy = [[x / len(stats) for x in row] for row in acc]
+    it = max(s["iters_state"] for s in stats) + max(s["iters_adjoint"] for s in stats)
+    work = []
+    for i, n in enumerate(w.grid_n):
+        u = (n - 2) ** 3 + ((w.grid_n[i - 1] - 2) ** 3 if i else 0)
+        work.append(float(u * it))
+    fit = rates.fit_rates(w.grid_n, e, V, wy, work)
+    return {"estimates": len(stats), "alpha": fit["alpha"], "beta": fit["beta"],
+            "alpha_Y": fit["alpha_Y"], "gamma_work": fit["gamma"], "C_X": fit["C_X"],
+            "C_V": fit["C_V"], "norm_mean_dX": e, "var_dX": V, "abs_mean_dY": wy}
+
+
 def host_threads():
     """Host threads the oracle may use: the CPUs this process may run on,
     bounded by OMP_NUM_THREADS where the environment sets it (the share of
@@ -545,6 +569,7 @@ def main():
         "max_relres": max(s["max_relres"] for s in stats),
         "roofline": roofline(tm, kind, nfin, w.precision),
     }
+    out["rates"] = level_rates(w, stats)
     if not args.no_mixed:
         wm = inputs.WORKLOADS[args.mixed_workload]
         log(args, f"mixed workload {args.mixed_workload} ({wm.precision})")

@@ -764,10 +764,9 @@ __global__ void __launch_bounds__(TY* TZ)
   }
   const int oy = y0 - 2 + oidx / PZ, oz = z0 - 2 + oidx % PZ;
   const int sy = y0 - 2 + sidx / PZ, sz = z0 - 2 + sidx % PZ;
-  auto in_grid = [&](int jy, int jz) { return jy >= 0 && jz >= 0 && jy <= n - 1 && jz <= n - 1; };
   auto in_int = [&](int jy, int jz) { return jy >= 1 && jz >= 1 && jy <= n - 2 && jz <= n - 2; };
-  const bool o_grid = in_grid(oy, oz), o_int = in_int(oy, oz);
-  const bool s_grid = s_on && in_grid(sy, sz), s_int = s_on && in_int(sy, sz);
+  const bool o_int = in_int(oy, oz);
+  const bool s_int = s_on && in_int(sy, sz);
 
   // one plane of one column as loaded: b, 1/D (interior only) and 1/a
   struct Raw {
@@ -775,15 +774,28 @@ __global__ void __launch_bounds__(TY* TZ)
     CR a;
   };
   const CR one = CK == 2 ? CR(0x3F80) : CR(1);
-  auto load = [&](int ix, int jy, int jz, bool grid, bool inter) -> Raw {
+  // Columns are addressed as in k_post2: a 32-bit element offset in plane 0
+  // and the plane stride, every in-grid vertex loaded without a mask (b and
+  // 1/D are zero off the interior, so x1 is too), ring slots outside the
+  // grid reading the nearest in-grid column (their values only reach
+  // discarded non-interior results).
+  const T* __restrict__ brow = rhs + base;
+  const T* __restrict__ drow = dinv + base;
+  const uint32_t pstr = (uint32_t)n * (uint32_t)LP;
+  auto col_off = [&](int jy, int jz) -> uint32_t {
+    jy = min(max(jy, 0), n - 1);
+    jz = min(max(jz, 0), n - 1);
+    return (uint32_t)(jy * LP + jz + LO);
+  };
+  const uint32_t ooff = col_off(oy, oz);
+  const uint32_t soff = col_off(sy, sz);
+  auto load = [&](int ix, uint32_t off) -> Raw {
     Raw v{T(0), T(0), one};
-    if (ix < 0 || ix > n - 1 || !grid) return v;
-    const size_t e = ((size_t)ix * n + jy) * LP + jz + LO;
+    if (ix < 0 || ix > n - 1) return v;   // uniform
+    const size_t e = (size_t)off + (size_t)ix * pstr;
     v.a = cache[e];
-    if (inter && ix >= 1 && ix <= n - 2) {
-      v.b = rhs[base + e];
-      v.d = dinv[base + e];
-    }
+    v.b = brow[e];
+    v.d = drow[e];
     return v;
   };
   auto cvt = [&](CR v) -> T {
@@ -804,14 +816,14 @@ __global__ void __launch_bounds__(TY* TZ)
   T sxm = T(0), sxc = T(0), sxp = T(0), sbm = T(1), sbc = T(1), sbp = T(1), src = T(0), srp = T(0);
   {
     const int q = x0 - 1;
-    const Raw m = load(q - 1, oy, oz, o_grid, o_int), c = load(q, oy, oz, o_grid, o_int),
-              p = load(q + 1, oy, oz, o_grid, o_int);
+    const Raw m = load(q - 1, ooff), c = load(q, ooff),
+              p = load(q + 1, ooff);
     oxm = x1of(m); oxc = x1of(c); oxp = x1of(p);
     obm = cvt(m.a); obc = cvt(c.a); obp = cvt(p.a);
     orc = c.b; orp = p.b;
     if (s_on) {
-      const Raw sm = load(q - 1, sy, sz, s_grid, s_int), sc = load(q, sy, sz, s_grid, s_int),
-                sp = load(q + 1, sy, sz, s_grid, s_int);
+      const Raw sm = load(q - 1, soff), sc = load(q, soff),
+                sp = load(q + 1, soff);
       sxm = x1of(sm); sxc = x1of(sc); sxp = x1of(sp);
       sbm = cvt(sm.a); sbc = cvt(sc.a); sbp = cvt(sp.a);
       src = sc.b; srp = sp.b;
@@ -823,9 +835,9 @@ __global__ void __launch_bounds__(TY* TZ)
   T gfxm = T(0), gfxp = T(0), gfym = T(0), gfyp = T(0), gfzm = T(0), gfzp = T(0), gdiag = T(1);
 
   for (int q = x0 - 1; q <= x1; ++q) {
-    const Raw on = load(q + 2, oy, oz, o_grid, o_int);
+    const Raw on = load(q + 2, ooff);
     Raw sn{T(0), T(0), one};
-    if (s_on) sn = load(q + 2, sy, sz, s_grid, s_int);
+    if (s_on) sn = load(q + 2, soff);
 
     T* __restrict__ b3 = sb[q % 3];
     s1[oidx] = oxc;
@@ -1028,25 +1040,38 @@ __global__ void __launch_bounds__(TY* TZ)
   }
   const int oy = y0 - 2 + oidx / PZ, oz = z0 - 2 + oidx % PZ;
   const int sy = y0 - 2 + sidx / PZ, sz = z0 - 2 + sidx % PZ;
-  auto in_grid = [&](int jy, int jz) { return jy >= 0 && jz >= 0 && jy <= n - 1 && jz <= n - 1; };
   auto in_int = [&](int jy, int jz) { return jy >= 1 && jz >= 1 && jy <= n - 2 && jz <= n - 2; };
-  const bool o_grid = in_grid(oy, oz), o_int = in_int(oy, oz);
-  const bool s_grid = s_on && in_grid(sy, sz), s_int = s_on && in_int(sy, sz);
+  const bool o_int = in_int(oy, oz);
+  const bool s_int = s_on && in_int(sy, sz);
 
   struct Raw {  // one plane of one column as loaded: x, b (interior only), 1/a
     T x, b;
     CR a;
   };
   const CR one = CK == 2 ? CR(0x3F80) : CR(1);
-  auto load = [&](int ix, int jy, int jz, bool grid, bool inter) -> Raw {
+  // A column is addressed by its 32-bit element offset in plane 0 and the
+  // plane stride.  Every in-grid vertex is loaded without a mask: boundary
+  // vertices and padding hold zeros in x and b, and the prolonged coarse
+  // correction vanishes on the boundary.  Ring slots outside the grid read
+  // the nearest in-grid column; their values feed only results at
+  // non-interior positions, which are set to zero or discarded.
+  const T* __restrict__ xrow = xin + base;
+  const T* __restrict__ brow = rhs + base;
+  const uint32_t pstr = (uint32_t)n * (uint32_t)LP;
+  auto col_off = [&](int jy, int jz) -> uint32_t {
+    jy = min(max(jy, 0), n - 1);
+    jz = min(max(jz, 0), n - 1);
+    return (uint32_t)(jy * LP + jz + LO);
+  };
+  const uint32_t ooff = col_off(oy, oz);
+  const uint32_t soff = col_off(sy, sz);
+  auto load = [&](int ix, uint32_t off) -> Raw {
     Raw v{T(0), T(0), one};
-    if (ix < 0 || ix > n - 1 || !grid) return v;
-    const size_t e = ((size_t)ix * n + jy) * LP + jz + LO;
+    if (ix < 0 || ix > n - 1) return v;   // uniform
+    const size_t e = (size_t)off + (size_t)ix * pstr;
     v.a = cache[e];
-    if (inter && ix >= 1 && ix <= n - 2) {
-      v.x = xin[base + e];
-      v.b = rhs[base + e];
-    }
+    v.x = xrow[e];
+    v.b = brow[e];
     return v;
   };
   auto cvt = [&](CR v) -> T {
@@ -1075,11 +1100,9 @@ __global__ void __launch_bounds__(TY* TZ)
     if (tid < CSLAB) scs[(J & 3) * CSLAB + tid] = v;
   };
   ProlongLds<T> pco, pcs;
-  // prolonged correction of plane ix of a column (zero where x is)
-  auto corr = [&](ProlongLds<T>& pc, int ix, bool inter) -> T {
-    const T v = pc.at(scs, CSLAB, ix);
-    return (inter && ix >= 1 && ix <= n - 2) ? v : T(0);
-  };
+  // prolonged correction of plane ix of a column (zero on the boundary,
+  // where every contributing coarse vertex is a boundary vertex)
+  auto corr = [&](ProlongLds<T>& pc, int ix) -> T { return pc.at(scs, CSLAB, ix); };
 
   const int x0 = 1 + xcix * g.t.xchunk;
   const int x1 = min(x0 + g.t.xchunk, n - 1);
@@ -1115,21 +1138,21 @@ __global__ void __launch_bounds__(TY* TZ)
   T sym = T(0), syc = T(0), syp = T(0), sbm = T(1), sbc = T(1), sbp = T(1), src = T(0), srp = T(0),
     sfb = T(0);
   {
-    const Raw m = load(ixs, oy, oz, o_grid, o_int), c = load(ixs + 1, oy, oz, o_grid, o_int),
-              p = load(ixs + 2, oy, oz, o_grid, o_int);
-    oym = m.x + corr(pco, ixs, o_int);
-    oyc = c.x + corr(pco, ixs + 1, o_int);
-    oyp = p.x + corr(pco, ixs + 2, o_int);
+    const Raw m = load(ixs, ooff), c = load(ixs + 1, ooff),
+              p = load(ixs + 2, ooff);
+    oym = m.x + corr(pco, ixs);
+    oyc = c.x + corr(pco, ixs + 1);
+    oyp = p.x + corr(pco, ixs + 2);
     obm = cvt(m.a); obc = cvt(c.a); obp = cvt(p.a);
     ofb = face(obm, obc);
     orc = c.b; orp = p.b;
     if (SHARE) sa[oidx] = obc;
     if (s_on) {
-      const Raw sm = load(ixs, sy, sz, s_grid, s_int), sc = load(ixs + 1, sy, sz, s_grid, s_int),
-                sp = load(ixs + 2, sy, sz, s_grid, s_int);
-      sym = sm.x + corr(pcs, ixs, s_int);
-      syc = sc.x + corr(pcs, ixs + 1, s_int);
-      syp = sp.x + corr(pcs, ixs + 2, s_int);
+      const Raw sm = load(ixs, soff), sc = load(ixs + 1, soff),
+                sp = load(ixs + 2, soff);
+      sym = sm.x + corr(pcs, ixs);
+      syc = sc.x + corr(pcs, ixs + 1);
+      syp = sp.x + corr(pcs, ixs + 2);
       sbm = cvt(sm.a); sbc = cvt(sc.a); sbp = cvt(sp.a);
       sfb = face(sbm, sbc);
       src = sc.b; srp = sp.b;
@@ -1150,9 +1173,9 @@ __global__ void __launch_bounds__(TY* TZ)
   double dot = 0.0;
 
   for (int q = x0 - 1; q <= x1; ++q) {
-    const Raw on = load(q + 2, oy, oz, o_grid, o_int);
+    const Raw on = load(q + 2, ooff);
     Raw sn{T(0), T(0), one};
-    if (s_on) sn = load(q + 2, sy, sz, s_grid, s_int);
+    if (s_on) sn = load(q + 2, soff);
     if (((q + 3) >> 1) > chi) {
       ++chi;
       cstore(chi, cnext);
@@ -1167,8 +1190,8 @@ __global__ void __launch_bounds__(TY* TZ)
       b3[sidx] = SHARE ? sbp : sbc;
     }
     __syncthreads();
-    const T ocn = corr(pco, q + 2, o_int);
-    const T scn = s_on ? corr(pcs, q + 2, s_int) : T(0);
+    const T ocn = corr(pco, q + 2);
+    const T scn = s_on ? corr(pcs, q + 2) : T(0);
     faces_yz(q + 1, oidx);
     if (s_on) faces_yz(q + 1, sidx);
 

@@ -679,6 +679,14 @@ double jac_bytes(int n, int rows, bool x_zero, bool prolong, const GridArgs&) {
   return N * b;
 }
 
+// Algorithmic bytes of the fused pre-smoothing pass from x = 0: b read, x2 and
+// the residual written (coefficient and reciprocal diagonal: 0 bytes).
+template <typename T>
+double pre2r_bytes(int n, int rows) {
+  const double N = (double)rows * (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
+  return N * 3.0 * (double)sizeof(T);
+}
+
 // Algorithmic bytes of the fused post-smoothing pass: x and b read, x''
 // written, coarse rows read once (coefficient: 0 bytes, as above).
 template <typename T>
@@ -774,7 +782,9 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P, int k0 = 0, int rlim = INT_MAX, bool xin
       continue;
     }
     if (deg == 2 && dinv && c->pre2r && fused_tiles(g)) {
-      march_pre2r<T>(g, dinv, v.B, A[1], A[0], om[0], om[1], c->stream);
+      timed_launch(c, g, pre2r_bytes<T>(L.n, g.rows), [&] {
+        march_pre2r<T>(g, dinv, v.B, A[1], A[0], om[0], om[1], c->stream);
+      }, 3);
       // both pre-smoothing steps and the residual in one pass: x2 in A[1], r in A[0]
       restrict_rows<T>(L.n, g.rows, 0, P->d_scal, A[0], mg_view<T>(P->sizes[k + 1]).B,
                        c->stream);
@@ -1902,7 +1912,7 @@ int mlsgd_kernel_timing(mlsgd_ctx* c, int enable, int n, double* ms_total, int64
     if (launches) *launches = c->tm.launches;
     if (bytes) *bytes = c->tm.total_bytes;
     if (enable >= 0) {
-      require(enable <= 2, "enable must be -1, 0, 1 or 2");
+      require(enable <= 3, "enable must be -1, 0, 1, 2 or 3");
       c->tm.on = enable != 0;
       c->tm.kind = enable != 0 ? enable : 1;
       c->tm.n = n;

@@ -317,6 +317,33 @@ def test_full_size_estimate_matches_oracle(mm, orc, workload, bar):
     assert st["EY_shifted"] == pytest.approx(so["EY_shifted"], rel=1e-10)
 
 
+def test_full_size_257_estimate_matches_oracle(mm, orc):
+    """The 9^3..257^3 workload (M = 8192/2048/512/128/32/8, FP32 cycles in
+    FP64 PCG to rtol 1e-10) in the benchmark's launch configuration against
+    the complete oracle estimate of the same draws on all host cores, the
+    oracle solving to rtol 1e-11 (the FP64 floor at 257^3 is about 3e-12):
+    gradient within the mixed bar 1e-8, objective within 1e-9."""
+    import os
+    import torch
+    import bench
+    w = inputs.WORKLOADS["mlmc_257_batched"]
+    print("full size 257 estimate against the oracle", flush=True)
+    ctx = bench.make_ctx(mm, w, torch.device("cuda:0"))
+    u = w.u0()
+    g, st = ctx.mlmc_gradient(u, w.M, first=[0] * len(w.M))
+    ctx.close()
+    assert st["nonconverged"] == 0
+    threads = len(os.sched_getaffinity(0))
+    pb = orc.make_problem(w.grid_n, K=w.K, sigma2=w.sigma2, theta=w.theta, alpha=w.alpha,
+                          rtol=1e-11, nthreads=threads)
+    go, so = orc.mlmc_gradient(pb, None, u, w.y_d(), w.M, first=[0] * len(w.M))
+    err = _rel(g.cpu().numpy(), go)
+    print("257 full-estimate relative L2 error", err, flush=True)
+    assert err <= 1e-8
+    assert st["J"] == pytest.approx(so["J"], rel=1e-9)
+    assert st["s"] == pytest.approx(so["s"], rel=1e-9)
+
+
 def test_full_size_257_sampled(mm, orc):
     """The 9^3..257^3 workload (M = 8192/.../8, mixed, rtol 1e-10) at full
     size in the benchmark's launch configuration: every solve converges, the
