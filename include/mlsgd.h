@@ -217,6 +217,20 @@ int mlsgd_solve_state_adjoint_noalloc(mlsgd_ctx* ctx, int level, int coarse,
 int mlsgd_solve_sizes(mlsgd_ctx* ctx, int count, const int* n_list, int level, int64_t first,
                       double f_value, double* y_out, mlsgd_solve_stats* st);
 
+/* The exact coarsest-grid solve of mlsgd_solve_sizes' hierarchies that stop
+ * above 3^3, exposed for checking: the inverse of the rediscretised operator
+ * (the Sec. 5 model problem's finite-difference form, see the top of this
+ * header) on an n^3 grid (4 <= n <= 9, N = (n-2)^3 interior unknowns) for the
+ * KL draws of samples first .. first+count-1 of `level`, computed as on the
+ * solve path: a blocked Cholesky factorisation on the FP64 matrix cores,
+ * then L^-1 and A^-1 = L^-T L^-1.  out: device, count * N * N doubles,
+ * problem-major, row-major over the interior unknowns in the vertex order
+ * (x slowest, z fastest).  Allocates and frees its own work buffers.
+ * Errors: MLSGD_EINVAL for n outside 4..9, count outside 1..4096, a negative
+ * level or first, or a null out. */
+int mlsgd_dense_coarse_inverse(mlsgd_ctx* ctx, int n, int level, int64_t first, int count,
+                               double* out);
+
 /* One MLMC gradient estimate (Sec. 2.2, the estimator with truncated
  * denominator; Algorithm 1, GradientEstimate):
  *   grad = E^ML[X] / max{1, E^ML[Y]} + alpha u   on the finest grid,

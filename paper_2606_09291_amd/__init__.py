@@ -24,6 +24,7 @@ EXPORTS = [
     "mlsgd_philox_words", "mlsgd_solve_state_adjoint", "mlsgd_solve_sizes", "mlsgd_mlmc_gradient",
     "mlsgd_mlmc_objective", "mlsgd_set_batch", "mlsgd_step", "mlsgd_kernel_timing",
     "mlsgd_get_tuning", "mlsgd_set_tuning", "mlsgd_set_graph", "mlsgd_solve_state_adjoint_noalloc",
+    "mlsgd_dense_coarse_inverse",
 ]
 SMOOTHER_RBGS, SMOOTHER_RBGS_FUSED, SMOOTHER_CHEBYSHEV = 0, 1, 2
 ADAPT_BATCH, ADAPT_STEP = 1, 2
@@ -131,6 +132,7 @@ def lib():
                                             P(_SolveStats)]
     L.mlsgd_solve_state_adjoint_noalloc.argtypes = [vp, i32, i32, i64, i64, vp, vp, vp, vp,
                                                     P(_SolveStats), P(i64)]
+    L.mlsgd_dense_coarse_inverse.argtypes = [vp, i32, i32, i64, i32, vp]
     L.mlsgd_solve_sizes.argtypes = [vp, i32, P(i32), i32, i64, ctypes.c_double, vp,
                                     P(_SolveStats)]
     L.mlsgd_mlmc_gradient.argtypes = [vp, vp, i32, P(i64), P(i64), vp, P(_GradStats)]
@@ -329,6 +331,17 @@ class Context:
             out.append(y[o:o + n ** 3].view(n, n, n))
             o += n ** 3
         return out, stats
+
+    def dense_coarse_inverse(self, n, level, first, count):
+        """Inverses of the rediscretised n^3 operators of the given draws
+        (mlsgd_dense_coarse_inverse), as a (count, N, N) float64 tensor."""
+        torch = _torch()
+        N = (n - 2) ** 3
+        out = torch.empty((count, N, N), dtype=torch.float64, device=self.device)
+        self._check(self.lib.mlsgd_dense_coarse_inverse(self._h, int(n), int(level), int(first),
+                                                        int(count),
+                                                        ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def set_graph(self, enable=True):
         """Run estimates as replayed HIP graphs (mlsgd_set_graph)."""

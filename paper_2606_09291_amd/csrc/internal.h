@@ -157,8 +157,11 @@ void copy_active_rows(int n, int rows, int row0, const CgScal* scal, const TS* s
                       hipStream_t s);
 
 // ---- dense coarsest-grid solve (hierarchies that stop above 3^3) ----
+// pitch (and edge) of one problem's dense coarsest matrix with N unknowns:
+// padded to a multiple of the 16 x 16 tiles of the factorisation
+__host__ __device__ __forceinline__ int dense_pitch(int N) { return (N + 15) / 16 * 16; }
 void dense_coarse_inv(int n, int rows, const double* coef, int K, const double* cosT,
-                      double* ainv, hipStream_t s);
+                      double* ainv, double* work, hipStream_t s);
 template <typename T>
 void dense_apply(int n, int rows, const CgScal* scal, const double* ainv, const T* b, T* x,
                  hipStream_t s);

@@ -2050,22 +2050,88 @@ template void prolong_add_rows<float>(int, int, int, const CgScal*, const float*
 // keeps (b - 1)^3 interior unknowns (at most 7^3 here) and is solved exactly
 // with the inverse of its rediscretised operator, built per problem from the
 // KL draw and applied as a small dense product in every V-cycle.
+//
+// The inverse comes from a blocked Cholesky factorisation A = L L^T on 16 x 16
+// tiles.  Every tile product runs on the FP64 matrix cores
+// (v_mfma_f64_16x16x4f64: four instructions per 16 x 16 x 16 product); the
+// 16 x 16 diagonal blocks are factored and inverted on the vector ALUs in
+// LDS.  Then W = L^-1 by blocked forward substitution, and A^-1 = W^T W.  The
+// matrix is padded to Np = 16 ceil(N / 16) with the identity, whose inverse
+// block is the identity again and is never read.  One workgroup of four waves
+// per problem; A, then A^-1, lives in the problem's Np x Np block of `ainv`,
+// W in the same block of `work` (both stay cache-resident at these sizes).
+//
+// MFMA operand layout (16 x 16 x 4, FP64): lane l supplies a = X[l % 16][k0 +
+// l / 16] of the left factor and b = Y[k0 + l / 16][l % 16] of the right one,
+// and holds C[4 r + l / 16][l % 16] in accumulator element r.
 // ---------------------------------------------------------------------------
 constexpr int DENSE_NMAX = 9;
+constexpr int DT = 16;                 // tile edge
+typedef double dbl4 __attribute__((ext_vector_type(4)));
 
-// One workgroup per problem: 1/a at the coarsest vertices, the operator
-// (A y)_v = h^-2 sum_f a_f (y_v - y_w) with a_f = 2 / (b_v + b_w) on the
-// interior unknowns, Gauss-Jordan inversion in place (SPD: no pivoting),
-// then A^-1 <- (A^-1 + A^-T) / 2 so the coarse solve is exactly symmetric.
+__device__ __forceinline__ dbl4 mfma_f64(double a, double b, dbl4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// One wave's 16 x 16 tile of a row-major matrix with pitch ld at tile (I, J).
+struct TileRef {
+  double* m;
+  int ld;
+  __device__ double* at(int I, int J) const { return m + ((size_t)I * DT) * ld + (size_t)J * DT; }
+};
+
+__device__ __forceinline__ dbl4 tile_load_c(const double* t, int ld, int li, int lk) {
+  dbl4 c;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) c[r] = t[(4 * r + lk) * ld + li];
+  return c;
+}
+__device__ __forceinline__ void tile_store_c(double* t, int ld, int li, int lk, dbl4 c) {
+#pragma unroll
+  for (int r = 0; r < 4; ++r) t[(4 * r + lk) * ld + li] = c[r];
+}
+// c += sign * X Y^T (X, Y tiles, row-major, pitch ld)
+__device__ __forceinline__ dbl4 mma_xyt(const double* x, const double* y, int ld, int li, int lk,
+                                        double sign, dbl4 c) {
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl)
+    c = mfma_f64(sign * x[li * ld + 4 * sl + lk], y[li * ld + 4 * sl + lk], c);
+  return c;
+}
+// c += sign * X Y
+__device__ __forceinline__ dbl4 mma_xy(const double* x, int ldx, const double* y, int ldy, int li,
+                                       int lk, double sign, dbl4 c) {
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl)
+    c = mfma_f64(sign * x[li * ldx + 4 * sl + lk], y[(4 * sl + lk) * ldy + li], c);
+  return c;
+}
+// c += X^T Y
+__device__ __forceinline__ dbl4 mma_xty(const double* x, const double* y, int ld, int li, int lk,
+                                        dbl4 c) {
+#pragma unroll
+  for (int sl = 0; sl < 4; ++sl)
+    c = mfma_f64(x[(4 * sl + lk) * ld + li], y[(4 * sl + lk) * ld + li], c);
+  return c;
+}
+
 __global__ void __launch_bounds__(256)
     k_dense_coarse_inv(int n, const double* __restrict__ coef, int K,
-                       const double* __restrict__ cosT, double* __restrict__ ainv) {
+                       const double* __restrict__ cosT, double* __restrict__ ainv,
+                       double* __restrict__ work) {
   __shared__ double sb[DENSE_NMAX * DENSE_NMAX * DENSE_NMAX];
   __shared__ double sc[KMAX * KMAX * KMAX];
-  __shared__ double col[(DENSE_NMAX - 2) * (DENSE_NMAX - 2) * (DENSE_NMAX - 2)];
+  __shared__ double sd[DT][DT + 1];     // diagonal tile being factored (L)
+  __shared__ double st[DT][DT + 1];     // its inverse T = L^-1
+  __shared__ double sw[4][DT][DT + 1];  // one scratch tile per wave
   const int prob = blockIdx.x, tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6, li = lane & 15, lk = lane >> 4;
   const int m = n - 2, N = m * m * m, K3 = K * K * K;
-  double* A = ainv + (size_t)prob * N * N;
+  const int Np = (N + DT - 1) / DT * DT, nt = Np / DT;
+  const TileRef A{ainv + (size_t)prob * Np * Np, Np};
+  const TileRef W{work + (size_t)prob * Np * Np, Np};
+
+  // the operator: 1/a at every vertex from the KL sum, harmonic faces
   for (int j = tid; j < K3; j += 256) sc[j] = coef[(size_t)prob * K3 + j];
   __syncthreads();
   for (int v = tid; v < n * n * n; v += 256) {
@@ -2078,7 +2144,11 @@ __global__ void __launch_bounds__(256)
                cosT[k3 * n + iz];
     sb[v] = exp(-l);
   }
-  for (int e = tid; e < N * N; e += 256) A[e] = 0.0;
+  for (size_t e = tid; e < (size_t)Np * Np; e += 256) {
+    const int i = (int)(e / Np), j = (int)(e % Np);
+    A.m[e] = (i == j && i >= N) ? 1.0 : 0.0;
+    W.m[e] = 0.0;
+  }
   __syncthreads();
   const double ih2 = (double)(n - 1) * (double)(n - 1);
   for (int i = tid; i < N; i += 256) {
@@ -2091,40 +2161,111 @@ __global__ void __launch_bounds__(256)
       const double af = ih2 * face(sb[v], sb[(jx * n + jy) * n + jz]);
       diag += af;
       if (jx >= 1 && jx <= m && jy >= 1 && jy <= m && jz >= 1 && jz <= m)
-        A[(size_t)i * N + ((jx - 1) * m + (jy - 1)) * m + (jz - 1)] = -af;
+        A.m[(size_t)i * Np + ((jx - 1) * m + (jy - 1)) * m + (jz - 1)] = -af;
     }
-    A[(size_t)i * N + i] = diag;
+    A.m[(size_t)i * Np + i] = diag;
   }
   __syncthreads();
-  for (int k = 0; k < N; ++k) {
-    for (int i = tid; i < N; i += 256) col[i] = A[(size_t)i * N + k];
+
+  // Cholesky, right-looking over tile columns k
+  const int ti = tid / DT, tj = tid % DT;   // this thread's element of a 16 x 16 tile
+  for (int k = 0; k < nt; ++k) {
+    sd[ti][tj] = *(A.at(k, k) + ti * Np + tj);
+    st[ti][tj] = 0.0;
     __syncthreads();
-    const double p = 1.0 / col[k];
-    for (int j = tid; j < N; j += 256) A[(size_t)k * N + j] = (j == k ? 1.0 : A[(size_t)k * N + j]) * p;
-    __syncthreads();
-    for (int j = tid; j < N; j += 256) {  // each thread owns columns j
-      const double akj = A[(size_t)k * N + j];
-      for (int i = 0; i < N; ++i) {
-        if (i == k) continue;
-        A[(size_t)i * N + j] = (j == k ? 0.0 : A[(size_t)i * N + j]) - col[i] * akj;
+    for (int j = 0; j < DT; ++j) {           // unblocked factor of the diagonal tile
+      if (ti == j && tj == j) sd[j][j] = sqrt(sd[j][j]);
+      __syncthreads();
+      if (tj == j && ti > j) sd[ti][j] /= sd[j][j];
+      __syncthreads();
+      if (tj > j && ti >= tj) sd[ti][tj] -= sd[ti][j] * sd[tj][j];
+      __syncthreads();
+    }
+    for (int i = 0; i < DT; ++i) {           // T = L^-1, row by row
+      if (ti == i && tj <= i) {
+        double acc = (tj == i) ? 1.0 : 0.0;
+        for (int q = tj; q < i; ++q) acc -= sd[i][q] * st[q][tj];
+        st[i][tj] = acc / sd[i][i];
       }
+      __syncthreads();
+    }
+    *(A.at(k, k) + ti * Np + tj) = tj <= ti ? sd[ti][tj] : 0.0;
+    *(W.at(k, k) + ti * Np + tj) = st[ti][tj];
+    // panel: L_ik = A_ik T^T, one tile per wave in turn
+    for (int i = k + 1 + wave; i < nt; i += 4) {
+      double* t = A.at(i, k);
+      dbl4 c = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl)
+        c = mfma_f64(t[li * Np + 4 * sl + lk], st[li][4 * sl + lk], c);
+      tile_store_c(t, Np, li, lk, c);
+    }
+    __syncthreads();
+    // trailing update of the lower tiles: A_ij -= L_ik L_jk^T, k < j <= i
+    const int rem = nt - 1 - k;
+    for (int p = wave; p < rem * (rem + 1) / 2; p += 4) {
+      int i = 0;
+      while ((i + 1) * (i + 2) / 2 <= p) ++i;
+      const int j = p - i * (i + 1) / 2;
+      const int I = k + 1 + i, J = k + 1 + j;
+      double* t = A.at(I, J);
+      dbl4 c = tile_load_c(t, Np, li, lk);
+      c = mma_xyt(A.at(I, k), A.at(J, k), Np, li, lk, -1.0, c);
+      tile_store_c(t, Np, li, lk, c);
     }
     __syncthreads();
   }
-  for (int e = tid; e < N * N; e += 256) {
-    const int i = e / N, j = e - (e / N) * N;
-    if (i < j) {
-      const double s = 0.5 * (A[(size_t)i * N + j] + A[(size_t)j * N + i]);
-      A[(size_t)i * N + j] = s;
-      A[(size_t)j * N + i] = s;
+
+  // W = L^-1: column blocks k in turn per wave; W_kk = T_k is already there,
+  // W_ik = -T_i (sum_{k <= j < i} L_ij W_jk) for i > k
+  for (int k = wave; k < nt; k += 4) {
+    for (int i = k + 1; i < nt; ++i) {
+      dbl4 c = {0.0, 0.0, 0.0, 0.0};
+      for (int j = k; j < i; ++j) c = mma_xy(A.at(i, j), Np, W.at(j, k), Np, li, lk, 1.0, c);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) sw[wave][4 * r + lk][li] = c[r];
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      const double* Ti = W.at(i, i);
+      dbl4 w = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int sl = 0; sl < 4; ++sl)
+        w = mfma_f64(-Ti[li * Np + 4 * sl + lk], sw[wave][4 * sl + lk][li], w);
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      tile_store_c(W.at(i, k), Np, li, lk, w);
+      // the tile is read back by other lanes of this wave for the next i
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
+  }
+  __syncthreads();
+
+  // A^-1 = W^T W: tile (I, J), I >= J, sum over K >= I of W_KI^T W_KJ,
+  // written with its mirror (J, I) over the no longer needed factor
+  for (int p = wave; p < nt * (nt + 1) / 2; p += 4) {
+    int I = 0;
+    while ((I + 1) * (I + 2) / 2 <= p) ++I;
+    const int J = p - I * (I + 1) / 2;
+    dbl4 c = {0.0, 0.0, 0.0, 0.0};
+    for (int Kt = I; Kt < nt; ++Kt) c = mma_xty(W.at(Kt, I), W.at(Kt, J), Np, li, lk, c);
+    tile_store_c(A.at(I, J), Np, li, lk, c);
+    if (I != J) {
+      double* t = A.at(J, I);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) t[li * Np + 4 * r + lk] = c[r];
     }
   }
 }
 
 void dense_coarse_inv(int n, int rows, const double* coef, int K, const double* cosT,
-                      double* ainv, hipStream_t s) {
+                      double* ainv, double* work, hipStream_t s) {
   if (rows <= 0) return;
-  hipLaunchKernelGGL(k_dense_coarse_inv, dim3(rows), dim3(256), 0, s, n, coef, K, cosT, ainv);
+  hipLaunchKernelGGL(k_dense_coarse_inv, dim3(rows), dim3(256), 0, s, n, coef, K, cosT, ainv,
+                     work);
 }
 
 // x = A^-1 b on the interior of every active problem's coarsest row (the
@@ -2144,10 +2285,11 @@ __global__ void __launch_bounds__(256)
   };
   for (int i = tid; i < N; i += 256) sbv[i] = (double)b[base + vtx(i)];
   __syncthreads();
-  const double* A = ainv + (size_t)prob * N * N;
+  const int Np = dense_pitch(N);
+  const double* A = ainv + (size_t)prob * Np * Np;
   for (int i = tid; i < N; i += 256) {
     double acc = 0.0;
-    for (int j = 0; j < N; ++j) acc += A[(size_t)j * N + i] * sbv[j];
+    for (int j = 0; j < N; ++j) acc += A[(size_t)j * Np + i] * sbv[j];
     x[base + vtx(i)] = (T)acc;
   }
 }

@@ -114,7 +114,8 @@ struct Plan {
   double* d_partial = nullptr;
   double* d_phi = nullptr;
   double* d_w = nullptr;
-  double* ainv = nullptr;  // coarsest-grid inverses [rows][N][N] when the hierarchy stops above 3^3
+  double* ainv = nullptr;  // coarsest-grid inverses [rows][Np][Np] when the hierarchy stops above 3^3
+  double* dwork = nullptr; // their factorisation's L^-1, same shape
   int dense_N = 0;
   long long npartial = 0;  // partial-sum slots (one per workgroup tile of every problem)
   void* arena = nullptr;
@@ -408,8 +409,11 @@ size_t plan_carve(mlsgd_ctx* c, Plan* P, char* base) {
   P->d_partial = cv.take<double>((size_t)P->npartial);
   P->d_phi = cv.take<double>(np);
   P->d_w = cv.take<double>(np);
-  if (P->dense_N)
-    P->ainv = cv.take<double>((size_t)P->sizes.back().rows * P->dense_N * P->dense_N);
+  if (P->dense_N) {
+    const size_t np = (size_t)dense_pitch(P->dense_N);
+    P->ainv = cv.take<double>((size_t)P->sizes.back().rows * np * np);
+    P->dwork = cv.take<double>((size_t)P->sizes.back().rows * np * np);
+  }
   return ((cv.off + 255) & ~(size_t)255) + 256;
 }
 
@@ -483,7 +487,7 @@ void plan_fields(mlsgd_ctx* c, Plan* P) {
   }
   if (P->dense_N) {
     const SizeLvl& co = P->sizes.back();
-    dense_coarse_inv(co.n, co.rows, P->d_coef, K, co.cosT, P->ainv, c->stream);
+    dense_coarse_inv(co.n, co.rows, P->d_coef, K, co.cosT, P->ainv, P->dwork, c->stream);
   }
   HIPCHK(hipGetLastError());
 }
@@ -2073,6 +2077,43 @@ int mlsgd_solve_state_adjoint_noalloc(mlsgd_ctx* c, int level, int coarse, int64
     plan_init(c, &T);   // the array keeps the previous call's contents
     plan_draws(c, &T, b, true);
     return solve_block(c, &T, n, count, y_out, p_out, phi_out, st);
+  });
+}
+
+int mlsgd_dense_coarse_inverse(mlsgd_ctx* c, int n, int level, int64_t first, int count,
+                               double* out) {
+  if (!c) return MLSGD_EINVAL;
+  return guard_impl(c, [&]() -> int {
+    require(n >= 4 && n <= 9, "n must be between 4 and 9");
+    require(level >= 0 && first >= 0 && count >= 1 && count <= 4096,
+            "need level >= 0, first >= 0 and 1 <= count <= 4096");
+    require(out != nullptr, "out is null");
+    const int K = c->pb.kl_K, K3 = K * K * K;
+    const int N = (n - 2) * (n - 2) * (n - 2), Np = dense_pitch(N);
+    std::vector<int> lv(count, level);
+    std::vector<int64_t> sm(count);
+    for (int j = 0; j < count; ++j) sm[j] = first + j;
+    char* buf = (char*)dalloc(c, sizeof(int) * count + sizeof(int64_t) * count +
+                                     sizeof(double) * ((size_t)count * K3 + 2 * (size_t)count * Np * Np) + 1024);
+    Carver cv{buf};
+    int* d_lv = cv.take<int>(count);
+    int64_t* d_sm = cv.take<int64_t>(count);
+    double* d_coef = cv.take<double>((size_t)count * K3);
+    double* d_ainv = cv.take<double>((size_t)count * Np * Np);
+    double* d_work = cv.take<double>((size_t)count * Np * Np);
+    HIPCHK(hipMemcpyAsync(d_lv, lv.data(), sizeof(int) * count, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(d_sm, sm.data(), sizeof(int64_t) * count, hipMemcpyHostToDevice,
+                          c->stream));
+    kl_coeffs(d_lv, d_sm, count, c->pb.seed, K, c->pb.kl_sigma2, c->pb.kl_law, c->pb.kl_rho,
+              d_coef, c->stream);
+    dense_coarse_inv(n, count, d_coef, K, cos_for(c, n), d_ainv, d_work, c->stream);
+    HIPCHK(hipGetLastError());
+    for (int j = 0; j < count; ++j)
+      HIPCHK(hipMemcpy2DAsync(out + (size_t)j * N * N, sizeof(double) * N,
+                              d_ainv + (size_t)j * Np * Np, sizeof(double) * Np,
+                              sizeof(double) * N, (size_t)N, hipMemcpyDeviceToDevice, c->stream));
+    dfree(c, buf);   // synchronises the stream first
+    return MLSGD_OK;
   });
 }
 
