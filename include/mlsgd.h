@@ -118,6 +118,10 @@ typedef struct mlsgd_grad_stats {
   double norm2_EX;         /* |E^ML[X]|_h^2 in units e^{2 theta s} */
   double ms_solve;         /* device time of the solves, ms */
   double ms_total;         /* device time of the whole estimate, ms */
+  /* per level: measured work per sample, interior unknowns x Krylov
+   * iterations summed over the level's state and adjoint solves on the fine
+   * and the coarse grid, divided by M; the adaptive controller's cost */
+  double work_per_sample[MLSGD_MAX_LEVELS];
 } mlsgd_grad_stats;
 
 typedef struct mlsgd_step_stats {
@@ -260,7 +264,8 @@ int mlsgd_set_batch(mlsgd_ctx* ctx, int L, const int64_t* M,
  * MLSGD) with fresh samples: the gradient uses the current batch and running
  * offsets, which then advance by M.  adapt is a set of flags:
  * MLSGD_ADAPT_BATCH runs the adaptive controller (Sec. 4.1: power sums,
- * optimal batch size, bias estimate, level growth) to choose the next batch;
+ * optimal batch size with the estimate's measured work per sample as the
+ * cost of a level, bias estimate, level growth) to choose the next batch;
  * MLSGD_ADAPT_STEP takes the adaptive step size of Sec. 5
  * (eq. adaptive-step-size: tau_k = (|g_k|^2 - err_sam) / (Lhat |g_k|^2),
  * Lhat = |g_k - g_{k-1}| / (tau_{k-1} |g_{k-1}|), clamped at 0), with tau as

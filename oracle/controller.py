@@ -5,7 +5,9 @@ Readings where the printed formulas are ambiguous (listed with the others in
 the design notes): the inner sum of the optimal batch size uses the previous
 iteration's statistics; the factor is 2/eps^2, which makes the sampling
 error of the unrounded batch exactly eps^2/2 (the stated target); the cost
-per sample is the number of interior unknowns of the fine and coarse grid;
+per sample is the measured work passed in (interior unknowns x Krylov
+iterations of the level's solves), or the interior-unknown count of the
+fine and coarse grid;
 the bias estimate extrapolates each level's correction to the finest level
 with the fitted rate; eps = 0.9 |g| of the gradient just computed; every
 level's batch, an added level's included, is capped at the number of samples
@@ -88,12 +90,15 @@ def bias_estimate(level_norms2, alpha_hat, L):
     return out
 
 
-def control(stats, M, grid, theta, grad_norm, n_levels_max=None):
-    """One controller update from the statistics of the estimate just made."""
+def control(stats, M, grid, theta, grad_norm, n_levels_max=None, costs=None):
+    """One controller update from the statistics of the estimate just made.
+    costs: the measured cost per sample of each level (the paper uses the
+    previous iteration's measured average cost); the interior-unknown count
+    of level_costs when not given."""
     L = len(M)
     v2, chat, sc = power_sums(stats, theta, L)
     eps = 0.9 * grad_norm
-    C = level_costs(grid[:L])
+    C = list(costs[:L]) if costs is not None else level_costs(grid[:L])
     Mn = optimal_batch(v2, M, C, eps, caps=[batch_cap(n) for n in grid[:L]])
     e2 = [(stats["norm2_mean_dX"][i] + chat * stats["mean_dY"][i] ** 2) * sc * sc
           for i in range(L)]

@@ -82,6 +82,7 @@ class _GradStats(ctypes.Structure):
         ("mean_phi_f", _D8),
         ("grad_norm", ctypes.c_double), ("norm2_EX", ctypes.c_double),
         ("ms_solve", ctypes.c_double), ("ms_total", ctypes.c_double),
+        ("work_per_sample", _D8),
     ]
 
     def as_dict(self, L):

@@ -261,7 +261,14 @@ struct EpiOut {     // device-side scalar results, copied to the host once
   double s, EY, denom, J, gnorm2, unorm2, exnorm2;
   double mean_dY[8], norm2_mean_dX[8], m2_dX[8], m2_dY[8], mean_phi_f[8];
   int truncated, pad;
+  unsigned long long work[8];  // per level: sum of interior unknowns x Krylov iterations
 };
+// zero the per-level work sums of an estimate
+void level_work_zero(EpiOut* out, hipStream_t s);
+// add every problem's interior unknowns x iterations (its grid has n vertices
+// per axis) to the work sum of the level whose draw it uses
+void level_work_add(int count, int n, const int* prob_level, const CgScal* scal, EpiOut* out,
+                    hipStream_t s);
 void epilogue_scalars(int L, const EpiLevel* lev, const double* phi, const double* w,
                       const double* part, long long u_off, int nL, double theta,
                       double alpha, int with_dx, EpiOut* out, hipStream_t s);

@@ -2882,6 +2882,29 @@ __global__ void k_zero_int(int* x) {
   if (threadIdx.x == 0) *x = 0;
 }
 
+__global__ void k_level_work_zero(EpiOut* out) {
+  if (threadIdx.x < 8) out->work[threadIdx.x] = 0ull;
+}
+void level_work_zero(EpiOut* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_level_work_zero, dim3(1), dim3(64), 0, s, out);
+}
+// Integer sums (exact, order-independent) of the problems' interior unknowns
+// x iterations per level.
+__global__ void k_level_work_add(int count, unsigned long long per, const int* __restrict__ lvl,
+                                 const CgScal* __restrict__ scal, EpiOut* out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= count) return;
+  const int l = lvl[p];
+  if (l >= 0 && l < 8) atomicAdd(&out->work[l], per * (unsigned long long)scal[p].iters);
+}
+void level_work_add(int count, int n, const int* prob_level, const CgScal* scal, EpiOut* out,
+                    hipStream_t s) {
+  if (count <= 0) return;
+  const unsigned long long per = (unsigned long long)(n - 2) * (n - 2) * (n - 2);
+  hipLaunchKernelGGL(k_level_work_add, dim3((count + 255) / 256), dim3(256), 0, s, count, per,
+                     prob_level, scal, out);
+}
+
 void cg_scalar(int phase, CgScal* scal, int nprob, const int* poff, const int* pcnt,
                const double* partial, double rtol, int max_iters, int* active_count,
                hipStream_t s, int aux) {

@@ -1440,12 +1440,19 @@ void estimate_enqueue(mlsgd_ctx* c, const EstPrep& e, int L, const int64_t* M, c
   Plan* P = e.P;
   level_rhs(c, u);
   if (fixed_s > 0) plan_fields(c, P);
+  level_work_zero(c->d_epi_out, s);
+  auto add_work = [&]() {   // the iterations of the solves just finished, per level
+    for (const auto& gr : P->groups)
+      level_work_add(gr.count, gr.n, P->d_level + gr.p0, P->d_scal + gr.p0, c->d_epi_out, s);
+  };
   state_phase(c, P, it_s, nc_s, rr_s, nullptr, fixed_s);
+  add_work();
   if (grad_out) {
     if (fixed_a > 0)
       krylov_fixed(c, P, fixed_a, 1);
     else
       krylov(c, P, it_a, nc_a, rr_a);
+    add_work();
   }
   if (fixed_s <= 0) HIPCHK(hipEventRecord(c->ev[1], s));
   shift_weights(P->nprob, P->d_phi, c->pb.theta, P->d_w, &c->d_epi_out->s, s);
@@ -1501,8 +1508,8 @@ void validate_batch(mlsgd_ctx* c, int L, const int64_t* M, const int64_t* first)
 }
 
 // Statistics of a finished estimate from the epilogue record.
-int finish_stats(mlsgd_ctx* c, int L, bool grad, double* J_out, mlsgd_grad_stats* st, int it_s,
-                 int it_a, int nc, double rr) {
+int finish_stats(mlsgd_ctx* c, int L, const int64_t* M, bool grad, double* J_out,
+                 mlsgd_grad_stats* st, int it_s, int it_a, int nc, double rr) {
   const EpiOut& eo = *c->h_epi_out;
   if (J_out) *J_out = eo.J;
   if (st) {
@@ -1522,6 +1529,7 @@ int finish_stats(mlsgd_ctx* c, int L, bool grad, double* J_out, mlsgd_grad_stats
       st->m2_dY[i] = eo.m2_dY[i];
       st->mean_phi_f[i] = eo.mean_phi_f[i];
     }
+    for (int i = 0; i < L; ++i) st->work_per_sample[i] = (double)eo.work[i] / (double)M[i];
     st->grad_norm = grad ? std::sqrt(eo.gnorm2) : 0.0;
     st->norm2_EX = grad ? eo.exnorm2 : 0.0;
     float ms1 = 0, ms2 = 0;
@@ -1552,7 +1560,7 @@ int run_estimate_eager(mlsgd_ctx* c, const double* u, int L, const int64_t* M,
   HIPCHK(hipEventRecord(c->ev[2], s));
   HIPCHK(hipMemcpyAsync(c->h_epi_out, c->d_epi_out, sizeof(EpiOut), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  return finish_stats(c, L, grad_out != nullptr, J_out, st, it_s, it_a, nc_s + nc_a,
+  return finish_stats(c, L, M, grad_out != nullptr, J_out, st, it_s, it_a, nc_s + nc_a,
                       std::max(rr_s, rr_a));
 }
 
@@ -1642,7 +1650,7 @@ int run_estimate_graph(mlsgd_ctx* c, const double* u, int L, const int64_t* M,
     HIPCHK(hipMemcpyAsync(grad_out, c->d_g_graph, sizeof(double) * cube(c->nfin),
                           hipMemcpyDeviceToDevice, s));
   const double rr = std::max(st_s.relres, grad_out ? st_a.relres : 0.0);
-  return finish_stats(c, L, grad_out != nullptr, J_out, st, st_s.iters,
+  return finish_stats(c, L, M, grad_out != nullptr, J_out, st, st_s.iters,
                       grad_out ? st_a.iters : 0, 0, rr);
 }
 
@@ -1655,9 +1663,11 @@ int run_estimate(mlsgd_ctx* c, const double* u, int L, const int64_t* M, const i
 // Adaptive controller (Sec. 4.1): second-order power sums v^2 per level,
 // optimal batch sizes for a sampling error eps^2/2, sampling-error estimate,
 // squared-bias estimate and the level update.  Units: the paper's unshifted
-// X, Y (statistics are rescaled by e^{theta s}).  Costs: the deterministic
-// model C_i = interior unknowns (fine + coarse) per sample, so the batch
-// sequence is reproducible.  eps = 0.9 |g| of the gradient just computed.
+// X, Y (statistics are rescaled by e^{theta s}).  Costs: the measured work
+// per sample of each level in the estimate just made (interior unknowns x
+// Krylov iterations over its state and adjoint solves, fine and coarse), an
+// exact integer count, so the batch sequence is reproducible.  eps = 0.9 |g|
+// of the gradient just computed.
 // Every level's batch, an added level's included, is capped at the samples
 // whose solver arrays (14 arrays of n^3 doubles each) fit 32 GiB.
 struct CtrlOut {
@@ -1680,9 +1690,12 @@ CtrlOut controller(const mlsgd_ctx* c, const mlsgd_grad_stats& g, int L, const i
   double v2[MLSGD_MAX_LEVELS], C[MLSGD_MAX_LEVELS];
   for (int i = 0; i < L; ++i) {
     v2[i] = (g.m2_dX[i] + Chat * g.m2_dY[i]) * sc * sc;
+    // cost per sample: the estimate's measured work on the level (interior
+    // unknowns x Krylov iterations of its fine and coarse, state and adjoint
+    // solves); the unknown count where no work was recorded
     const double nf = (double)(c->pb.grid_n[i] - 2);
     const double ncs = i > 0 ? (double)(c->pb.grid_n[i - 1] - 2) : 0.0;
-    C[i] = nf * nf * nf + ncs * ncs * ncs;
+    C[i] = g.work_per_sample[i] > 0.0 ? g.work_per_sample[i] : nf * nf * nf + ncs * ncs * ncs;
   }
   const double eps = 0.9 * g.grad_norm;
   o.eps = eps;

@@ -112,3 +112,27 @@ def test_batch_cap_bounds_every_level_including_an_added_one():
     out = ctl.control(stats, [4, 4, 4], grid, theta=0.0, grad_norm=1e-9, n_levels_max=4)
     assert out["L"] == 4
     assert out["M_next"] == [ctl.batch_cap(n) for n in grid]
+
+
+def test_costs_enter_only_through_their_ratios():
+    """The optimal batch depends on the level costs only through their ratios
+    (a common unit, seconds or unknowns x iterations, cancels), and the
+    default costs are the interior-unknown counts."""
+    stats = {"s": 0.1, "EY_shifted": 1.0, "norm2_EX": 0.5,
+             "m2_dX": [3.0, 1.0, 0.2], "m2_dY": [0.3, 0.1, 0.02],
+             "norm2_mean_dX": [1.0, 0.1, 0.05], "mean_dY": [1.0, 0.01, 0.005]}
+    grid, M = [9, 17, 33], [40, 20, 10]
+    base = ctl.control(stats, M, grid, theta=0.5, grad_norm=0.02)
+    same = ctl.control(stats, M, grid, theta=0.5, grad_norm=0.02, costs=ctl.level_costs(grid))
+    scaled = ctl.control(stats, M, grid, theta=0.5, grad_norm=0.02,
+                         costs=[17.0 * c for c in ctl.level_costs(grid)])
+    assert base["M_next"] == same["M_next"] == scaled["M_next"]
+    # a level made twice as expensive gets fewer samples, by sqrt(2) before rounding
+    C = ctl.level_costs(grid)
+    C2 = [C[0], 2.0 * C[1], C[2]]
+    v2, _, _ = ctl.power_sums(stats, 0.5, 3)
+    r1 = ctl.optimal_batch(v2, M, C, 0.018, ceil=False)
+    r2 = ctl.optimal_batch(v2, M, C2, 0.018, ceil=False)
+    tot1 = sum(math.sqrt(v / max(m - 1, 1) * c) for v, m, c in zip(v2, M, C))
+    tot2 = sum(math.sqrt(v / max(m - 1, 1) * c) for v, m, c in zip(v2, M, C2))
+    assert r2[1] / r1[1] == pytest.approx(tot2 / tot1 / math.sqrt(2.0), rel=1e-12)

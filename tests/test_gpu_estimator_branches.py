@@ -86,7 +86,7 @@ def test_library_controller_adds_a_level(mm, orc):
     ctx.close()
     gs = st["grad"]
     out = ctl.control(gs, M, grid, theta=lc["theta"], grad_norm=gs["grad_norm"],
-                      n_levels_max=len(grid))
+                      n_levels_max=len(grid), costs=gs["work_per_sample"])
     assert out["L"] == 3 and out["err_num"] > 0.5 * out["eps"] ** 2
     assert st["M_next"] == out["M_next"]
     assert st["err_num"] == pytest.approx(out["err_num"], rel=1e-12)

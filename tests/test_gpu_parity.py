@@ -262,7 +262,15 @@ def test_adaptive_controller_matches_oracle(mm, orc):
     h = 1.0 / (nL - 1)
     gn = math.sqrt(h ** 3 * float(np.sum(go[1:-1, 1:-1, 1:-1] ** 2)))
     assert st["grad"]["grad_norm"] == pytest.approx(gn, rel=1e-9)
-    out = ctl.control(so, M, grid, theta=2.0, grad_norm=gn, n_levels_max=3)
+    # the library's cost per level: its measured work per sample, between
+    # one iteration and the slowest solve's count for every state and adjoint
+    # solve of the level
+    work = st["grad"]["work_per_sample"]
+    its = st["grad"]["iters_state"] + st["grad"]["iters_adjoint"]
+    for i, n in enumerate(grid):
+        unk = (n - 2) ** 3 + ((grid[i - 1] - 2) ** 3 if i else 0)
+        assert 2 * unk <= work[i] <= its * unk
+    out = ctl.control(so, M, grid, theta=2.0, grad_norm=gn, n_levels_max=3, costs=work)
     assert st["eps"] == pytest.approx(out["eps"], rel=1e-9)
     assert st["err_sam"] == pytest.approx(out["err_sam"], rel=1e-7)
     assert st["err_num"] == pytest.approx(out["err_num"], rel=1e-6)
