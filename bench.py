@@ -65,6 +65,8 @@ def parse():
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain device copy of known size (counter calibration)")
+    ap.add_argument("--odd-size", action="store_true",
+                    help="only run the batch of 300 independent odd-size solves")
     ap.add_argument("--quiet", action="store_true")
     return ap.parse_args()
 
@@ -522,6 +524,11 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args)
+        return
+    if args.odd_size:
+        import torch
+        import paper_2606_09291_amd as m
+        print(json.dumps(odd_size_solves(m, torch.device("cuda:0"))), flush=True)
         return
     if args.rates:
         run_rates(args)
