@@ -57,7 +57,7 @@ extern "C" {
 /* precision of the solves */
 #define MLSGD_FP64 0          /* FP64 everywhere */
 #define MLSGD_MIXED_FP32 1    /* FP32 V-cycles inside FP64 refinement */
-#define MLSGD_MIXED_BF16 2    /* as MIXED_FP32 with BF16-stored smoothing */
+#define MLSGD_MIXED_BF16 2    /* as MIXED_FP32, the smoother's 1/a cache in bfloat16 */
 
 /* outer solver */
 #define MLSGD_SOLVER_CG 0     /* unpreconditioned conjugate gradients */
