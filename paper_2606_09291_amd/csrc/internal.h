@@ -108,16 +108,23 @@ void march_jac2z(const GridArgs& g, const T* dinv, const T* b, T* xout, double o
 inline bool fused_tiles(const GridArgs& g) {
   return g.cache != nullptr && ((g.t.TZ == 64 && g.t.TY >= 8) || g.t.TZ == 32 || g.t.TZ == 16);
 }
+// the x chunks of g start on odd planes (one chunk, or chunks of even length)
+inline bool pre2r_half_tiles(const GridArgs& g) {
+  return g.t.nxc == 1 || (g.t.xchunk & 1) == 0;
+}
 // the same two steps and the residual of their result in one pass:
 // xout = J(omega2) J(omega1) 0, rout = b - A xout (tiles and coefficient as
-// fused_tiles; returns false, launching nothing, otherwise)
+// fused_tiles; returns false, launching nothing, otherwise).  half: rout
+// receives instead the x part of the full-weighting restriction of the
+// residual, plane I = r(2I-1)/4 + r(2I)/2 + r(2I+1)/4 at interior columns, for
+// restrict_yz_rows (also needs pre2r_half_tiles)
 template <typename T>
 bool march_pre2r(const GridArgs& g, const T* dinv, const T* b, T* xout, T* rout, double omega1,
-                 double omega2, hipStream_t s);
+                 double omega2, bool half, hipStream_t s);
 // two Jacobi steps after the coarse-grid correction in one pass:
 // xout = J(omega_b) J(omega_a) (xin + P xc), partials of <b, xout> for the
-// problems >= top_begin (partial nullable); same tile and coefficient
-// conditions (and xc non-null), false otherwise
+// problems >= top_begin (partial nullable); xin null: x = 0, not read; same
+// tile and coefficient conditions (and xc non-null), false otherwise
 template <typename T>
 bool march_post2(const GridArgs& g, const T* xin, const T* xc, const T* b, T* xout,
                  double omega_a, double omega_b, const int* poff, double* partial, int top_begin,
@@ -143,6 +150,10 @@ void vcycle_small(int rows, const double* om, int deg, int top_begin, const CgSc
 template <typename T>
 void restrict_rows(int nf, int rows, int row0, const CgScal* scal, const T* fine,
                    T* coarse, hipStream_t s);
+// the y and z parts of full weighting from march_pre2r's half output
+template <typename T>
+void restrict_yz_rows(int nf, int rows, int row0, const CgScal* scal, const T* h, T* coarse,
+                      hipStream_t s);
 template <typename T>
 void prolong_add_rows(int nc, int rows, int row0, const CgScal* scal, const T* coarse,
                       T* fine, hipStream_t s);

@@ -699,8 +699,17 @@ template void march_jac2z<float>(const GridArgs&, const float*, const float*, fl
 // formed for x2 on plane q and reuses them for r on that plane one step
 // later.  The loads of plane q + 2 are issued at the start of step q and
 // combined at its end.
+//
+// RH: instead of r, the x part of the full-weighting restriction of r,
+//   h(I) = r(2I-1) / 4 + r(2I) / 2 + r(2I+1) / 4   (per interior column)
+// goes into plane I of rout, for the coarse planes I with x0 < 2I < x1 of
+// the workgroup's x chunk (x0 odd: one chunk, or chunks of even length), so
+// every coarse plane is written by one chunk; the march forms r on one more
+// plane (x1) for the last of them.  k_restrict_yz_rows finishes the
+// restriction from h: 28 instead of 32 B per fine point for the pass and
+// the restriction's read.
 // ---------------------------------------------------------------------------
-template <typename T, int TY, int TZ, int CK>
+template <typename T, int TY, int TZ, int CK, bool RH>
 __global__ void __launch_bounds__(TY* TZ)
     k_pre2r(GridArgs g, const T* __restrict__ dinv, const T* __restrict__ rhs,
             T* __restrict__ xout, T* __restrict__ rout, T omega1, T omega2) {
@@ -808,6 +817,8 @@ __global__ void __launch_bounds__(TY* TZ)
 
   const int x0 = 1 + xc * g.t.xchunk;
   const int x1 = min(x0 + g.t.xchunk, n - 1);
+  // last step: r on plane x1 as well when the restriction reads it
+  const int qend = RH ? min(x1 + 1, n - 1) : x1;
 
   // On entry to step q: x1 and 1/a at q-1, q, q+1 and b at q, q+1 for the
   // patch column (o*) and the slot (s*; two-point ring slots and corners use
@@ -830,11 +841,12 @@ __global__ void __launch_bounds__(TY* TZ)
     }
   }
 
-  // patch column: x2 at q-2, q-1, the faces of plane q-1 and b at q-1
-  T x2a = T(0), x2b = T(0), rm_ = T(0);
+  // patch column: x2 at q-2, q-1, the faces of plane q-1 and b at q-1; with
+  // RH the partial h of the coarse plane being summed
+  T x2a = T(0), x2b = T(0), rm_ = T(0), hacc = T(0);
   T gfxm = T(0), gfxp = T(0), gfym = T(0), gfyp = T(0), gfzm = T(0), gfzp = T(0), gdiag = T(1);
 
-  for (int q = x0 - 1; q <= x1; ++q) {
+  for (int q = x0 - 1; q <= qend; ++q) {
     const Raw on = load(q + 2, ooff);
     Raw sn{T(0), T(0), one};
     if (s_on) sn = load(q + 2, soff);
@@ -889,8 +901,22 @@ __global__ void __launch_bounds__(TY* TZ)
                     (gfzm * x2p[oidx - 1] + gfzp * x2p[oidx + 1]);
       const T r = rm_ - ih2 * (gdiag * x2b - off);
       const size_t e = base + ((size_t)qr * n + oy) * LP + oz + LO;
-      __builtin_nontemporal_store(x2b, &xout[e]);
-      __builtin_nontemporal_store(r, &rout[e]);
+      if constexpr (RH) {
+        if (qr < x1) __builtin_nontemporal_store(x2b, &xout[e]);
+        if (qr & 1) {
+          // r(qr) closes coarse plane (qr - 1) / 2 and opens (qr + 1) / 2
+          if (qr >= x0 + 2) {
+            const size_t eh = base + ((size_t)((qr - 1) >> 1) * n + oy) * LP + oz + LO;
+            __builtin_nontemporal_store(hacc + T(0.25) * r, &rout[eh]);
+          }
+          hacc = T(0.25) * r;
+        } else {
+          hacc = hacc + T(0.5) * r;
+        }
+      } else {
+        __builtin_nontemporal_store(x2b, &xout[e]);
+        __builtin_nontemporal_store(r, &rout[e]);
+      }
     }
 
     // advance one plane
@@ -911,18 +937,22 @@ __global__ void __launch_bounds__(TY* TZ)
 
 template <typename T>
 bool march_pre2r(const GridArgs& g, const T* dinv, const T* b, T* xout, T* rout, double omega1,
-                 double omega2, hipStream_t s) {
-  if (!fused_tiles(g)) return false;
+                 double omega2, bool half, hipStream_t s) {
+  if (!fused_tiles(g) || (half && !pre2r_half_tiles(g))) return false;
   if (g.rows <= 0) return true;
   const int nblk = g.rows * g.t.tiles_per_row;
-#define MLSGD_LAUNCH(TY_, TZ_, CK_)                                                     \
-  hipLaunchKernelGGL((k_pre2r<T, TY_, TZ_, CK_>), dim3(nblk), dim3(TY_ * TZ_), 0, s, g, \
+#define MLSGD_LAUNCH(TY_, TZ_, CK_, RH_)                                                     \
+  hipLaunchKernelGGL((k_pre2r<T, TY_, TZ_, CK_, RH_>), dim3(nblk), dim3(TY_ * TZ_), 0, s, g, \
                      dinv, b, xout, rout, (T)omega1, (T)omega2)
-#define MLSGD_LAUNCH2(TY_, TZ_)  \
-  if (b16)                       \
-    MLSGD_LAUNCH(TY_, TZ_, 2);   \
-  else                           \
-    MLSGD_LAUNCH(TY_, TZ_, 1)
+#define MLSGD_LAUNCH2(TY_, TZ_)         \
+  if (b16 && half)                      \
+    MLSGD_LAUNCH(TY_, TZ_, 2, true);    \
+  else if (b16)                         \
+    MLSGD_LAUNCH(TY_, TZ_, 2, false);   \
+  else if (half)                        \
+    MLSGD_LAUNCH(TY_, TZ_, 1, true);    \
+  else                                  \
+    MLSGD_LAUNCH(TY_, TZ_, 1, false)
   const bool b16 = sizeof(T) == 4 && g.cache_bf16;
   if (g.t.TZ == 16) {
     MLSGD_LAUNCH2(16, 16);
@@ -938,9 +968,9 @@ bool march_pre2r(const GridArgs& g, const T* dinv, const T* b, T* xout, T* rout,
   return true;
 }
 template bool march_pre2r<double>(const GridArgs&, const double*, const double*, double*,
-                                  double*, double, double, hipStream_t);
+                                  double*, double, double, bool, hipStream_t);
 template bool march_pre2r<float>(const GridArgs&, const float*, const float*, float*, float*,
-                                 double, double, hipStream_t);
+                                 double, double, bool, hipStream_t);
 
 // ---------------------------------------------------------------------------
 // Fused post-smoothing: two Chebyshev steps after the coarse-grid correction
@@ -965,8 +995,12 @@ template bool march_pre2r<float>(const GridArgs&, const float*, const float*, fl
 // read their y and z faces instead of forming them; in FP32, whose
 // reciprocal is one instruction, they are formed from 1/a where used (a
 // three-plane 1/a ring), which measured faster.
+//
+// XZ: x is zero and not read (y = P e, 25 B per point), for the
+// pre-smoothing of a full-multigrid cycle from the prolonged solution of the
+// grid below.
 // ---------------------------------------------------------------------------
-template <typename T, int TY, int TZ, int CK>
+template <typename T, int TY, int TZ, int CK, bool XZ>
 __global__ void __launch_bounds__(TY* TZ)
     k_post2(GridArgs g, const T* __restrict__ xin, const T* __restrict__ xc,
             const T* __restrict__ rhs, T* __restrict__ xout, const int* __restrict__ poff,
@@ -1055,7 +1089,7 @@ __global__ void __launch_bounds__(TY* TZ)
   // correction vanishes on the boundary.  Ring slots outside the grid read
   // the nearest in-grid column; their values feed only results at
   // non-interior positions, which are set to zero or discarded.
-  const T* __restrict__ xrow = xin + base;
+  const T* __restrict__ xrow = XZ ? nullptr : xin + base;
   const T* __restrict__ brow = rhs + base;
   const uint32_t pstr = (uint32_t)n * (uint32_t)LP;
   auto col_off = [&](int jy, int jz) -> uint32_t {
@@ -1070,7 +1104,7 @@ __global__ void __launch_bounds__(TY* TZ)
     if (ix < 0 || ix > n - 1) return v;   // uniform
     const size_t e = (size_t)off + (size_t)ix * pstr;
     v.a = cache[e];
-    v.x = xrow[e];
+    if constexpr (!XZ) v.x = xrow[e];
     v.b = brow[e];
     return v;
   };
@@ -1297,14 +1331,18 @@ bool march_post2(const GridArgs& g, const T* xin, const T* xc, const T* b, T* xo
   if (!fused_tiles(g) || !xc) return false;
   if (g.rows <= 0) return true;
   const int nblk = g.rows * g.t.tiles_per_row;
-#define MLSGD_LAUNCH(TY_, TZ_, CK_)                                                        \
-  hipLaunchKernelGGL((k_post2<T, TY_, TZ_, CK_>), dim3(nblk), dim3(TY_ * TZ_), 0, s, g, xin, \
-                     xc, b, xout, poff, partial, top_begin, (T)omega_a, (T)omega_b)
-#define MLSGD_LAUNCH2(TY_, TZ_)  \
-  if (b16)                       \
-    MLSGD_LAUNCH(TY_, TZ_, 2);   \
-  else                           \
-    MLSGD_LAUNCH(TY_, TZ_, 1)
+#define MLSGD_LAUNCH(TY_, TZ_, CK_, XZ_)                                                 \
+  hipLaunchKernelGGL((k_post2<T, TY_, TZ_, CK_, XZ_>), dim3(nblk), dim3(TY_ * TZ_), 0, s, g, \
+                     xin, xc, b, xout, poff, partial, top_begin, (T)omega_a, (T)omega_b)
+#define MLSGD_LAUNCH2(TY_, TZ_)         \
+  if (b16 && !xin)                      \
+    MLSGD_LAUNCH(TY_, TZ_, 2, true);    \
+  else if (b16)                         \
+    MLSGD_LAUNCH(TY_, TZ_, 2, false);   \
+  else if (!xin)                        \
+    MLSGD_LAUNCH(TY_, TZ_, 1, true);    \
+  else                                  \
+    MLSGD_LAUNCH(TY_, TZ_, 1, false)
   const bool b16 = sizeof(T) == 4 && g.cache_bf16;
   if (g.t.TZ == 16) {
     MLSGD_LAUNCH2(16, 16);
@@ -1924,6 +1962,36 @@ __global__ void k_restrict_rows(int nf, int rows, int row0, const CgScal* scal,
   }
 }
 
+// The y and z parts of full weighting after k_pre2r's x part: coarse vertex
+// (I, J, K) = sum over dy of w(dy) (h(I, 2J+dy, 2K-1) / 4 + h(I, 2J+dy, 2K) / 2
+// + h(I, 2J+dy, 2K+1) / 4), w = 1/2 at dy = 0 and 1/4 at dy = +-1, with h
+// plane I held in plane I of the fine row.
+template <typename T>
+__global__ void k_restrict_yz_rows(int nf, int rows, int row0, const CgScal* scal,
+                                   const T* __restrict__ h, T* __restrict__ coarse) {
+  const int nc = (nf - 1) / 2 + 1, mc = nc - 2;
+  const long long per = (long long)mc * mc * mc;
+  const long long total = per * rows;
+  const size_t sf = (size_t)lay_row(nf), scs = (size_t)lay_row(nc);
+  const int fp = lay_pitch(nf), fo = lay_off(nf), cp = lay_pitch(nc), co = lay_off(nc);
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int row = (int)(i / per);
+    if (scal && !scal[row0 + row].active) continue;
+    const int r = (int)(i - (long long)row * per);
+    const int jx = 1 + r / (mc * mc), jy = 1 + (r / mc) % mc, jz = 1 + r % mc;
+    const T* f = h + (size_t)row * sf;
+    T acc = T(0);
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const T wy = dy == 0 ? T(0.5) : T(0.25);
+      const T* p = f + ((size_t)jx * nf + (2 * jy + dy)) * fp + 2 * jz + fo;
+      acc += wy * (T(0.25) * p[-1] + T(0.5) * p[0] + T(0.25) * p[1]);
+    }
+    coarse[(size_t)row * scs + ((size_t)jx * nc + jy) * cp + jz + co] = acc;
+  }
+}
+
 template <typename T>
 __global__ void k_prolong_add_rows(int nc, int rows, int row0, const CgScal* scal,
                                    const T* __restrict__ coarse, T* __restrict__ fine, int set) {
@@ -1991,6 +2059,19 @@ void restrict_rows(int nf, int rows, int row0, const CgScal* scal, const T* fine
   hipLaunchKernelGGL(k_restrict_rows<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, nf, rows,
                      row0, scal, fine, coarse);
 }
+template <typename T>
+void restrict_yz_rows(int nf, int rows, int row0, const CgScal* scal, const T* h, T* coarse,
+                      hipStream_t s) {
+  if (rows <= 0) return;
+  const int mc = (nf - 1) / 2 - 1;
+  const long long total = (long long)mc * mc * mc * rows;
+  hipLaunchKernelGGL(k_restrict_yz_rows<T>, dim3(grid_for(total, 256)), dim3(256), 0, s, nf,
+                     rows, row0, scal, h, coarse);
+}
+template void restrict_yz_rows<double>(int, int, int, const CgScal*, const double*, double*,
+                                       hipStream_t);
+template void restrict_yz_rows<float>(int, int, int, const CgScal*, const float*, float*,
+                                      hipStream_t);
 template <typename T>
 void prolong_add_rows(int nc, int rows, int row0, const CgScal* scal, const T* coarse, T* fine,
                       hipStream_t s) {

@@ -195,6 +195,7 @@ struct mlsgd_ctx {
   int tile_y = 8;           // y extent of the stencil tiles on large grids
   int xchunk = 32;          // x planes per workgroup
   bool pre2r = true;        // fused pre-smoothing and residual pass where it applies
+  bool pre2r_half = true;   // that pass writes the residual restricted along x
   bool post2 = true;        // fused two-step post-smoothing pass where it applies
   bool vsmall = true;       // the cycle from 9^3 down as one kernel where it applies
   bool xdefer = true;       // x's Krylov step applied by the next matvec
@@ -683,12 +684,13 @@ double jac_bytes(int n, int rows, bool x_zero, bool prolong, const GridArgs&) {
   return N * b;
 }
 
-// Algorithmic bytes of the fused pre-smoothing pass from x = 0: b read, x2 and
-// the residual written (coefficient and reciprocal diagonal: 0 bytes).
+// Algorithmic bytes of the fused pre-smoothing pass from x = 0: b read, x2
+// written, and the residual (half: its x-restricted half, on every second
+// plane) written (coefficient and reciprocal diagonal: 0 bytes).
 template <typename T>
-double pre2r_bytes(int n, int rows) {
+double pre2r_bytes(int n, int rows, bool half) {
   const double N = (double)rows * (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
-  return N * 3.0 * (double)sizeof(T);
+  return N * (half ? 2.5 : 3.0) * (double)sizeof(T);
 }
 
 // Algorithmic bytes of the fused post-smoothing pass: x and b read, x''
@@ -718,8 +720,8 @@ const float* dinv_of<float>(const SizeLvl& L) { return L.Dif; }
 //
 // k0, rlim, xinit serve the full-multigrid start: the cycle then begins on
 // grid size k0, covers rows 0 .. rlim-1 of every size (the problems whose top
-// grid is k0 or larger), and its pre-smoothing on k0 starts from the guess
-// in the X rows instead of from zero.
+// grid is k0 or larger), and its pre-smoothing on k0 starts from the
+// prolonged current solution of size k0 + 1 instead of from zero.
 template <typename T>
 void vcycle_cheb(mlsgd_ctx* c, Plan* P, int k0 = 0, int rlim = INT_MAX, bool xinit = false) {
   const int S = (int)P->sizes.size();
@@ -773,11 +775,20 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P, int k0 = 0, int rlim = INT_MAX, bool xin
     int j0 = 1;
     const T* dinv = dinv_of<T>(L);
     if (xinit && k == k0) {
-      // pre-smoothing from the guess in the X rows
-      for (int j = 0; j < deg; ++j) {
-        march_jac<T>(g, A[cur], nullptr, v.B, A[cur ^ 1], 0, om[j], nullptr, nullptr, 0,
-                     c->stream);
-        cur ^= 1;
+      // pre-smoothing from the prolonged solution of the grid below
+      SizeLvl& Lc = P->sizes[k + 1];
+      const T* xc = Lc.cur ? mg_view<T>(Lc).R : mg_view<T>(Lc).X;
+      if (deg == 2 && c->post2 && fused_tiles(g)) {
+        // prolongation and both steps in one pass (x = 0 plus the correction)
+        march_post2<T>(g, nullptr, xc, v.B, A[1], om[0], om[1], nullptr, nullptr, 0, c->stream);
+        cur = 1;
+      } else {
+        prolong_rows<T>(Lc.n, g.rows, xc, A[0], c->stream);
+        for (int j = 0; j < deg; ++j) {
+          march_jac<T>(g, A[cur], nullptr, v.B, A[cur ^ 1], 0, om[j], nullptr, nullptr, 0,
+                       c->stream);
+          cur ^= 1;
+        }
       }
       march_resid<T>(g, A[cur], v.B, A[cur ^ 1], c->stream);
       restrict_rows<T>(L.n, g.rows, 0, P->d_scal, A[cur ^ 1], mg_view<T>(P->sizes[k + 1]).B,
@@ -786,12 +797,19 @@ void vcycle_cheb(mlsgd_ctx* c, Plan* P, int k0 = 0, int rlim = INT_MAX, bool xin
       continue;
     }
     if (deg == 2 && dinv && c->pre2r && fused_tiles(g)) {
-      timed_launch(c, g, pre2r_bytes<T>(L.n, g.rows), [&] {
-        march_pre2r<T>(g, dinv, v.B, A[1], A[0], om[0], om[1], c->stream);
+      // both pre-smoothing steps and the residual in one pass: x2 in A[1],
+      // and in A[0] r or (half) r restricted along x, then the rest of the
+      // restriction
+      const bool half = c->pre2r_half && pre2r_half_tiles(g);
+      timed_launch(c, g, pre2r_bytes<T>(L.n, g.rows, half), [&] {
+        march_pre2r<T>(g, dinv, v.B, A[1], A[0], om[0], om[1], half, c->stream);
       }, 3);
-      // both pre-smoothing steps and the residual in one pass: x2 in A[1], r in A[0]
-      restrict_rows<T>(L.n, g.rows, 0, P->d_scal, A[0], mg_view<T>(P->sizes[k + 1]).B,
-                       c->stream);
+      if (half)
+        restrict_yz_rows<T>(L.n, g.rows, 0, P->d_scal, A[0], mg_view<T>(P->sizes[k + 1]).B,
+                            c->stream);
+      else
+        restrict_rows<T>(L.n, g.rows, 0, P->d_scal, A[0], mg_view<T>(P->sizes[k + 1]).B,
+                         c->stream);
       L.cur = 1;
       continue;
     }
@@ -1047,9 +1065,6 @@ void fmg_start(mlsgd_ctx* c, Plan* P) {
   }
   for (int k = S - 2; k >= 0; --k) {
     SizeLvl& L = P->sizes[k];
-    SizeLvl& Lc = P->sizes[k + 1];
-    const T* xc = Lc.cur ? mg_view<T>(Lc).R : mg_view<T>(Lc).X;
-    prolong_rows<T>(Lc.n, L.rows, xc, mg_view<T>(L).X, s);
     vcycle_cheb<T>(c, P, k, L.rows, true);
     const T* xk = L.cur ? mg_view<T>(L).R : mg_view<T>(L).X;
     for (auto& gr : P->groups)
@@ -1858,6 +1873,7 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     if (const char* e = getenv("MLSGD_TY64")) c->tile_y = atoi(e);
     if (const char* e = getenv("MLSGD_XCHUNK")) c->xchunk = atoi(e);
     if (const char* e = getenv("MLSGD_PRE2R")) c->pre2r = atoi(e) != 0;
+    if (const char* e = getenv("MLSGD_PRE2R_HALF")) c->pre2r_half = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_POST2")) c->post2 = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_VSMALL")) c->vsmall = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_XDEFER")) c->xdefer = atoi(e) != 0;

@@ -4,6 +4,8 @@ boundary).  These tests take every path through such rows against the FP64
 oracle on identical draws:
 - each smoother, coefficient mode and precision on a 17^3..129^3 hierarchy;
 - tile heights and ragged x chunks on the 129^3 grid;
+- the residual restricted along x by the pre-smoothing pass against the full
+  residual and restriction;
 - independent solves of mixed sizes (129 padded, 65 and 33 dense) through the
   packed output of mlsgd_solve_sizes;
 - the unpacked state and adjoint outputs of mlsgd_solve_state_adjoint.
@@ -194,6 +196,54 @@ def test_fused_passes_equal_level_by_level_passes(mm, orc, monkeypatch, grid, M,
         pb = orc.make_problem(grid, rtol=1e-13, **KW)
         go, _ = orc.mlmc_gradient(pb, None, u, yd, M, first=[2] * len(M))
         assert _rel(out[1][0], go) <= (1e-9 if precision == "fp64" else 1e-8)
+
+
+@pytest.mark.parametrize("grid,M,precision,tuning", [
+    (GRID, M, "fp64", {}),
+    (GRID, M, "mixed", {"tile_y": 16, "xchunk": 40}),
+    ([17, 33, 65], [8, 4, 3], "bf16", {}),
+    (GRID, M, "fp64", {"xchunk": 9}),
+])
+def test_half_restriction_equals_full_restriction(mm, orc, monkeypatch, grid, M, precision,
+                                                  tuning):
+    """The fused pre-smoothing pass may write its residual already restricted
+    along x (every second plane), the restriction then finishing y and z.
+    Full weighting is a product of one-dimensional weights, so both orders
+    give the coarse right-hand side up to rounding: whole estimates agree to
+    rounding with identical iteration counts, and match the oracle.  Chunks
+    of odd length (9 planes: more than one chunk on every grid from 17^3 up)
+    cannot split the coarse planes between chunks, keep the full residual
+    and give identical bits."""
+    print("half restriction", grid, precision, tuning, flush=True)
+    nL = grid[-1]
+    yd = inputs.target_sin(nL)
+    u = inputs.control_xyz(nL) + 15.0 * yd
+    prec = {"fp64": mm.FP64, "mixed": mm.MIXED_FP32, "bf16": mm.MIXED_BF16}[precision]
+    out = []
+    for flag in ("0", "1"):
+        monkeypatch.setenv("MLSGD_PRE2R_HALF", flag)
+        ctx = mm.Context(mm.Problem(grid_n=grid, y_d=yd, rtol=1e-12, precision=prec, **KW),
+                         use_tuned=False)
+        if tuning:
+            ctx.set_tuning(**tuning)
+        g, st = ctx.mlmc_gradient(u, M, first=[1] * len(M))
+        ctx.close()
+        assert st["nonconverged"] == 0
+        out.append((g.cpu().numpy(), st))
+    d = _rel(out[1][0], out[0][0])
+    print("half vs full restriction: relative L2", d, "iterations", out[0][1]["iters_state"],
+          out[1][1]["iters_state"], out[0][1]["iters_adjoint"], out[1][1]["iters_adjoint"],
+          flush=True)
+    if tuning.get("xchunk", 0) % 2 == 1:
+        assert np.array_equal(out[0][0], out[1][0])
+    assert d <= 1e-13
+    assert out[0][1]["J"] == pytest.approx(out[1][1]["J"], rel=1e-14)
+    assert out[0][1]["iters_state"] == out[1][1]["iters_state"]
+    assert out[0][1]["iters_adjoint"] == out[1][1]["iters_adjoint"]
+    if grid != GRID:
+        pb = orc.make_problem(grid, rtol=1e-13, **KW)
+        go, _ = orc.mlmc_gradient(pb, None, u, yd, M, first=[1] * len(M))
+        assert _rel(out[1][0], go) <= 1e-8
 
 
 def test_largest_grids(mm, orc):
