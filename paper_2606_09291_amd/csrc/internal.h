@@ -162,7 +162,7 @@ void prolong_add_rows(int nc, int rows, int row0, const CgScal* scal, const T* c
 template <typename T>
 void prolong_rows(int nc, int rows, const T* coarse, T* fine, hipStream_t s);
 // dst rows (FP64, n^3 solver rows) = src rows for the problems row0.. that
-// are active; the rows of inactive problems are left as they are
+// are active, zero for the inactive ones
 template <typename TS>
 void copy_active_rows(int n, int rows, int row0, const CgScal* scal, const TS* src, double* dst,
                       hipStream_t s);

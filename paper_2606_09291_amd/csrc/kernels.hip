@@ -2092,8 +2092,8 @@ void prolong_rows(int nc, int rows, const T* coarse, T* fine, hipStream_t s) {
 template void prolong_rows<double>(int, int, const double*, double*, hipStream_t);
 template void prolong_rows<float>(int, int, const float*, float*, hipStream_t);
 
-// dst rows = src rows (widened to FP64) for the active problems; the rows of
-// inactive problems are left as they are
+// dst rows = src rows (widened to FP64) for the active problems, zero for the
+// inactive ones
 template <typename TS>
 __global__ void k_copy_active_rows(long long per, int rows, int row0, const CgScal* scal,
                                    const TS* __restrict__ src, double* __restrict__ dst) {
@@ -2101,7 +2101,7 @@ __global__ void k_copy_active_rows(long long per, int rows, int row0, const CgSc
   for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
        i += (long long)gridDim.x * blockDim.x) {
     const int row = (int)(i / per);
-    if (scal[row0 + row].active) dst[i] = (double)src[i];
+    dst[i] = scal[row0 + row].active ? (double)src[i] : 0.0;
   }
 }
 template <typename TS>
@@ -3250,19 +3250,62 @@ constexpr int SB = 32;  // samples per block of the level reductions
 int level_sample_blocks(int M) { return (M + SB - 1) / SB; }
 
 // dX_m(v) = w_f[m] p_f[m](v) - w_c[m] (P p_c[m])(v) at interior v = (ix, iy, iz)
-// of the fine grid; p_f and p_c are solver rows
-__device__ __forceinline__ double dx_at(int nf, int m, const double* __restrict__ pf,
-                                        const double* __restrict__ wf,
-                                        const double* __restrict__ pc,
-                                        const double* __restrict__ wc, int ix, int iy, int iz) {
-  const size_t sf = (size_t)lay_row(nf);
-  double d = wf[m] * pf[(size_t)m * sf + ((size_t)ix * nf + iy) * lay_pitch(nf) + iz + lay_off(nf)];
+// of the fine grid; p_f and p_c are solver rows.  The addressing of a vertex
+// is formed once (DxSite) and serves every sample: the fine element offset in
+// a row, the coarse corner (ix/2, iy/2, iz/2) and the steps to the corners
+// one further along each odd axis, with 0/1 masks, so that every sample adds
+// the same corners in prolong_at's order (a masked corner adds 0).
+struct DxSite {
+  uint32_t of, oc, dz, dy, dx;
+  double w, mz, my, mx;
+};
+__device__ __forceinline__ DxSite dx_site(int nf, int ix, int iy, int iz) {
+  DxSite t;
+  t.of = (uint32_t)(ix * nf + iy) * (uint32_t)lay_pitch(nf) + (uint32_t)(iz + lay_off(nf));
+  const int nc = (nf - 1) / 2 + 1, cp = lay_pitch(nc);
+  t.oc = (uint32_t)((ix >> 1) * nc + (iy >> 1)) * (uint32_t)cp + (uint32_t)((iz >> 1) + lay_off(nc));
+  t.dz = iz & 1;
+  t.dy = (iy & 1) ? (uint32_t)cp : 0u;
+  t.dx = (ix & 1) ? (uint32_t)nc * (uint32_t)cp : 0u;
+  t.mz = (iz & 1) ? 1.0 : 0.0;
+  t.my = (iy & 1) ? 1.0 : 0.0;
+  t.mx = (ix & 1) ? 1.0 : 0.0;
+  t.w = ((ix & 1) ? 0.5 : 1.0) * ((iy & 1) ? 0.5 : 1.0) * ((iz & 1) ? 0.5 : 1.0);
+  return t;
+}
+__device__ __forceinline__ double dx_eval(const DxSite& t, int m, size_t sf, size_t scs,
+                                          const double* __restrict__ pf,
+                                          const double* __restrict__ wf,
+                                          const double* __restrict__ pc,
+                                          const double* __restrict__ wc) {
+  double d = wf[m] * pf[(size_t)m * sf + t.of];
   if (pc) {
-    const int nc = (nf - 1) / 2 + 1;
-    const size_t scs = (size_t)lay_row(nc);
-    d -= wc[m] * prolong_at(nc, lay_pitch(nc), lay_off(nc), pc + (size_t)m * scs, ix, iy, iz);
+    const double* __restrict__ c = pc + (size_t)m * scs + t.oc;
+    const double c0 = c[0], c1 = c[t.dz], c2 = c[t.dy], c3 = c[t.dy + t.dz];
+    const double c4 = c[t.dx], c5 = c[t.dx + t.dz], c6 = c[t.dx + t.dy],
+                 c7 = c[t.dx + t.dy + t.dz];
+    const double myz = t.my * t.mz, mxz = t.mx * t.mz, mxy = t.mx * t.my;
+    double v = c0;
+    v += t.mz * c1;
+    v += t.my * c2;
+    v += myz * c3;
+    v += t.mx * c4;
+    v += mxz * c5;
+    v += mxy * c6;
+    v += mxy * t.mz * c7;
+    d -= wc[m] * (t.w * v);
   }
   return d;
+}
+
+// interior vertex v < nf^3 (dense index) as (ix, iy, iz); false off the interior
+__device__ __forceinline__ bool dx_vertex(int nf, uint32_t v, int& ix, int& iy, int& iz) {
+  const uint32_t n = (uint32_t)nf, nn = n * n;
+  ix = (int)(v / nn);
+  const uint32_t r = v - (uint32_t)ix * nn;
+  iy = (int)(r / n);
+  iz = (int)(r - (uint32_t)iy * n);
+  return interior(nf, ix, iy, iz);
 }
 
 __global__ void k_level_dx_partial(int nf, int M, const double* __restrict__ pf,
@@ -3272,11 +3315,13 @@ __global__ void k_level_dx_partial(int nf, int M, const double* __restrict__ pf,
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const int sb = blockIdx.y;
   if (v >= N) return;
-  const int ix = (int)(v / ((long long)nf * nf)), iy = (int)((v / nf) % nf), iz = (int)(v % nf);
+  int ix, iy, iz;
   double acc = 0.0;
-  if (interior(nf, ix, iy, iz)) {
+  if (dx_vertex(nf, (uint32_t)v, ix, iy, iz)) {
+    const DxSite t = dx_site(nf, ix, iy, iz);
+    const size_t sf = (size_t)lay_row(nf), scs = (size_t)lay_row((nf - 1) / 2 + 1);
     const int m1 = min(M, (sb + 1) * SB);
-    for (int m = sb * SB; m < m1; ++m) acc += dx_at(nf, m, pf, wf, pc, wc, ix, iy, iz);
+    for (int m = sb * SB; m < m1; ++m) acc += dx_eval(t, m, sf, scs, pf, wf, pc, wc);
   }
   part[(size_t)sb * N + v] = acc;
 }
@@ -3318,13 +3363,15 @@ __global__ void __launch_bounds__(256)
   const int chunk = blockIdx.x, sb = blockIdx.y;
   const long long lo = (long long)chunk * M2_CHUNK, hi = min(N, lo + M2_CHUNK);
   const int m1 = min(M, (sb + 1) * SB);
+  const size_t sf = (size_t)lay_row(nf), scs = (size_t)lay_row((nf - 1) / 2 + 1);
   double acc = 0.0;
   for (long long v = lo + threadIdx.x; v < hi; v += 256) {
-    const int ix = (int)(v / ((long long)nf * nf)), iy = (int)((v / nf) % nf), iz = (int)(v % nf);
-    if (!interior(nf, ix, iy, iz)) continue;
+    int ix, iy, iz;
+    if (!dx_vertex(nf, (uint32_t)v, ix, iy, iz)) continue;
+    const DxSite t = dx_site(nf, ix, iy, iz);
     const double mv = mean[v];
     for (int m = sb * SB; m < m1; ++m) {
-      const double d = dx_at(nf, m, pf, wf, pc, wc, ix, iy, iz) - mv;
+      const double d = dx_eval(t, m, sf, scs, pf, wf, pc, wc) - mv;
       acc += d * d;
     }
   }

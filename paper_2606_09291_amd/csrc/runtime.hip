@@ -1030,8 +1030,9 @@ int read_count(mlsgd_ctx* c) {
 // each larger grid the prolonged solution of the grid below improved by one
 // cycle from that grid, over the problems whose top grid is that size or
 // larger.  A problem's result on its top grid becomes its starting iterate x0
-// (active problems only; the others keep x = 0) and the B rows of the top
-// grids receive r0 = b - A x0.  bb must already hold |b|^2.
+// (active problems; the others get x = 0, so x need not be cleared before)
+// and the B rows of the top grids receive r0 = b - A x0.  bb must already
+// hold |b|^2.
 bool fmg_applies(mlsgd_ctx* c, Plan* P) {
   return c->fmg && c->pb.solver == MLSGD_SOLVER_MGPCG && c->smoother == 2 && !P->ainv &&
          P->sizes.size() >= 2 && P->sizes.back().n == 3;
@@ -1305,11 +1306,13 @@ void level_rhs(mlsgd_ctx* c, const double* u) {
 void state_phase(mlsgd_ctx* c, Plan* P, int* it, int* nc, double* rr, double* y_out,
                  int fixed = 0) {
   hipStream_t s = c->stream;
+  // x starts at 0 (the full-multigrid start writes every x row itself)
+  const bool clear = !fmg_applies(c, P);
   for (auto& gr : P->groups) {
     double* b = rows_of(P->sizes[gr.sl].B, gr);
     rows_broadcast(gr.n, gr.count, c->rhs_lvl[gr.n], b, s);
     rows_broadcast(gr.n, gr.count, c->rhs_lvl[gr.n], gr.b0, s);
-    rows_zero((long long)gr.count * srow(gr.n), gr.x, s);
+    if (clear) rows_zero((long long)gr.count * srow(gr.n), gr.x, s);
   }
   HIPCHK(hipGetLastError());
   if (fixed > 0)
