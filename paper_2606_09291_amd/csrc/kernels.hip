@@ -51,6 +51,22 @@ __device__ __forceinline__ T face(T bv, T bw) {
   return T(2) * drcp(bv + bw);
 }
 
+// Reciprocal and face of the fused smoothing passes: in FP64 one Newton step
+// from the hardware estimate instead of two (within a few ulp of drcp).  The
+// pre- and post-smoothing passes of a grid both use them, so the cycle stays
+// symmetric: multigrid for the operator with these faces, a fixed SPD
+// operator within a few ulp of A, while the Krylov matvec applies A itself.
+__device__ __forceinline__ double srcp(double d) {
+  const double r = __builtin_amdgcn_rcp(d);
+  const double e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float srcp(float d) { return __builtin_amdgcn_rcpf(d); }
+template <typename T>
+__device__ __forceinline__ T sface(T bv, T bw) {
+  return T(2) * srcp(bv + bw);
+}
+
 // Workgroups are dealt round-robin to the 8 XCDs; renumber them so that each
 // XCD (own L2) receives a contiguous range of logical tiles, which then share
 // halo rows in that L2.
@@ -683,8 +699,9 @@ template void march_jac2z<float>(const GridArgs&, const float*, const float*, fl
 //   x2 = x1 + omega2 D^-1 (b - A x1)
 //   r  = b - A x2
 // x2 and r are written; b, 1/D and 1/a are read once: 40 B per point instead
-// of 32 + 32 for the two-step pass and a residual pass.  Both outputs equal
-// those two passes' bitwise (same faces, neighbours and summation order).
+// of 32 + 32 for the two-step pass and a residual pass.  Neighbours and
+// summation order are those two passes'; faces and 1/D of the steps come
+// from the one-step reciprocal srcp (within a few ulp of theirs in FP64).
 //
 // The march lags the residual one plane behind the second step.  At plane q
 // the workgroup puts x1 and 1/a of its patch and a two-point ring in LDS,
@@ -865,29 +882,29 @@ __global__ void __launch_bounds__(TY* TZ)
     T x2c = T(0);
     T fxm = T(0), fxp = T(0), fym = T(0), fyp = T(0), fzm = T(0), fzp = T(0), diag = T(1);
     if (qin && o_int) {
-      fxm = face(obc, obm);
-      fxp = face(obc, obp);
-      fym = face(obc, b3[oidx - PZ]);
-      fyp = face(obc, b3[oidx + PZ]);
-      fzm = face(obc, b3[oidx - 1]);
-      fzp = face(obc, b3[oidx + 1]);
+      fxm = sface(obc, obm);
+      fxp = sface(obc, obp);
+      fym = sface(obc, b3[oidx - PZ]);
+      fyp = sface(obc, b3[oidx + PZ]);
+      fzm = sface(obc, b3[oidx - 1]);
+      fzp = sface(obc, b3[oidx + 1]);
       diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
       const T off = ((fxm * oxm + fxp * oxp) + (fym * s1[oidx - PZ] + fyp * s1[oidx + PZ])) +
                     (fzm * s1[oidx - 1] + fzp * s1[oidx + 1]);
-      x2c = oxc + omega2 * (orc - ih2 * (diag * oxc - off)) * drcp(ih2 * diag);
+      x2c = oxc + omega2 * (orc - ih2 * (diag * oxc - off)) * srcp(ih2 * diag);
     }
     T* __restrict__ x2s = s2[q & 1];
     x2s[oidx] = x2c;
     if (ring1) {
       T v = T(0);
       if (qin && s_int) {
-        const T hxm = face(sbc, sbm), hxp = face(sbc, sbp);
-        const T hym = face(sbc, b3[sidx - PZ]), hyp = face(sbc, b3[sidx + PZ]);
-        const T hzm = face(sbc, b3[sidx - 1]), hzp = face(sbc, b3[sidx + 1]);
+        const T hxm = sface(sbc, sbm), hxp = sface(sbc, sbp);
+        const T hym = sface(sbc, b3[sidx - PZ]), hyp = sface(sbc, b3[sidx + PZ]);
+        const T hzm = sface(sbc, b3[sidx - 1]), hzp = sface(sbc, b3[sidx + 1]);
         const T hd = ((hxm + hxp) + (hym + hyp)) + (hzm + hzp);
         const T hoff = ((hxm * sxm + hxp * sxp) + (hym * s1[sidx - PZ] + hyp * s1[sidx + PZ])) +
                        (hzm * s1[sidx - 1] + hzp * s1[sidx + 1]);
-        v = sxc + omega2 * (src - ih2 * (hd * sxc - hoff)) * drcp(ih2 * hd);
+        v = sxc + omega2 * (src - ih2 * (hd * sxc - hoff)) * srcp(ih2 * hd);
       }
       x2s[sidx] = v;
     }
@@ -981,7 +998,8 @@ template bool march_pre2r<float>(const GridArgs&, const float*, const float*, fl
 // with the partial sums of <b, x4> for the problems whose top grid this is.
 // x, e / 8, b and 1/a are read and x4 written once: 33 B per point instead of
 // 33 + 32 for the step with the folded correction and a plain step.  Both
-// steps use k_march's faces, neighbours and summation order.
+// steps use k_march's neighbours and summation order, with faces and 1/D from
+// srcp as in k_pre2r.
 //
 // The plane pipeline is that of k_pre2r (y in place of x1): y and 1/a of the
 // patch and a two-point ring on plane q in LDS, x3 on the patch and its
@@ -1014,7 +1032,7 @@ __global__ void __launch_bounds__(TY* TZ)
   constexpr int CSLAB = CYN * CZN;
   static_assert(CSLAB <= NT, "coarse slab larger than the workgroup");
   using CR = typename std::conditional<CK == 2, uint16_t, T>::type;
-  // FP64 shares faces through LDS (its reciprocal costs five operations);
+  // FP64 shares faces through LDS (its reciprocal costs three operations);
   // FP32 forms every face from 1/a (one reciprocal instruction)
   constexpr bool SHARE = sizeof(T) == 8;
   constexpr int NF = SHARE ? 3 : 1, NB = SHARE ? 1 : 3;
@@ -1160,8 +1178,8 @@ __global__ void __launch_bounds__(TY* TZ)
   auto faces_yz = [&](int p, int idx) {
     if constexpr (SHARE) {
       const int r = idx / PZ, cc = idx - (idx / PZ) * PZ;
-      if (r < TY + 3) fy[p % 3][idx] = face(sa[idx], sa[idx + PZ]);
-      if (cc < TZ + 3) fz[p % 3][idx] = face(sa[idx], sa[idx + 1]);
+      if (r < TY + 3) fy[p % 3][idx] = sface(sa[idx], sa[idx + PZ]);
+      if (cc < TZ + 3) fz[p % 3][idx] = sface(sa[idx], sa[idx + 1]);
     }
   };
 
@@ -1178,7 +1196,7 @@ __global__ void __launch_bounds__(TY* TZ)
     oyc = c.x + corr(pco, ixs + 1);
     oyp = p.x + corr(pco, ixs + 2);
     obm = cvt(m.a); obc = cvt(c.a); obp = cvt(p.a);
-    ofb = face(obm, obc);
+    ofb = sface(obm, obc);
     orc = c.b; orp = p.b;
     if (SHARE) sa[oidx] = obc;
     if (s_on) {
@@ -1188,7 +1206,7 @@ __global__ void __launch_bounds__(TY* TZ)
       syc = sc.x + corr(pcs, ixs + 1);
       syp = sp.x + corr(pcs, ixs + 2);
       sbm = cvt(sm.a); sbc = cvt(sc.a); sbp = cvt(sp.a);
-      sfb = face(sbm, sbc);
+      sfb = sface(sbm, sbc);
       src = sc.b; srp = sp.b;
       if (SHARE) sa[sidx] = sbc;
     }
@@ -1238,11 +1256,11 @@ __global__ void __launch_bounds__(TY* TZ)
       if constexpr (SHARE) {
         fym = fyq[idx - PZ]; fyp = fyq[idx]; fzm = fzq[idx - 1]; fzp = fzq[idx];
       } else {
-        fym = face(bv, b3[idx - PZ]); fyp = face(bv, b3[idx + PZ]);
-        fzm = face(bv, b3[idx - 1]); fzp = face(bv, b3[idx + 1]);
+        fym = sface(bv, b3[idx - PZ]); fyp = sface(bv, b3[idx + PZ]);
+        fzm = sface(bv, b3[idx - 1]); fzp = sface(bv, b3[idx + 1]);
       }
     };
-    const T ofc = face(obc, obp);
+    const T ofc = sface(obc, obp);
     T x3c = T(0), odc = T(0);
     if (qin && o_int) {
       const T fxm = ofb, fxp = ofc;
@@ -1251,12 +1269,12 @@ __global__ void __launch_bounds__(TY* TZ)
       const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
       const T off = ((fxm * oym + fxp * oyp) + (fym * s1[oidx - PZ] + fyp * s1[oidx + PZ])) +
                     (fzm * s1[oidx - 1] + fzp * s1[oidx + 1]);
-      odc = drcp(ih2 * diag);
+      odc = srcp(ih2 * diag);
       x3c = oyc + omega_a * (orc - ih2 * (diag * oyc - off)) * odc;
     }
     T* __restrict__ x3s = s3[q & 1];
     x3s[oidx] = x3c;
-    const T sfc = face(sbc, sbp);
+    const T sfc = sface(sbc, sbp);
     if (ring1) {
       T v = T(0);
       if (qin && s_int) {
@@ -1266,7 +1284,7 @@ __global__ void __launch_bounds__(TY* TZ)
         const T hd = ((hxm + hxp) + (hym + hyp)) + (hzm + hzp);
         const T hoff = ((hxm * sym + hxp * syp) + (hym * s1[sidx - PZ] + hyp * s1[sidx + PZ])) +
                        (hzm * s1[sidx - 1] + hzp * s1[sidx + 1]);
-        v = syc + omega_a * (src - ih2 * (hd * syc - hoff)) * drcp(ih2 * hd);
+        v = syc + omega_a * (src - ih2 * (hd * syc - hoff)) * srcp(ih2 * hd);
       }
       x3s[sidx] = v;
     }
@@ -1285,16 +1303,16 @@ __global__ void __launch_bounds__(TY* TZ)
         fym = fyr[oidx - PZ]; fyp = fyr[oidx]; fzm = fzr[oidx - 1]; fzp = fzr[oidx];
       } else {
         const T* __restrict__ bq = sb[qr % 3];
-        fym = face(obm, bq[oidx - PZ]); fyp = face(obm, bq[oidx + PZ]);
-        fzm = face(obm, bq[oidx - 1]); fzp = face(obm, bq[oidx + 1]);
+        fym = sface(obm, bq[oidx - PZ]); fyp = sface(obm, bq[oidx + PZ]);
+        fzm = sface(obm, bq[oidx - 1]); fzp = sface(obm, bq[oidx + 1]);
       }
       const T diag = ((fxm + fxp) + (fym + fyp)) + (fzm + fzp);
       const T off = ((fxm * x3a + fxp * x3c) + (fym * x3p[oidx - PZ] + fyp * x3p[oidx + PZ])) +
                     (fzm * x3p[oidx - 1] + fzp * x3p[oidx + 1]);
-      // FP64: odb is drcp(ih2 * diag) of this column and plane as the x3
-      // step formed it (a five-operation reciprocal); FP32 forms it again
+      // FP64: odb is srcp(ih2 * diag) of this column and plane as the x3
+      // step formed it (a three-operation reciprocal); FP32 forms it again
       // (one instruction, and the kept value would cost occupancy)
-      const T dinv = sizeof(T) == 8 ? odb : drcp(ih2 * diag);
+      const T dinv = sizeof(T) == 8 ? odb : srcp(ih2 * diag);
       const T val = x3b + omega_b * (rm_ - ih2 * (diag * x3b - off)) * dinv;
       const size_t e = base + ((size_t)qr * n + oy) * LP + oz + LO;
       __builtin_nontemporal_store(val, &xout[e]);
