@@ -50,6 +50,7 @@ struct CgScal {
   int iters;
   int pending;    // x += alpha p of the last step not yet applied
   int pbuf;       // which of the two direction buffers holds that p
+  int restart;    // the last true-residual check found rr above rtol
 };
 
 // Arguments common to every launch over one grid size.
@@ -196,6 +197,9 @@ void cos_table(int n, int K, double* out, hipStream_t s);
 void rows_broadcast(int n, int rows, const double* src, double* dst, hipStream_t s);
 // solver rows copied (copy_rows) or converted to dense rows (unpack_rows)
 void copy_rows(int n, int rows, const double* src, double* dst, hipStream_t s);
+// the same for the rows of active problems only (problems row0 .. row0 + rows - 1)
+void copy_rows_active(int n, int rows, int row0, const CgScal* scal, const double* src,
+                      double* dst, hipStream_t s);
 void unpack_rows(int n, int rows, const double* src, double* dst, hipStream_t s);
 void rows_zero(long long count, double* x, hipStream_t s);
 void to_f32(long long count, const double* x, float* y, hipStream_t s);
@@ -224,7 +228,8 @@ enum ScalPhase {
   PH_RR = 4,         // rr = sum; ++iters; converged or out of iterations -> inactive
   PH_RZ = 5,         // rz_new = sum; beta = rz_new / rz; rz = rz_new
   PH_RZ_RR = 6,      // unpreconditioned: rz_new = rr
-  PH_TRUE = 7,       // rr = sum (true residual); active = rr > rtol^2 bb; nothing pending
+  PH_TRUE = 7,       // rr = sum (true residual); active = restart = rr > rtol^2 bb; nothing pending
+  PH_RECHECK = 8,    // active = restart: the problems the last check restarted (no sum)
 };
 void cg_scalar(int phase, CgScal* scal, int nprob, const int* poff, const int* pcnt,
                const double* partial, double rtol, int max_iters, int* active_count,

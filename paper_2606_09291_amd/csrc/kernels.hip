@@ -2905,6 +2905,7 @@ __global__ void __launch_bounds__(256)
         sc.pq = 0.0;
         sc.pending = 0;
         sc.pbuf = 0;
+        sc.restart = 0;
         break;
       case PH_RZ0:
         if (sc.active) {
@@ -2959,9 +2960,13 @@ __global__ void __launch_bounds__(256)
       case PH_TRUE:
         sc.rr = sum;
         sc.active = (sc.bb > 0.0) && (sum > rt2 * sc.bb) && (sc.iters < max_iters);
+        sc.restart = sc.active;
         sc.alpha = 0.0;
         sc.beta = 0.0;
         sc.pending = 0;
+        break;
+      case PH_RECHECK:
+        sc.active = sc.restart;
         break;
     }
     scal[p] = sc;
@@ -3237,6 +3242,21 @@ void copy_elems(long long count, const double* src, double* dst, hipStream_t s) 
 }
 void copy_rows(int n, int rows, const double* src, double* dst, hipStream_t s) {
   copy_elems(lay_row(n) * rows, src, dst, s);
+}
+__global__ void k_copy_rows_active(long long per, int rows, int row0, const CgScal* scal,
+                                   const double* __restrict__ src, double* __restrict__ dst) {
+  const long long total = per * rows;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    if (scal[row0 + (int)(i / per)].active) dst[i] = src[i];
+  }
+}
+void copy_rows_active(int n, int rows, int row0, const CgScal* scal, const double* src,
+                      double* dst, hipStream_t s) {
+  if (rows <= 0) return;
+  const long long per = lay_row(n);
+  hipLaunchKernelGGL(k_copy_rows_active, dim3(grid_for(per * rows, 256)), dim3(256), 0, s, per,
+                     rows, row0, scal, src, dst);
 }
 
 // ---------------------------------------------------------------------------

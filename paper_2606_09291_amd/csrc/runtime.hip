@@ -1191,10 +1191,16 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
                   c->d_count, s);
       }
     }
-    // true residual b0 - A x into q, its norm; restart the problems that drifted
+    // true residual b0 - A x into q, its norm; restart the problems that
+    // drifted.  After a restart only the restarted problems are checked again:
+    // the others were not touched, and their partial slots still hold the last
+    // check's sums
     flush_steps(c, P);
+    if (restart > 0)
+      cg_scalar(PH_RECHECK, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, nullptr, rtol, maxit,
+                nullptr, s);
     for (auto& gr : P->groups) {
-      GridArgs g = args_group(c, P, gr, false);
+      GridArgs g = args_group(c, P, gr, restart > 0);
       march_resid<double>(g, gr.x, gr.b0, gr.q, s);
       group_dot(g, gr.q, gr.q, P->d_poff, P->d_partial, s);
     }
@@ -1203,7 +1209,8 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
     HIPCHK(hipGetLastError());
     if (read_count(c) == 0) break;
     for (auto& gr : P->groups)
-      copy_rows(gr.n, gr.count, gr.q, rows_of(P->sizes[gr.sl].B, gr), s);
+      copy_rows_active(gr.n, gr.count, gr.p0, P->d_scal, gr.q, rows_of(P->sizes[gr.sl].B, gr),
+                       s);
   }
   scal_to_stats(P->d_scal, P->nprob, rtol, &c->d_stat->iters, &c->d_stat->nonconv,
                 &c->d_stat->relres, s);
@@ -1260,10 +1267,14 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
       }
     }
   };
-  auto true_residual = [&]() {
+  // the true residual of every problem, or (recheck) of the problems the last
+  // check restarted: the others were not touched since, and their partial
+  // slots still hold that check's sums, so PH_TRUE keeps their verdict
+  auto true_residual = [&](bool recheck) {
     flush_steps(c, P);
+    if (recheck) cg(PH_RECHECK, nullptr);
     for (auto& gr : P->groups) {
-      GridArgs g = args_group(c, P, gr, false);
+      GridArgs g = args_group(c, P, gr, recheck);
       march_resid<double>(g, gr.x, gr.b0, gr.q, s);
       group_dot(g, gr.q, gr.q, P->d_poff, P->d_partial, s);
     }
@@ -1278,12 +1289,13 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
   fmg(c, P);
   start();
   iterate(iters);
-  true_residual();
+  true_residual(false);
+  // restart block: the problems that missed rtol start again from b - A x
   for (auto& gr : P->groups)
-    copy_rows(gr.n, gr.count, gr.q, rows_of(P->sizes[gr.sl].B, gr), s);
+    copy_rows_active(gr.n, gr.count, gr.p0, P->d_scal, gr.q, rows_of(P->sizes[gr.sl].B, gr), s);
   start();
   iterate(kRestartIters);
-  true_residual();
+  true_residual(true);
   scal_to_stats(P->d_scal, P->nprob, rtol, &c->d_stat[slot].iters, &c->d_stat[slot].nonconv,
                 &c->d_stat[slot].relres, s);
   HIPCHK(hipGetLastError());
