@@ -201,6 +201,9 @@ struct mlsgd_ctx {
   bool xdefer = true;       // x's Krylov step applied by the next matvec
   bool fmg = true;          // full-multigrid start of the Krylov solves
   double fmg_margin = 0.7;  // recursive-residual target as a fraction of rtol after that start
+  // Krylov iterations whose active count the host does not read (no solve
+  // of the previous call finished before them); results do not depend on it
+  int kry_quiet = 0;
   // event timing of the smoothing passes on one grid size (roofline figures)
   struct Timing {
     bool on = false;
@@ -1176,12 +1179,16 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
       cg_scalar(PH_RZ0_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, nullptr, rtol, maxit,
                 c->d_count, s);
     }
+    // the first quiet iterations run without a host read of the active
+    // count: a problem that converged there is inactive and skipped, so at
+    // worst a few launches run empty
+    const int quiet = restart == 0 ? c->kry_quiet : 0;
     for (int it = 0; it < maxit; ++it) {
       krylov_step(c, P, mg, it);
       cg_scalar(PH_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol_rr, maxit,
                 c->d_count, s);
       HIPCHK(hipGetLastError());
-      if (read_count(c) == 0) break;
+      if (it + 1 > quiet && read_count(c) == 0) break;
       if (mg) {
         precondition(c, P);
         cg_scalar(PH_RZ, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
@@ -1220,6 +1227,7 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
   *iters_out = c->h_stat->iters;
   *nonconv_out = c->h_stat->nonconv;
   *relres_out = c->h_stat->relres;
+  c->kry_quiet = std::max(0, std::min(*iters_out, maxit) - 2);
 }
 
 // The same batched PCG with a fixed iteration count and no host reads, so it
