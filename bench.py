@@ -35,9 +35,15 @@ TRAFFIC_FILES = {  # committed counter summaries of the timed kernel, by timing 
 #   kind 2, fused post-smoothing pass: x and b read, x'' written, coarse
 #     correction read once (1/8 point);
 #   kind 1, plain smoothing step: x and b read, x' written.
-ALG_BYTES_PER_POINT = {2: lambda e: 3.0 * e + e / 8.0, 1: lambda e: 3.0 * e}
+#   kind 3, fused pre-smoothing pass: b read, x2 written, the x-restricted
+#     residual written on every second plane;
+#   kind 4, Krylov matvec: z read, p_old read, p_new and q written, x read
+#     and written by the deferred step (z in FP32 under FP32 V-cycles).
+ALG_BYTES_PER_POINT = {2: lambda e: 3.0 * e + e / 8.0, 1: lambda e: 3.0 * e,
+                       3: lambda e: 2.5 * e}
 # (kind 1 also has launches from a zero start, 2e, and with a folded
-# correction, 3e + e/8; the library reports each launch's own bytes)
+# correction, 3e + e/8; kind 4's first iteration of a solve applies no x
+# step, 32 instead of 48 B; the library reports each launch's own bytes)
 CACHE_BYTES_PER_POINT = {"fp64": 8.0, "mixed": 4.0, "mixed_bf16": 2.0}
 ELEM_BYTES = {"fp64": 8.0, "mixed": 4.0, "mixed_bf16": 4.0}
 
@@ -103,7 +109,8 @@ def run(args, m, w, dev, steps, warmup, timing_n=None, graph=False, timing_kind=
     the first warm-up call captures the batch shape as a HIP graph and every
     later call replays it (no event timing then).  timing_kind selects the
     kernel timed on grid timing_n: 2 the fused post-smoothing pass, 1 the
-    plain smoothing step."""
+    plain smoothing step, 3 the fused pre-smoothing pass, 4 the Krylov
+    matvec."""
     import torch
     ctx = make_ctx(m, w, dev)
     if graph:
@@ -138,7 +145,24 @@ KERNEL_NAMES = {
     2: ("fused post-smoothing pass (k_post2: coarse-grid correction folded in, two Chebyshev "
         "steps, cached 1/a) on the {n}^3 rows"),
     1: "Chebyshev smoothing step (k_march OP_JAC, damped Jacobi, cached 1/a) on the {n}^3 rows",
+    3: ("fused pre-smoothing pass (k_pre2r: two Chebyshev steps from zero, residual restricted "
+        "along x, cached 1/a and 1/D) on the {n}^3 rows"),
+    4: ("Krylov matvec (k_march OP_MATVEC: p = z + beta p, q = A p, deferred x step, cached 1/a) "
+        "on the {n}^3 rows"),
 }
+
+
+def other_kernel_rooflines(args, m, w, dev, nfin):
+    """Live roofline records of the fused pre-smoothing pass and the Krylov
+    matvec on the finest grid, each from its own short host-driven run of the
+    same workload after the timed region (one kernel is timed per run)."""
+    recs = []
+    for kind in (3, 4):
+        tm = run(args, m, w, dev, 2, 1, timing_n=nfin, timing_kind=kind)["timing"]
+        rec = roofline(tm, kind, nfin, w.precision)
+        rec.pop("traffic", None)
+        recs.append(rec)
+    return recs
 
 
 def dominant_timing(args, m, w, dev, tm, nfin):
@@ -459,9 +483,9 @@ def roofline(tm, kind, n, precision):
     alg = tm["bytes"] / launches
     e = ELEM_BYTES[precision]
     achieved = alg / (avg_ms * 1e-3) / 1e9
-    # kind 2 launches all move the same bytes per point; kind 1 mixes starts
-    # from zero and folded corrections, so its point count is not derived
-    points = alg / ALG_BYTES_PER_POINT[kind](e) if kind == 2 else None
+    # kind 2 and 3 launches all move the same bytes per point; kinds 1 and 4
+    # mix launches of different bytes, so their point count is not derived
+    points = alg / ALG_BYTES_PER_POINT[kind](e) if kind in (2, 3) else None
     cache = points * CACHE_BYTES_PER_POINT[precision] if points else None
     return {
         "kernel": KERNEL_NAMES[kind].format(n=n),
@@ -474,7 +498,8 @@ def roofline(tm, kind, n, precision):
         "avg_launch_ms": avg_ms,
         "launches": launches,
         "algorithmic_bytes_per_launch": alg,
-        "algorithmic_bytes_per_point": ALG_BYTES_PER_POINT[kind](e),
+        "algorithmic_bytes_per_point": (ALG_BYTES_PER_POINT[kind](e) if kind in ALG_BYTES_PER_POINT
+                                        else None),
         "interior_points_per_launch": points,
         "coefficient_cache_bytes_per_launch": cache,
         "frac_with_cache_bytes": ((alg + cache) / (avg_ms * 1e-3) / 1e9 / HBM_PEAK_GBS
@@ -577,6 +602,7 @@ def main():
         "roofline": roofline(tm, kind, nfin, w.precision),
     }
     out["rates"] = level_rates(w, stats)
+    out["other_kernels"] = other_kernel_rooflines(args, m, w, dev, nfin)
     if not args.no_mixed:
         wm = inputs.WORKLOADS[args.mixed_workload]
         log(args, f"mixed workload {args.mixed_workload} ({wm.precision})")

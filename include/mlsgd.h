@@ -315,20 +315,21 @@ int mlsgd_set_tuning(mlsgd_ctx* ctx, const mlsgd_tuning* tuning);
  * is on.  Errors: MLSGD_EINVAL for enable outside {0, 1}. */
 int mlsgd_set_graph(mlsgd_ctx* ctx, int enable);
 
-/* Event timing of a smoothing kernel on grid size n (the dominant kernels
- * of the solves), for roofline figures.  Each launch of the selected kernel
- * on that grid is bracketed by HIP events on the context's stream: the plain
+/* Event timing of a kernel of the solves on grid size n (their dominant
+ * kernels), for roofline figures.  Each launch of the selected kernel on that
+ * grid is bracketed by HIP events on the context's stream: the plain
  * smoothing step (enable = 1), the fused two-step post-smoothing pass
- * (enable = 2) or the fused pre-smoothing pass with its residual (enable =
- * 3); the fused passes run on grids with 64-wide tiles of height 8 or 16 and
- * a cached coefficient.  The call first returns the totals accumulated so
- * far (host outputs, nullable: summed milliseconds, launch count,
- * algorithmic bytes = interior points x bytes the pass must move, the
- * coefficient counted at 0 bytes since the method regenerates it from the
- * draws; a kernel that reads a per-call coefficient cache moves that cache
- * on top), then, if enable >= 0, resets them and switches timing on
- * (enable = 1, 2 or 3, for grid n) or off (enable = 0); enable < 0 only
- * reads.  Errors: MLSGD_EINVAL for enable > 3. */
+ * (enable = 2), the fused pre-smoothing pass with its residual (enable = 3)
+ * or the Krylov matvec (enable = 4); the fused passes run on grids with
+ * 64-wide tiles of height 8 or 16 and a cached coefficient.  The call
+ * first returns the totals accumulated so far (host outputs, nullable:
+ * summed milliseconds, launch count, algorithmic bytes = interior points x
+ * bytes the kernel must move, the coefficient counted at 0 bytes since the
+ * method regenerates it from the draws; a kernel that reads a per-call
+ * coefficient cache moves that cache on top), then, if enable >= 0, resets
+ * them and switches timing on
+ * (enable = 1, 2, 3 or 4, for grid n) or off (enable = 0); enable < 0
+ * only reads.  Errors: MLSGD_EINVAL for enable > 4. */
 int mlsgd_kernel_timing(mlsgd_ctx* ctx, int enable, int n, double* ms_total,
                         int64_t* launches, double* bytes);
 

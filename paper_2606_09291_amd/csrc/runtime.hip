@@ -696,6 +696,14 @@ double pre2r_bytes(int n, int rows, bool half) {
   return N * (half ? 2.5 : 3.0) * (double)sizeof(T);
 }
 
+// Algorithmic bytes of the Krylov matvec: z read (z_bytes per point), p_old
+// read, p_new and q written, and x read and written when it applies the
+// previous step of x (coefficient: 0 bytes).
+double matvec_bytes(int n, int rows, double z_bytes, bool defer) {
+  const double N = (double)rows * (double)(n - 2) * (double)(n - 2) * (double)(n - 2);
+  return N * (z_bytes + 24.0 + (defer ? 16.0 : 0.0));
+}
+
 // Algorithmic bytes of the fused post-smoothing pass: x and b read, x''
 // written, coarse rows read once (coefficient: 0 bytes, as above).
 template <typename T>
@@ -1108,14 +1116,17 @@ void krylov_step(mlsgd_ctx* c, Plan* P, bool mg, int it) {
     GridArgs g = args_group(c, P, gr, true);
     SizeLvl& L = P->sizes[gr.sl];
     double* xd = (defer && it > 0) ? gr.x : nullptr;
-    if (mg && c->mixed) {
-      march_matvec<double, float>(g, z32(c, P, gr), gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q,
-                                  P->d_poff, P->d_partial, s, xd);
-    } else {
-      const double* z = mg ? z64(c, P, gr) : rows_of(L.B, gr);
-      march_matvec<double, double>(g, z, gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q, P->d_poff,
-                                   P->d_partial, s, xd);
-    }
+    const bool z32b = mg && c->mixed;
+    timed_launch(c, g, matvec_bytes(gr.n, gr.count, z32b ? 4.0 : 8.0, xd != nullptr), [&] {
+      if (z32b) {
+        march_matvec<double, float>(g, z32(c, P, gr), gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q,
+                                    P->d_poff, P->d_partial, s, xd);
+      } else {
+        const double* z = mg ? z64(c, P, gr) : rows_of(L.B, gr);
+        march_matvec<double, double>(g, z, gr.p[gr.pcur], gr.p[gr.pcur ^ 1], gr.q, P->d_poff,
+                                     P->d_partial, s, xd);
+      }
+    }, 4);
     pslot = gr.pcur ^ 1;
   }
   cg_scalar(PH_ALPHA, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
@@ -1968,7 +1979,7 @@ int mlsgd_kernel_timing(mlsgd_ctx* c, int enable, int n, double* ms_total, int64
     if (launches) *launches = c->tm.launches;
     if (bytes) *bytes = c->tm.total_bytes;
     if (enable >= 0) {
-      require(enable <= 3, "enable must be -1, 0, 1, 2 or 3");
+      require(enable <= 4, "enable must be -1, 0, 1, 2, 3 or 4");
       c->tm.on = enable != 0;
       c->tm.kind = enable != 0 ? enable : 1;
       c->tm.n = n;
