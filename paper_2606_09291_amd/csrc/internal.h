@@ -73,6 +73,10 @@ struct GridArgs {
 // ---- stencil kernels (marching LDS tiles, coefficient regenerated) ----
 template <typename T>
 void march_resid(const GridArgs& g, const T* x, const T* b, T* r, hipStream_t s);
+// partials of |b - A x|^2 (interior points, one slot per problem and tile, as
+// group_dot's), without storing the residual
+void march_resid_norm(const GridArgs& g, const double* x, const double* b, const int* poff,
+                      double* partial, hipStream_t s);
 // p_new = z + beta p_old, q = A p_new, <p_new, q>; with x non-null also the
 // step of the previous iteration, x += alpha p_old (alpha still in the
 // problem's scalars), which the update then leaves out
@@ -197,9 +201,6 @@ void cos_table(int n, int K, double* out, hipStream_t s);
 void rows_broadcast(int n, int rows, const double* src, double* dst, hipStream_t s);
 // solver rows copied (copy_rows) or converted to dense rows (unpack_rows)
 void copy_rows(int n, int rows, const double* src, double* dst, hipStream_t s);
-// the same for the rows of active problems only (problems row0 .. row0 + rows - 1)
-void copy_rows_active(int n, int rows, int row0, const CgScal* scal, const double* src,
-                      double* dst, hipStream_t s);
 void unpack_rows(int n, int rows, const double* src, double* dst, hipStream_t s);
 void rows_zero(long long count, double* x, hipStream_t s);
 void to_f32(long long count, const double* x, float* y, hipStream_t s);

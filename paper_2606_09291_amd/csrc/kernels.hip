@@ -537,7 +537,8 @@ __global__ void __launch_bounds__(TY* TZ)
       // stores a zero in the same vector store as its line's vertices
       if (OP == OP_RESID) {
         const T r = bv - ih2 * (diag * xcur - off);
-        __builtin_nontemporal_store(own ? r : T(0), &out[idx]);
+        if (out) __builtin_nontemporal_store(own ? r : T(0), &out[idx]);
+        if (partial && own) dot += (double)r * (double)r;
       } else if (OP == OP_MATVEC) {
         const T q = own ? ih2 * (diag * xcur - off) : T(0);
         __builtin_nontemporal_store(q, &out[idx]);
@@ -583,7 +584,7 @@ __global__ void __launch_bounds__(TY* TZ)
     hbn = hbnn;
     bv = bvn;
   }
-  const bool want = (OP == OP_MATVEC) ||
+  const bool want = (OP == OP_MATVEC) || (OP == OP_RESID && partial != nullptr) ||
                     ((OP == OP_GS || OP == OP_JAC || OP == OP_JACP) && partial != nullptr &&
                      prob >= top_begin);
   if (want) {
@@ -636,6 +637,11 @@ static void launch_march(const GridArgs& g, const TI* in, const T* in2, const T*
 template <typename T>
 void march_resid(const GridArgs& g, const T* x, const T* b, T* r, hipStream_t s) {
   launch_march<T, T, OP_RESID>(g, x, nullptr, b, r, nullptr, nullptr, nullptr, 0, 0, 0, T(1), s);
+}
+void march_resid_norm(const GridArgs& g, const double* x, const double* b, const int* poff,
+                      double* partial, hipStream_t s) {
+  launch_march<double, double, OP_RESID>(g, x, nullptr, b, nullptr, nullptr, poff, partial, 0, 0,
+                                         0, 1.0, s);
 }
 template <typename T, typename TZ>
 void march_matvec(const GridArgs& g, const TZ* z, const T* p_old, T* p_new, T* q,
@@ -3242,21 +3248,6 @@ void copy_elems(long long count, const double* src, double* dst, hipStream_t s) 
 }
 void copy_rows(int n, int rows, const double* src, double* dst, hipStream_t s) {
   copy_elems(lay_row(n) * rows, src, dst, s);
-}
-__global__ void k_copy_rows_active(long long per, int rows, int row0, const CgScal* scal,
-                                   const double* __restrict__ src, double* __restrict__ dst) {
-  const long long total = per * rows;
-  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
-       i += (long long)gridDim.x * blockDim.x) {
-    if (scal[row0 + (int)(i / per)].active) dst[i] = src[i];
-  }
-}
-void copy_rows_active(int n, int rows, int row0, const CgScal* scal, const double* src,
-                      double* dst, hipStream_t s) {
-  if (rows <= 0) return;
-  const long long per = lay_row(n);
-  hipLaunchKernelGGL(k_copy_rows_active, dim3(grid_for(per * rows, 256)), dim3(256), 0, s, per,
-                     rows, row0, scal, src, dst);
 }
 
 // ---------------------------------------------------------------------------

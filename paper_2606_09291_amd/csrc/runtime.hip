@@ -1209,26 +1209,25 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
                   c->d_count, s);
       }
     }
-    // true residual b0 - A x into q, its norm; restart the problems that
-    // drifted.  After a restart only the restarted problems are checked again:
-    // the others were not touched, and their partial slots still hold the last
-    // check's sums
+    // the norm of the true residual b0 - A x (not stored); restart the
+    // problems that drifted.  After a restart only the restarted problems are
+    // checked again: the others were not touched, and their partial slots
+    // still hold the last check's sums
     flush_steps(c, P);
     if (restart > 0)
       cg_scalar(PH_RECHECK, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, nullptr, rtol, maxit,
                 nullptr, s);
-    for (auto& gr : P->groups) {
-      GridArgs g = args_group(c, P, gr, restart > 0);
-      march_resid<double>(g, gr.x, gr.b0, gr.q, s);
-      group_dot(g, gr.q, gr.q, P->d_poff, P->d_partial, s);
-    }
+    for (auto& gr : P->groups)
+      march_resid_norm(args_group(c, P, gr, restart > 0), gr.x, gr.b0, P->d_poff, P->d_partial,
+                       s);
     cg_scalar(PH_TRUE, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
               c->d_count, s);
     HIPCHK(hipGetLastError());
     if (read_count(c) == 0) break;
+    // the restarted problems start again from r = b - A x
     for (auto& gr : P->groups)
-      copy_rows_active(gr.n, gr.count, gr.p0, P->d_scal, gr.q, rows_of(P->sizes[gr.sl].B, gr),
-                       s);
+      march_resid<double>(args_group(c, P, gr, true), gr.x, gr.b0,
+                          rows_of(P->sizes[gr.sl].B, gr), s);
   }
   scal_to_stats(P->d_scal, P->nprob, rtol, &c->d_stat->iters, &c->d_stat->nonconv,
                 &c->d_stat->relres, s);
@@ -1292,11 +1291,8 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
   auto true_residual = [&](bool recheck) {
     flush_steps(c, P);
     if (recheck) cg(PH_RECHECK, nullptr);
-    for (auto& gr : P->groups) {
-      GridArgs g = args_group(c, P, gr, recheck);
-      march_resid<double>(g, gr.x, gr.b0, gr.q, s);
-      group_dot(g, gr.q, gr.q, P->d_poff, P->d_partial, s);
-    }
+    for (auto& gr : P->groups)
+      march_resid_norm(args_group(c, P, gr, recheck), gr.x, gr.b0, P->d_poff, P->d_partial, s);
     cg(PH_TRUE, P->d_partial);
   };
   for (auto& gr : P->groups) {
@@ -1311,7 +1307,8 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
   true_residual(false);
   // restart block: the problems that missed rtol start again from b - A x
   for (auto& gr : P->groups)
-    copy_rows_active(gr.n, gr.count, gr.p0, P->d_scal, gr.q, rows_of(P->sizes[gr.sl].B, gr), s);
+    march_resid<double>(args_group(c, P, gr, true), gr.x, gr.b0, rows_of(P->sizes[gr.sl].B, gr),
+                        s);
   start();
   iterate(kRestartIters);
   true_residual(true);
