@@ -201,6 +201,8 @@ void cos_table(int n, int K, double* out, hipStream_t s);
 void rows_broadcast(int n, int rows, const double* src, double* dst, hipStream_t s);
 // solver rows copied (copy_rows) or converted to dense rows (unpack_rows)
 void copy_rows(int n, int rows, const double* src, double* dst, hipStream_t s);
+// partial slots of problem p0 (pc of them) copied to problems p0+1 .. p0+count-1
+void replicate_slots(int p0, int count, int pc, const int* poff, double* partial, hipStream_t s);
 void unpack_rows(int n, int rows, const double* src, double* dst, hipStream_t s);
 void rows_zero(long long count, double* x, hipStream_t s);
 void to_f32(long long count, const double* x, float* y, hipStream_t s);

@@ -3249,6 +3249,21 @@ void copy_elems(long long count, const double* src, double* dst, hipStream_t s) 
 void copy_rows(int n, int rows, const double* src, double* dst, hipStream_t s) {
   copy_elems(lay_row(n) * rows, src, dst, s);
 }
+__global__ void k_replicate_slots(int p0, int count, int pc, const int* __restrict__ poff,
+                                  double* __restrict__ partial) {
+  const long long total = (long long)(count - 1) * pc;
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+       i += (long long)gridDim.x * blockDim.x) {
+    const int p = p0 + 1 + (int)(i / pc), t = (int)(i % pc);
+    partial[poff[p] + t] = partial[poff[p0] + t];
+  }
+}
+void replicate_slots(int p0, int count, int pc, const int* poff, double* partial, hipStream_t s) {
+  if (count <= 1 || pc <= 0) return;
+  const long long total = (long long)(count - 1) * pc;
+  hipLaunchKernelGGL(k_replicate_slots, dim3(grid_for(total, 256)), dim3(256), 0, s, p0, count,
+                     pc, poff, partial);
+}
 
 // ---------------------------------------------------------------------------
 // Entropic epilogue (Sec. 2.2 estimator, Sec. 4.1 power sums).

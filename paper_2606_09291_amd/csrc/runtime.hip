@@ -1155,15 +1155,18 @@ void flush_steps(mlsgd_ctx* c, Plan* P) {
 
 // Batched (preconditioned) CG on every problem of the plan.  On entry the
 // B rows of each top grid hold the right-hand side b, b0 a copy of it, x = 0.
-void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* relres_out) {
+void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* relres_out,
+            bool bb_ready = false) {
   hipStream_t s = c->stream;
   const bool mg = c->pb.solver == MLSGD_SOLVER_MGPCG;
   const double rtol = c->pb.rtol;
   const int maxit = c->pb.max_iters;
-  for (auto& gr : P->groups) {
-    GridArgs g = args_group(c, P, gr, false);
-    double* r = rows_of(P->sizes[gr.sl].B, gr);
-    group_dot(g, r, r, P->d_poff, P->d_partial, s);
+  if (!bb_ready) {
+    for (auto& gr : P->groups) {
+      GridArgs g = args_group(c, P, gr, false);
+      double* r = rows_of(P->sizes[gr.sl].B, gr);
+      group_dot(g, r, r, P->d_poff, P->d_partial, s);
+    }
   }
   cg_scalar(PH_INIT_BB, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
             c->d_count, s);
@@ -1248,7 +1251,7 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
 // iterations beyond their convergence only launch early-exiting kernels.
 constexpr int kRestartIters = 2;
 
-void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
+void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot, bool bb_ready = false) {
   hipStream_t s = c->stream;
   const bool mg = c->pb.solver == MLSGD_SOLVER_MGPCG;
   const double rtol = c->pb.rtol;
@@ -1295,10 +1298,12 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot) {
       march_resid_norm(args_group(c, P, gr, recheck), gr.x, gr.b0, P->d_poff, P->d_partial, s);
     cg(PH_TRUE, P->d_partial);
   };
-  for (auto& gr : P->groups) {
-    GridArgs g = args_group(c, P, gr, false);
-    double* r = rows_of(P->sizes[gr.sl].B, gr);
-    group_dot(g, r, r, P->d_poff, P->d_partial, s);
+  if (!bb_ready) {
+    for (auto& gr : P->groups) {
+      GridArgs g = args_group(c, P, gr, false);
+      double* r = rows_of(P->sizes[gr.sl].B, gr);
+      group_dot(g, r, r, P->d_poff, P->d_partial, s);
+    }
   }
   cg(PH_INIT_BB, P->d_partial);
   fmg(c, P);
@@ -1334,19 +1339,26 @@ void level_rhs(mlsgd_ctx* c, const double* u) {
 void state_phase(mlsgd_ctx* c, Plan* P, int* it, int* nc, double* rr, double* y_out,
                  int fixed = 0) {
   hipStream_t s = c->stream;
-  // x starts at 0 (the full-multigrid start writes every x row itself)
+  // x starts at 0 (the full-multigrid start writes every x row itself).
+  // Every problem of a group has the same right-hand side, so |b|^2 is
+  // summed over the group's first row and its partial slots copied to the
+  // others.
   const bool clear = !fmg_applies(c, P);
   for (auto& gr : P->groups) {
     double* b = rows_of(P->sizes[gr.sl].B, gr);
     rows_broadcast(gr.n, gr.count, c->rhs_lvl[gr.n], b, s);
     rows_broadcast(gr.n, gr.count, c->rhs_lvl[gr.n], gr.b0, s);
     if (clear) rows_zero((long long)gr.count * srow(gr.n), gr.x, s);
+    GridArgs g1 = args_group(c, P, gr, false);
+    g1.rows = 1;
+    group_dot(g1, b, b, P->d_poff, P->d_partial, s);
+    replicate_slots(gr.p0, gr.count, P->h_pcnt[gr.p0], P->d_poff, P->d_partial, s);
   }
   HIPCHK(hipGetLastError());
   if (fixed > 0)
-    krylov_fixed(c, P, fixed, 0);
+    krylov_fixed(c, P, fixed, 0, true);
   else
-    krylov(c, P, it, nc, rr);
+    krylov(c, P, it, nc, rr, true);
   for (auto& gr : P->groups) {
     if (y_out) unpack_rows(gr.n, gr.count, gr.x, y_out, s);
     GridArgs g = args_group(c, P, gr, false);
@@ -1493,11 +1505,11 @@ void estimate_enqueue(mlsgd_ctx* c, const EstPrep& e, int L, const int64_t* M, c
   };
   state_phase(c, P, it_s, nc_s, rr_s, nullptr, fixed_s);
   add_work();
-  if (grad_out) {
+  if (grad_out) {   // the misfit pass left |y - y_d|^2 in the partial slots
     if (fixed_a > 0)
-      krylov_fixed(c, P, fixed_a, 1);
+      krylov_fixed(c, P, fixed_a, 1, true);
     else
-      krylov(c, P, it_a, nc_a, rr_a);
+      krylov(c, P, it_a, nc_a, rr_a, true);
     add_work();
   }
   if (fixed_s <= 0) HIPCHK(hipEventRecord(c->ev[1], s));
@@ -1822,8 +1834,8 @@ int solve_block(mlsgd_ctx* c, Plan* P, int n, int64_t count, double* y_out, doub
   if (phi_out)
     HIPCHK(hipMemcpyAsync(phi_out, P->d_phi, sizeof(double) * count, hipMemcpyDeviceToDevice,
                           c->stream));
-  if (p_out) {
-    krylov(c, P, &it2, &nc2, &r2);
+  if (p_out) {   // the misfit pass left |y - y_d|^2 in the partial slots
+    krylov(c, P, &it2, &nc2, &r2, true);
     unpack_rows(n, (int)count, P->groups[0].x, p_out, c->stream);
   }
   HIPCHK(hipGetLastError());
