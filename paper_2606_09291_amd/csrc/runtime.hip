@@ -1130,7 +1130,7 @@ void krylov_step(mlsgd_ctx* c, Plan* P, bool mg, int it) {
     pslot = gr.pcur ^ 1;
   }
   cg_scalar(PH_ALPHA, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
-            c->d_count, s, pslot);
+            nullptr, s, pslot);
   for (auto& gr : P->groups) {
     GridArgs g = args_group(c, P, gr, true);
     float* r32 = (mg && c->mixed) ? P->sizes[gr.sl].Bf + (size_t)gr.p0 * srow(gr.n) : nullptr;
@@ -1169,7 +1169,7 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
     }
   }
   cg_scalar(PH_INIT_BB, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
-            c->d_count, s);
+            nullptr, s);
   fmg(c, P);
   // after a full-multigrid start r0 carries the evaluation error of b - A x0
   // (near the FP64 residual floor, about 0.3 rtol on 129^3 grids), which the
@@ -1188,10 +1188,10 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
     if (mg) {
       precondition(c, P);
       cg_scalar(PH_RZ0, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
-                c->d_count, s);
+                nullptr, s);
     } else {
       cg_scalar(PH_RZ0_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, nullptr, rtol, maxit,
-                c->d_count, s);
+                nullptr, s);
     }
     // the first quiet iterations run without a host read of the active
     // count: a problem that converged there is inactive and skipped, so at
@@ -1199,17 +1199,18 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
     const int quiet = restart == 0 ? c->kry_quiet : 0;
     for (int it = 0; it < maxit; ++it) {
       krylov_step(c, P, mg, it);
+      const bool read = it + 1 > quiet;
       cg_scalar(PH_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol_rr, maxit,
-                c->d_count, s);
+                read ? c->d_count : nullptr, s);
       HIPCHK(hipGetLastError());
-      if (it + 1 > quiet && read_count(c) == 0) break;
+      if (read && read_count(c) == 0) break;
       if (mg) {
         precondition(c, P);
         cg_scalar(PH_RZ, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
-                  c->d_count, s);
+                  nullptr, s);
       } else {
         cg_scalar(PH_RZ_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, nullptr, rtol, maxit,
-                  c->d_count, s);
+                  nullptr, s);
       }
     }
     // the norm of the true residual b0 - A x (not stored); restart the
@@ -1256,9 +1257,9 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot, bool bb_ready = fa
   const bool mg = c->pb.solver == MLSGD_SOLVER_MGPCG;
   const double rtol = c->pb.rtol;
   const int maxit = c->pb.max_iters;
+  // the host reads no count here (the stats kernel reports the outcome)
   auto cg = [&](int phase, const double* partial) {
-    cg_scalar(phase, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, partial, rtol, maxit, c->d_count,
-              s);
+    cg_scalar(phase, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, partial, rtol, maxit, nullptr, s);
   };
   auto start = [&]() {  // z = M r and rz for the active problems
     if (mg && c->mixed) {
@@ -1279,7 +1280,7 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot, bool bb_ready = fa
     for (int it = 0; it < count; ++it) {
       krylov_step(c, P, mg, it);
       cg_scalar(PH_RR, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial,
-                fmg_applies(c, P) ? c->fmg_margin * rtol : rtol, maxit, c->d_count, s);
+                fmg_applies(c, P) ? c->fmg_margin * rtol : rtol, maxit, nullptr, s);
       if (mg) {
         precondition(c, P);
         cg(PH_RZ, P->d_partial);
