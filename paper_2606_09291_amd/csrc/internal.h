@@ -233,6 +233,7 @@ enum ScalPhase {
   PH_RZ_RR = 6,      // unpreconditioned: rz_new = rr
   PH_TRUE = 7,       // rr = sum (true residual); active = restart = rr > rtol^2 bb; nothing pending
   PH_RECHECK = 8,    // active = restart: the problems the last check restarted (no sum)
+  PH_FORCE_RESTART = 9,  // test hook: every even-numbered problem with b != 0 restarts
 };
 void cg_scalar(int phase, CgScal* scal, int nprob, const int* poff, const int* pcnt,
                const double* partial, double rtol, int max_iters, int* active_count,

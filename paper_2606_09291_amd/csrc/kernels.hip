@@ -2974,6 +2974,12 @@ __global__ void __launch_bounds__(256)
       case PH_RECHECK:
         sc.active = sc.restart;
         break;
+      case PH_FORCE_RESTART:
+        if ((p & 1) == 0 && sc.bb > 0.0) {
+          sc.active = 1;
+          sc.restart = 1;
+        }
+        break;
     }
     scal[p] = sc;
     cnt += sc.active;

@@ -204,6 +204,10 @@ struct mlsgd_ctx {
   // Krylov iterations whose active count the host does not read (no solve
   // of the previous call finished before them); results do not depend on it
   int kry_quiet = 0;
+  // test hook: after a solve's first true-residual check, restart every
+  // even-numbered problem as well (exercises the restart path on converged
+  // problems, whose result then moves by at most the solver tolerance)
+  bool force_restart = false;
   // event timing of the smoothing passes on one grid size (roofline figures)
   struct Timing {
     bool on = false;
@@ -1224,8 +1228,12 @@ void krylov(mlsgd_ctx* c, Plan* P, int* iters_out, int* nonconv_out, double* rel
     for (auto& gr : P->groups)
       march_resid_norm(args_group(c, P, gr, restart > 0), gr.x, gr.b0, P->d_poff, P->d_partial,
                        s);
+    const bool force = c->force_restart && restart == 0;
     cg_scalar(PH_TRUE, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, P->d_partial, rtol, maxit,
-              c->d_count, s);
+              force ? nullptr : c->d_count, s);
+    if (force)
+      cg_scalar(PH_FORCE_RESTART, P->d_scal, P->nprob, P->d_poff, P->d_pcnt, nullptr, rtol, maxit,
+                c->d_count, s);
     HIPCHK(hipGetLastError());
     if (read_count(c) == 0) break;
     // the restarted problems start again from r = b - A x
@@ -1311,6 +1319,7 @@ void krylov_fixed(mlsgd_ctx* c, Plan* P, int iters, int slot, bool bb_ready = fa
   start();
   iterate(iters);
   true_residual(false);
+  if (c->force_restart) cg(PH_FORCE_RESTART, nullptr);
   // restart block: the problems that missed rtol start again from b - A x
   for (auto& gr : P->groups)
     march_resid<double>(args_group(c, P, gr, true), gr.x, gr.b0, rows_of(P->sizes[gr.sl].B, gr),
@@ -1923,6 +1932,7 @@ int mlsgd_create(mlsgd_ctx** out, const mlsgd_problem* pb, void* stream) {
     if (const char* e = getenv("MLSGD_XDEFER")) c->xdefer = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_FMG")) c->fmg = atoi(e) != 0;
     if (const char* e = getenv("MLSGD_FMG_MARGIN")) c->fmg_margin = atof(e);
+    if (const char* e = getenv("MLSGD_FORCE_RESTART")) c->force_restart = atoi(e) != 0;
     if (!(c->fmg_margin > 0.0 && c->fmg_margin <= 1.0)) c->fmg_margin = 0.7;
     c->nfin = pb->grid_n[pb->n_levels - 1];
     const size_t NF = cube(c->nfin);
