@@ -71,3 +71,26 @@ def test_forced_restarts_keep_the_estimate(mm, orc, monkeypatch, precision, grap
     pb = orc.make_problem(GRID, rtol=1e-13, **KW)
     go, _ = orc.mlmc_gradient(pb, None, u.cpu().numpy(), yd, M, first=[0] * len(M))
     assert _rel(out["1"][-1][0], go) <= (1e-9 if precision == "fp64" else 1e-8)
+
+
+def test_quiet_iterations_leave_results_unchanged(mm):
+    """After its first solve a context runs the first iterations of later
+    solves without reading the active count from the host.  Problems that
+    converge there are skipped as always, so the estimate of the same draws
+    is bit-identical to a fresh context's, and so are the iteration counts."""
+    import torch
+    print("quiet iterations", flush=True)
+    yd = inputs.target_sin(33)
+    u = torch.as_tensor(inputs.control_xyz(33) + 10.0 * yd, device="cuda:0")
+    mk = lambda: mm.Context(mm.Problem(grid_n=GRID, y_d=yd, rtol=1e-12, **KW), use_tuned=False)
+    warm = mk()
+    warm.mlmc_gradient(u, M, first=[5] * len(M))     # learns the iteration count
+    g_w, st_w = warm.mlmc_gradient(u, M, first=[0] * len(M))
+    warm.close()
+    fresh = mk()
+    g_f, st_f = fresh.mlmc_gradient(u, M, first=[0] * len(M))
+    fresh.close()
+    assert np.array_equal(g_w.cpu().numpy(), g_f.cpu().numpy())
+    assert st_w["iters_state"] == st_f["iters_state"]
+    assert st_w["iters_adjoint"] == st_f["iters_adjoint"]
+    assert st_w["J"] == st_f["J"]
