@@ -334,9 +334,35 @@ def run_rates(args):
     print(json.dumps(out))
 
 
+def mlsgd_run(args, m, w, dev, theta, steps):
+    """Adaptive MLSGD (Algorithm 1) on workload w at theta: projected steps
+    with step size 1/(1+j), batch sizes chosen by the controller after every
+    step.  Returns the wall time and the per-step records."""
+    import dataclasses
+    import torch
+    wt = dataclasses.replace(w, theta=theta)
+    ctx = make_ctx(m, wt, dev)
+    u = torch.as_tensor(wt.u0(), device=dev).contiguous()
+    ctx.set_batch(wt.M)
+    recs = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for j in range(steps):
+        st = ctx.step(u, 1.0 / (1.0 + j), adapt=True)
+        g = st["grad"]
+        recs.append({"step": j, "J": g["J"], "grad_norm": g["grad_norm"], "M": st["M_next"],
+                     "err_sam": st["err_sam"], "err_num": st["err_num"], "eps": st["eps"],
+                     "iters": [g["iters_state"], g["iters_adjoint"]], "ms": g["ms_total"]})
+        log(args, f"theta {theta} step {j}: J {g['J']:.6e} |g| {g['grad_norm']:.4e} "
+                  f"M_next {st['M_next']} {g['ms_total']:.1f} ms")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ctx.close()
+    return dt, recs
+
+
 def run_mlsgd(args):
-    """Adaptive MLSGD (Algorithm 1): projected steps with step size 1/(1+j),
-    batch sizes chosen by the controller after every step."""
+    """Adaptive MLSGD for every theta of --thetas, with every step's record."""
     import torch
     import paper_2606_09291_amd as m
     from paper_2606_09291_amd import inputs
@@ -344,29 +370,26 @@ def run_mlsgd(args):
     dev = torch.device("cuda:0")
     out = {"workload": w.name, "runs": []}
     for th in [float(x) for x in args.thetas.split(",")]:
-        import dataclasses
-        wt = dataclasses.replace(w, theta=th)
-        ctx = make_ctx(m, wt, dev)
-        u = torch.as_tensor(wt.u0(), device=dev).contiguous()
-        ctx.set_batch(wt.M)
-        recs = []
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for j in range(args.mlsgd_steps):
-            st = ctx.step(u, 1.0 / (1.0 + j), adapt=True)
-            g = st["grad"]
-            recs.append({"step": j, "J": g["J"], "grad_norm": g["grad_norm"], "M": st["M_next"],
-                         "err_sam": st["err_sam"], "err_num": st["err_num"], "eps": st["eps"],
-                         "iters": [g["iters_state"], g["iters_adjoint"]], "ms": g["ms_total"]})
-            log(args, f"theta {th} step {j}: J {g['J']:.6e} |g| {g['grad_norm']:.4e} "
-                      f"M_next {st['M_next']} {g['ms_total']:.1f} ms")
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        ctx.close()
+        dt, recs = mlsgd_run(args, m, w, dev, th, args.mlsgd_steps)
         out["runs"].append({"theta": th, "seconds": dt, "steps": args.mlsgd_steps,
                             "final_J": recs[-1]["J"], "final_grad_norm": recs[-1]["grad_norm"],
                             "records": recs})
     print(json.dumps(out), flush=True)
+
+
+def adaptive_leg(args, m, dev):
+    """The adaptive MLSGD run at theta = 1 in the default bench line: its
+    50 steps' wall time and outcome (the controller's batches per step are
+    in bench.py --mlsgd)."""
+    from paper_2606_09291_amd import inputs
+    w = inputs.WORKLOADS["adaptive_257"]
+    dt, recs = mlsgd_run(args, m, w, dev, 1.0, w.steps)
+    return {"workload": w.name + ", theta=1, mixed, rtol 1e-10", "steps": w.steps,
+            "seconds": dt, "steps_per_s": w.steps / dt,
+            "ms_per_step_after_first": sum(r["ms"] for r in recs[1:]) / max(1, len(recs) - 1),
+            "J_first": recs[0]["J"], "J_final": recs[-1]["J"],
+            "grad_norm_first": recs[0]["grad_norm"], "grad_norm_final": recs[-1]["grad_norm"],
+            "M_final": recs[-1]["M"], "iters_final": recs[-1]["iters"]}
 
 
 def level_rates(w, stats):
@@ -673,6 +696,8 @@ def main():
         vg = k257 / g257["dt"]
         out["batched_257"]["graph"] = {
             "value": vg, "ms_per_step": 1e3 / vg, "solves_per_s": s257 * vg}
+        log(args, "adaptive MLSGD, 9^3..257^3, 50 steps")
+        out["adaptive_257"] = adaptive_leg(args, m, dev)
         log(args, "odd-size solve batch")
         out["odd_size_solves"] = odd_size_solves(m, dev)
         wp = inputs.WORKLOADS["paper_law_65"]
