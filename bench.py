@@ -377,6 +377,36 @@ def run_mlsgd(args):
     print(json.dumps(out), flush=True)
 
 
+def autograd_leg(m, dev, reps=3):
+    """The autograd objective J(u) at 65^3 with 256 samples (single level,
+    FP64, rtol 1e-12) and its backward pass, timed separately after one
+    warm-up pass."""
+    import torch
+    from paper_2606_09291_amd import inputs
+    from paper_2606_09291_amd.autograd import objective
+    yd = inputs.target_sin(65)
+    ctx = m.Context(m.Problem(grid_n=[65], y_d=yd, theta=1.0, alpha=1e-3, rtol=1e-12))
+    u0 = torch.as_tensor(inputs.control_xyz(65), device=dev).contiguous()
+    fwd = bwd = 0.0
+    for r in range(reps + 1):
+        u = u0.clone().requires_grad_(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        J = objective(u, ctx, [256], [256 * r])
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        J.backward()
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        if r > 0:
+            fwd += t1 - t0
+            bwd += t2 - t1
+    ctx.close()
+    return {"workload": "autograd J(u) and dJ/du, 65^3, 256 samples, FP64 MG-PCG, rtol 1e-12",
+            "forward_ms": 1e3 * fwd / reps, "backward_ms": 1e3 * bwd / reps,
+            "value": reps / (fwd + bwd), "unit": "forward+backward passes/s"}
+
+
 def adaptive_leg(args, m, dev):
     """The adaptive MLSGD run at theta = 1 in the default bench line: its
     50 steps' wall time and outcome (the controller's batches per step are
@@ -698,6 +728,8 @@ def main():
             "value": vg, "ms_per_step": 1e3 / vg, "solves_per_s": s257 * vg}
         log(args, "adaptive MLSGD, 9^3..257^3, 50 steps")
         out["adaptive_257"] = adaptive_leg(args, m, dev)
+        log(args, "autograd objective, 65^3, 256 samples")
+        out["autograd_65"] = autograd_leg(m, dev)
         log(args, "odd-size solve batch")
         out["odd_size_solves"] = odd_size_solves(m, dev)
         wp = inputs.WORKLOADS["paper_law_65"]
